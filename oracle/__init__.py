@@ -1,0 +1,201 @@
+"""CPU oracle for the batched homotopy path tracker -- TEST INFRASTRUCTURE.
+
+Plain, slow, fp64 C implementation (``oracle.c``) of the tracker reading the
+project follows, wrapped with ctypes.  Only ``tests/``, the smoke check and
+the benchmark's CPU-baseline leg import this package.  It shares no code with
+the HIP library and never imports it; inputs come from ``workloads``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+CONVERGED, DIVERGED, FAILED_MINSTEP, FAILED_MAXSTEPS, FAILED_NEWTON_T1 = range(5)
+
+
+def build() -> str:
+    """Compile oracle.c into liboracle.so (gcc, no FMA contraction)."""
+    tmp = _SO + ".tmp"
+    cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fPIC", "-shared", "-pthread",
+           os.path.join(_HERE, "oracle.c"), "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+class RefSystem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_terms", ctypes.c_int32),
+                ("eq_ptr", ctypes.c_void_p), ("coeff", ctypes.c_void_p),
+                ("exps", ctypes.c_void_p)]
+
+
+class RefTolerances(ctypes.Structure):
+    _fields_ = [("tol_residual", ctypes.c_double), ("tol_corr", ctypes.c_double),
+                ("tol_final", ctypes.c_double), ("div_radius", ctypes.c_double),
+                ("h_init", ctypes.c_double), ("h_min", ctypes.c_double),
+                ("h_max", ctypes.c_double), ("max_steps", ctypes.c_int32),
+                ("max_newton", ctypes.c_int32), ("max_newton_final", ctypes.c_int32)]
+
+
+STATS_DTYPE = np.dtype([("steps", np.int32), ("rejections", np.int32),
+                        ("newton_iters", np.int32), ("evals", np.int32),
+                        ("solves", np.int32), ("pad", np.int32),
+                        ("t_final", np.float64), ("residual", np.float64)])
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_SO):
+                build()
+            L = ctypes.CDLL(_SO)
+            vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+            L.ref_default_tolerances.argtypes = [ctypes.POINTER(RefTolerances)]
+            L.ref_eval_system.argtypes = [ctypes.POINTER(RefSystem), vp, vp, vp]
+            L.ref_lu_solve.argtypes = [ctypes.c_int, vp, vp, vp]
+            L.ref_lu_solve.restype = ctypes.c_int
+            L.ref_start_point.argtypes = [ctypes.c_int, vp, i64, vp]
+            L.ref_rk4_predict.argtypes = [ctypes.POINTER(RefSystem), ctypes.POINTER(RefSystem),
+                                          vp, vp, ctypes.c_double, ctypes.c_double, vp]
+            L.ref_rk4_predict.restype = ctypes.c_int
+            L.ref_track_paths.argtypes = [ctypes.POINTER(RefSystem), ctypes.POINTER(RefSystem),
+                                          vp, vp, vp, i64, ctypes.POINTER(RefTolerances),
+                                          vp, vp, vp, i32]
+            L.ref_track_paths.restype = ctypes.c_int
+            L.ref_find_duplicates.argtypes = [ctypes.c_int, i64, vp, vp, ctypes.c_double, vp, i64]
+            L.ref_find_duplicates.restype = i64
+            _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+class _Sys:
+    """Keeps the numpy buffers of a RefSystem alive."""
+
+    def __init__(self, s):
+        self.eq_ptr = np.ascontiguousarray(s.eq_ptr, dtype=np.int32)
+        self.coeff = np.ascontiguousarray(s.coeff, dtype=np.complex128)
+        self.exps = np.ascontiguousarray(s.exps, dtype=np.uint8)
+        self.st = RefSystem(int(s.n), int(self.coeff.shape[0]), _ptr(self.eq_ptr).value,
+                            _ptr(self.coeff).value, _ptr(self.exps).value)
+
+
+def default_tolerances(**over) -> RefTolerances:
+    t = RefTolerances()
+    lib().ref_default_tolerances(ctypes.byref(t))
+    for k, v in over.items():
+        setattr(t, k, v)
+    return t
+
+
+def eval_system(s, x):
+    """(f(x), J_f(x)) for one point x (complex[n])."""
+    S = _Sys(s)
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    fx = np.zeros(s.n, np.complex128)
+    jac = np.zeros((s.n, s.n), np.complex128)
+    lib().ref_eval_system(ctypes.byref(S.st), _ptr(x), _ptr(fx), _ptr(jac))
+    return fx, jac
+
+
+def lu_solve(A, b):
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    b = np.ascontiguousarray(b, dtype=np.complex128)
+    y = np.zeros_like(b)
+    rc = lib().ref_lu_solve(int(A.shape[0]), _ptr(A), _ptr(b), _ptr(y))
+    if rc != 0:
+        raise ZeroDivisionError("zero pivot")
+    return y
+
+
+def start_point(degrees, path_id):
+    d = np.ascontiguousarray(degrees, dtype=np.int32)
+    x = np.zeros(d.shape[0], np.complex128)
+    lib().ref_start_point(int(d.shape[0]), _ptr(d), int(path_id), _ptr(x))
+    return x
+
+
+def rk4_predict(f, gamma, x, t, h):
+    """One RK4 predictor step of the total-degree homotopy from (x, t)."""
+    F = _Sys(f)
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    gam = np.asarray([complex(gamma).real, complex(gamma).imag], np.float64)
+    out = np.zeros_like(x)
+    rc = lib().ref_rk4_predict(ctypes.byref(F.st), None, _ptr(gam), _ptr(x), float(t), float(h),
+                               _ptr(out))
+    if rc != 0:
+        raise ArithmeticError("predictor failed")
+    return out
+
+
+def track_paths(f, gamma, path_ids=None, n_paths=None, start=None, g=None,
+                tol: RefTolerances | None = None, n_threads: int = 1):
+    """Tracks total-degree paths (or paths from given start points of g).
+    Returns (endpoints complex[P, n], status int32[P], stats STATS_DTYPE[P])."""
+    F = _Sys(f)
+    G = _Sys(g) if g is not None else None
+    if path_ids is not None:
+        path_ids = np.ascontiguousarray(path_ids, dtype=np.int64)
+        P = int(path_ids.shape[0])
+    elif start is not None:
+        start = np.ascontiguousarray(start, dtype=np.complex128)
+        P = int(start.shape[0])
+    else:
+        P = int(n_paths if n_paths is not None else f.bezout())
+    if start is not None:
+        start = np.ascontiguousarray(start, dtype=np.complex128)
+    gam = np.asarray([complex(gamma).real, complex(gamma).imag], np.float64)
+    ends = np.zeros((P, f.n), np.complex128)
+    status = np.full(P, -1, np.int32)
+    stats = np.zeros(P, STATS_DTYPE)
+    tol = tol or default_tolerances()
+    rc = lib().ref_track_paths(ctypes.byref(F.st), ctypes.byref(G.st) if G else None,
+                               _ptr(gam), _ptr(start), _ptr(path_ids), P, ctypes.byref(tol),
+                               _ptr(ends), _ptr(status), _ptr(stats), int(n_threads))
+    if rc != 0:
+        raise ValueError(f"ref_track_paths failed ({rc})")
+    return ends, status, stats
+
+
+def find_duplicates(endpoints, status, rel=1e-6, max_pairs=1 << 16):
+    e = np.ascontiguousarray(endpoints, dtype=np.complex128)
+    s = np.ascontiguousarray(status, dtype=np.int32)
+    pairs = np.zeros((max_pairs, 2), np.int64)
+    cnt = lib().ref_find_duplicates(int(e.shape[1]), int(e.shape[0]), _ptr(e), _ptr(s),
+                                    float(rel), _ptr(pairs), int(max_pairs))
+    return pairs[: min(cnt, max_pairs)].copy()
+
+
+def solve(f, gamma, n_threads=1, path_ids=None, tol=None, retrack=True):
+    """Tracks every total-degree path (or the given ids), then the post-pass:
+    converged endpoints that coincide within 1e-6 relative are path jumps;
+    both paths of each pair are tracked once more with h_max = 0.01 and
+    tol_corr = 1e-10.  Returns (endpoints, status, stats, remaining pairs)."""
+    tol = tol or default_tolerances()
+    ends, status, stats = track_paths(f, gamma, path_ids=path_ids,
+                                      n_paths=None if path_ids is not None else f.bezout(),
+                                      tol=tol, n_threads=n_threads)
+    pairs = find_duplicates(ends, status)
+    if retrack and len(pairs):
+        idx = np.unique(pairs.ravel())
+        ids = path_ids[idx] if path_ids is not None else idx.astype(np.int64)
+        t2 = default_tolerances(**{f: getattr(tol, f) for f, _ in RefTolerances._fields_})
+        t2.h_max = 0.01
+        t2.tol_corr = 1e-10
+        e2, s2, st2 = track_paths(f, gamma, path_ids=ids, tol=t2, n_threads=n_threads)
+        ends[idx], status[idx], stats[idx] = e2, s2, st2
+        pairs = find_duplicates(ends, status)
+    return ends, status, stats, pairs

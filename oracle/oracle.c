@@ -1,0 +1,470 @@
+/*
+ * CPU oracle for the batched homotopy path tracker -- TEST INFRASTRUCTURE.
+ * Only tests, the smoke check and the benchmark's CPU-baseline leg use it;
+ * see oracle.h for the contract and the reading of the method it follows.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared -pthread oracle.c -lm
+ */
+#include "oracle.h"
+
+#include <complex.h>
+#include <math.h>
+#include <pthread.h>
+#include <stdatomic.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+#define MAXN 16
+
+void ref_default_tolerances(ref_tolerances *tol) {
+  tol->tol_residual = 1e-10;
+  tol->tol_corr = 1e-8;
+  tol->tol_final = 1e-13;
+  tol->div_radius = 1e8;
+  tol->h_init = 0.01;
+  tol->h_min = 1e-13;
+  tol->h_max = 0.1;
+  tol->max_steps = 10000;
+  tol->max_newton = 3;
+  tol->max_newton_final = 6;
+}
+
+static cplx load(const double *p, int i) { return CMPLX(p[2 * i], p[2 * i + 1]); }
+static void store(double *p, int i, cplx z) { p[2 * i] = creal(z); p[2 * i + 1] = cimag(z); }
+
+/* Smith's complex division a / b (Smith 1962). */
+static cplx smith_div(cplx a, cplx b) {
+  double ar = creal(a), ai = cimag(a), br = creal(b), bi = cimag(b);
+  if (fabs(br) >= fabs(bi)) {
+    double r = bi / br, den = br + bi * r;
+    return CMPLX((ar + ai * r) / den, (ai - ar * r) / den);
+  } else {
+    double r = br / bi, den = br * r + bi;
+    return CMPLX((ar * r + ai) / den, (ai * r - ar) / den);
+  }
+}
+
+static double cabs1(cplx z) { return fabs(creal(z)) + fabs(cimag(z)); }
+
+/* ||v||_inf with the complex modulus |z| = hypot(re, im). */
+static double norm_inf(int n, const cplx *v) {
+  double m = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double a = cabs(v[i]);
+    if (!(a <= m)) m = a; /* also propagates NaN */
+  }
+  return m;
+}
+
+static int all_finite(int n, const cplx *v) {
+  for (int i = 0; i < n; ++i)
+    if (!isfinite(creal(v[i])) || !isfinite(cimag(v[i]))) return 0;
+  return 1;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Evaluation: f(x) and J_f(x) term by term, every monomial and every     */
+/* partial derivative by repeated multiplication.                          */
+/* ---------------------------------------------------------------------- */
+
+static void eval_f(const ref_system *s, const cplx *x, cplx *fx, cplx *jac) {
+  const int n = s->n;
+  for (int i = 0; i < n; ++i) {
+    if (fx) fx[i] = 0.0;
+    if (jac)
+      for (int j = 0; j < n; ++j) jac[i * n + j] = 0.0;
+    for (int t = s->eq_ptr[i]; t < s->eq_ptr[i + 1]; ++t) {
+      const uint8_t *a = s->exps + (size_t)t * n;
+      cplx c = load(s->coeff, t);
+      if (fx) {
+        cplx v = c;
+        for (int l = 0; l < n; ++l)
+          for (int e = 0; e < a[l]; ++e) v = v * x[l];
+        fx[i] += v;
+      }
+      if (jac) {
+        /* d/dx_j (c x^a) = a_j c x^(a - e_j) */
+        for (int j = 0; j < n; ++j) {
+          if (a[j] == 0) continue;
+          cplx v = c * (double)a[j];
+          for (int l = 0; l < n; ++l) {
+            int el = a[l] - (l == j ? 1 : 0);
+            for (int e = 0; e < el; ++e) v = v * x[l];
+          }
+          jac[i * n + j] += v;
+        }
+      }
+    }
+  }
+}
+
+void ref_eval_system(const ref_system *s, const double *x, double *fx, double *jac) {
+  const int n = s->n;
+  cplx xv[MAXN], fv[MAXN], jv[MAXN * MAXN];
+  for (int i = 0; i < n; ++i) xv[i] = load(x, i);
+  eval_f(s, xv, fx ? fv : NULL, jac ? jv : NULL);
+  if (fx)
+    for (int i = 0; i < n; ++i) store(fx, i, fv[i]);
+  if (jac)
+    for (int i = 0; i < n * n; ++i) store(jac, i, jv[i]);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Linear solve: Gaussian elimination with partial pivoting (outer product */
+/* form), then forward and back substitution.                              */
+/* ---------------------------------------------------------------------- */
+
+static int lu_solve(int n, cplx *A, const cplx *b, cplx *y) {
+  int piv[MAXN];
+  for (int k = 0; k < n; ++k) {
+    int mu = k;
+    double best = cabs1(A[k * n + k]);
+    for (int i = k + 1; i < n; ++i) {
+      double v = cabs1(A[i * n + k]);
+      if (v > best) { best = v; mu = i; } /* strict: ties keep the lowest row */
+    }
+    piv[k] = mu;
+    if (mu != k)
+      for (int j = 0; j < n; ++j) {
+        cplx tmp = A[k * n + j]; A[k * n + j] = A[mu * n + j]; A[mu * n + j] = tmp;
+      }
+    cplx p = A[k * n + k];
+    if (creal(p) == 0.0 && cimag(p) == 0.0) return -1;
+    for (int i = k + 1; i < n; ++i) {
+      A[i * n + k] = smith_div(A[i * n + k], p);
+      for (int j = k + 1; j < n; ++j) A[i * n + j] -= A[i * n + k] * A[k * n + j];
+    }
+  }
+  cplx z[MAXN];
+  for (int i = 0; i < n; ++i) z[i] = b[i];
+  for (int k = 0; k < n; ++k) {
+    cplx tmp = z[k]; z[k] = z[piv[k]]; z[piv[k]] = tmp;
+  }
+  for (int i = 0; i < n; ++i) /* L z = P b, unit lower triangular */
+    for (int j = 0; j < i; ++j) z[i] -= A[i * n + j] * z[j];
+  for (int i = n - 1; i >= 0; --i) { /* U y = z */
+    cplx v = z[i];
+    for (int j = i + 1; j < n; ++j) v -= A[i * n + j] * y[j];
+    y[i] = smith_div(v, A[i * n + i]);
+  }
+  return 0;
+}
+
+int ref_lu_solve(int n, const double *A, const double *b, double *y) {
+  if (n < 1 || n > MAXN) return -2;
+  cplx Av[MAXN * MAXN], bv[MAXN], yv[MAXN];
+  for (int i = 0; i < n * n; ++i) Av[i] = load(A, i);
+  for (int i = 0; i < n; ++i) bv[i] = load(b, i);
+  int rc = lu_solve(n, Av, bv, yv);
+  for (int i = 0; i < n; ++i) store(y, i, yv[i]);
+  return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Homotopy H(x,t) = gamma (1-t) g(x) + t f(x)                              */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+  const ref_system *f, *g; /* g == NULL: total degree */
+  int n;
+  int32_t deg[MAXN];
+  cplx gamma;
+} homotopy;
+
+static void eval_g(const homotopy *h, const cplx *x, cplx *gx, cplx *jg) {
+  const int n = h->n;
+  if (h->g) { eval_f(h->g, x, gx, jg); return; }
+  for (int i = 0; i < n; ++i) { /* g_i = x_i^{d_i} - 1, dg_i/dx_i = d_i x_i^{d_i-1} */
+    cplx p = 1.0;
+    for (int e = 0; e < h->deg[i] - 1; ++e) p = p * x[i];
+    if (gx) gx[i] = p * x[i] - 1.0;
+    if (jg) {
+      for (int j = 0; j < n; ++j) jg[i * n + j] = 0.0;
+      jg[i * n + i] = (double)h->deg[i] * p;
+    }
+  }
+}
+
+/* H and J_x at (x, t); Ht = dH/dt = f - gamma g (any of the outputs may be NULL). */
+static void eval_h(const homotopy *h, const cplx *x, double t, cplx *H, cplx *Jx, cplx *Ht) {
+  const int n = h->n;
+  cplx fx[MAXN], gx[MAXN], jf[MAXN * MAXN], jg[MAXN * MAXN];
+  eval_f(h->f, x, fx, Jx ? jf : NULL);
+  eval_g(h, x, gx, Jx ? jg : NULL);
+  cplx s = h->gamma * (1.0 - t);
+  for (int i = 0; i < n; ++i) {
+    if (H) H[i] = s * gx[i] + t * fx[i];
+    if (Ht) Ht[i] = fx[i] - h->gamma * gx[i];
+  }
+  if (Jx)
+    for (int i = 0; i < n * n; ++i) Jx[i] = t * jf[i] + s * jg[i];
+}
+
+/* ---------------------------------------------------------------------- */
+/* One path                                                                 */
+/* ---------------------------------------------------------------------- */
+
+void ref_start_point(int n, const int32_t *degrees, int64_t path_id, double *x) {
+  int64_t p = path_id;
+  for (int i = 0; i < n; ++i) {
+    int64_t k = p % degrees[i];
+    p /= degrees[i];
+    double ang = 2.0 * M_PI * (double)k / (double)degrees[i];
+    x[2 * i] = cos(ang);
+    x[2 * i + 1] = sin(ang);
+  }
+}
+
+/* Davidenko direction dx/dt = -J_x^{-1} H_t at (x, t). */
+static int tangent(const homotopy *h, const cplx *x, double t, cplx *k, ref_path_stats *st) {
+  const int n = h->n;
+  cplx J[MAXN * MAXN], Ht[MAXN], rhs[MAXN];
+  eval_h(h, x, t, NULL, J, Ht);
+  st->evals++;
+  for (int i = 0; i < n; ++i) rhs[i] = -Ht[i];
+  st->solves++;
+  if (lu_solve(n, J, rhs, k) != 0) return -1;
+  return all_finite(n, k) ? 0 : -1;
+}
+
+/* Classical fourth-order Runge-Kutta step for the Davidenko equation
+ * dx/dt = -J_x^{-1} H_t from (x, t) with step hstep to t_new = t + hstep;
+ * each stage is a fresh evaluation and solve. */
+static int rk4_predict(const homotopy *h, const cplx *x, double t, double hstep, double t_new,
+                       cplx *xp, ref_path_stats *st) {
+  const int n = h->n;
+  cplx xs[MAXN], k1[MAXN], k2[MAXN], k3[MAXN], k4[MAXN];
+  double th = t + 0.5 * hstep;
+  if (tangent(h, x, t, k1, st) != 0) return -1;
+  for (int i = 0; i < n; ++i) xs[i] = x[i] + (0.5 * hstep) * k1[i];
+  if (tangent(h, xs, th, k2, st) != 0) return -1;
+  for (int i = 0; i < n; ++i) xs[i] = x[i] + (0.5 * hstep) * k2[i];
+  if (tangent(h, xs, th, k3, st) != 0) return -1;
+  for (int i = 0; i < n; ++i) xs[i] = x[i] + hstep * k3[i];
+  if (tangent(h, xs, t_new, k4, st) != 0) return -1;
+  for (int i = 0; i < n; ++i)
+    xp[i] = x[i] + (hstep / 6.0) * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+  return all_finite(n, xp) ? 0 : -1;
+}
+
+/* Newton on H(., t) from x (in place).  Succeeds when the update satisfies
+ * ||dx|| <= tol * max(1, ||x||) (x after the update); fails on a zero
+ * pivot, a non-finite value, no contraction (||dx_j|| > ||dx_{j-1}||/2 from
+ * the second iteration on), or when max_it iterations do not succeed. */
+static int newton(const homotopy *h, cplx *x, double t, int max_it, double tol,
+                  int check_contraction, ref_path_stats *st) {
+  const int n = h->n;
+  double prev = 0.0;
+  for (int it = 1; it <= max_it; ++it) {
+    cplx J[MAXN * MAXN], H[MAXN], dx[MAXN];
+    eval_h(h, x, t, H, J, NULL);
+    st->evals++;
+    st->solves++;
+    st->newton_iters++;
+    if (lu_solve(n, J, H, dx) != 0) return 0;
+    for (int i = 0; i < n; ++i) x[i] -= dx[i];
+    if (!all_finite(n, dx) || !all_finite(n, x)) return 0;
+    double nd = norm_inf(n, dx);
+    double nx = norm_inf(n, x);
+    if (nd <= tol * (nx > 1.0 ? nx : 1.0)) return 1;
+    if (check_contraction && it >= 2 && nd > 0.5 * prev) return 0;
+    prev = nd;
+  }
+  return 0;
+}
+
+static void track_one(const homotopy *h, const cplx *x_start, const ref_tolerances *tol,
+                      cplx *x_end, int32_t *status, ref_path_stats *st) {
+  const int n = h->n;
+  cplx x[MAXN], xp[MAXN];
+  memset(st, 0, sizeof(*st));
+  for (int i = 0; i < n; ++i) x[i] = x_start[i];
+  double t = 0.0, hstep = tol->h_init;
+  int accepts = 0;
+  int32_t stat = -1;
+
+  while (t < 1.0) {
+    /* step size, clipped so the step ends exactly at t = 1 */
+    double t_new;
+    if (hstep >= 1.0 - t) { hstep = 1.0 - t; t_new = 1.0; }
+    else t_new = t + hstep;
+
+    /* RK4 predictor on dx/dt = -J_x^{-1} H_t */
+    int ok = rk4_predict(h, x, t, hstep, t_new, xp, st) == 0;
+    /* Newton corrector at t_new */
+    if (ok) ok = newton(h, xp, t_new, tol->max_newton, tol->tol_corr, 1, st);
+
+    st->steps++;
+    if (ok) {
+      t = t_new;
+      for (int i = 0; i < n; ++i) x[i] = xp[i];
+      if (++accepts == 3) {
+        hstep = 2.0 * hstep < tol->h_max ? 2.0 * hstep : tol->h_max;
+        accepts = 0;
+      }
+    } else {
+      st->rejections++;
+      hstep = 0.5 * hstep;
+      accepts = 0;
+    }
+    if (norm_inf(n, x) > tol->div_radius) { stat = REF_DIVERGED; break; }
+    if (t >= 1.0) break; /* reached t = 1: the step-size tests no longer apply */
+    if (hstep < tol->h_min) { stat = REF_FAILED_MINSTEP; break; }
+    if (st->steps > tol->max_steps) { stat = REF_FAILED_MAXSTEPS; break; }
+  }
+
+  if (stat < 0) {
+    /* t = 1: Newton on f = H(., 1) without the contraction test */
+    newton(h, x, 1.0, tol->max_newton_final, tol->tol_final, 0, st);
+    cplx fx[MAXN];
+    eval_f(h->f, x, fx, NULL);
+    double res = norm_inf(n, fx), nx = norm_inf(n, x);
+    st->residual = res;
+    if (res <= tol->tol_residual && nx <= tol->div_radius) stat = REF_CONVERGED;
+    else if (nx > tol->div_radius) stat = REF_DIVERGED;
+    else stat = REF_FAILED_NEWTON_T1;
+  } else {
+    cplx fx[MAXN];
+    eval_f(h->f, x, fx, NULL);
+    st->residual = norm_inf(n, fx);
+  }
+  st->t_final = t;
+  for (int i = 0; i < n; ++i) x_end[i] = x[i];
+  *status = stat;
+}
+
+static int make_homotopy(const ref_system *f, const ref_system *g, const double *gamma,
+                         homotopy *h) {
+  memset(h, 0, sizeof(*h));
+  h->f = f;
+  h->g = g;
+  h->n = f->n;
+  h->gamma = CMPLX(gamma[0], gamma[1]);
+  for (int i = 0; i < f->n; ++i) {
+    int d = 0;
+    for (int t = f->eq_ptr[i]; t < f->eq_ptr[i + 1]; ++t) {
+      int s = 0;
+      for (int l = 0; l < f->n; ++l) s += f->exps[(size_t)t * f->n + l];
+      if (s > d) d = s;
+    }
+    if (d < 1) return -1;
+    h->deg[i] = d;
+  }
+  return 0;
+}
+
+int ref_rk4_predict(const ref_system *f, const ref_system *g, const double *gamma,
+                    const double *x, double t, double hstep, double *xp) {
+  if (!f || f->n < 1 || f->n > MAXN) return -1;
+  homotopy h;
+  if (make_homotopy(f, g, gamma, &h) != 0) return -1;
+  cplx xv[MAXN], pv[MAXN];
+  for (int i = 0; i < f->n; ++i) xv[i] = load(x, i);
+  ref_path_stats st;
+  memset(&st, 0, sizeof(st));
+  int rc = rk4_predict(&h, xv, t, hstep, t + hstep, pv, &st);
+  for (int i = 0; i < f->n; ++i) store(xp, i, pv[i]);
+  return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Work crew: threads pull path indices from an atomic next-job counter.   */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+  const homotopy *h;
+  const double *start;
+  const int64_t *ids;
+  int64_t n_paths;
+  const ref_tolerances *tol;
+  double *endpoints;
+  int32_t *status;
+  ref_path_stats *stats;
+  atomic_llong next;
+} crew;
+
+static void *crew_worker(void *arg) {
+  crew *c = (crew *)arg;
+  const int n = c->h->n;
+  for (;;) {
+    int64_t k = atomic_fetch_add(&c->next, 1);
+    if (k >= c->n_paths) break;
+    cplx xs[MAXN], xe[MAXN];
+    if (c->start) {
+      for (int i = 0; i < n; ++i) xs[i] = load(c->start + (size_t)2 * n * k, i);
+    } else {
+      double tmp[2 * MAXN];
+      ref_start_point(n, c->h->deg, c->ids ? c->ids[k] : k, tmp);
+      for (int i = 0; i < n; ++i) xs[i] = load(tmp, i);
+    }
+    ref_path_stats st;
+    int32_t s;
+    track_one(c->h, xs, c->tol, xe, &s, &st);
+    for (int i = 0; i < n; ++i) store(c->endpoints + (size_t)2 * n * k, i, xe[i]);
+    c->status[k] = s;
+    if (c->stats) c->stats[k] = st;
+  }
+  return NULL;
+}
+
+int ref_track_paths(const ref_system *f, const ref_system *g, const double *gamma,
+                    const double *start, const int64_t *path_ids, int64_t n_paths,
+                    const ref_tolerances *tol, double *endpoints, int32_t *status,
+                    ref_path_stats *stats, int32_t n_threads) {
+  if (!f || f->n < 1 || f->n > MAXN || n_paths < 0 || !endpoints || !status) return -1;
+  if (g && g->n != f->n) return -1;
+  if (g && !start) return -1;
+  ref_tolerances deftol;
+  if (!tol) { ref_default_tolerances(&deftol); tol = &deftol; }
+  homotopy h;
+  if (make_homotopy(f, g, gamma, &h) != 0) return -1;
+  crew c;
+  c.h = &h;
+  c.start = start;
+  c.ids = path_ids;
+  c.n_paths = n_paths;
+  c.tol = tol;
+  c.endpoints = endpoints;
+  c.status = status;
+  c.stats = stats;
+  atomic_init(&c.next, 0);
+  if (n_threads < 1) n_threads = 1;
+  if (n_threads == 1) {
+    crew_worker(&c);
+    return 0;
+  }
+  pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)n_threads);
+  if (!th) return -3;
+  int started = 0;
+  for (int i = 0; i < n_threads; ++i)
+    if (pthread_create(&th[i], NULL, crew_worker, &c) == 0) ++started;
+  if (started == 0) crew_worker(&c);
+  for (int i = 0; i < started; ++i) pthread_join(th[i], NULL);
+  free(th);
+  return 0;
+}
+
+int64_t ref_find_duplicates(int n, int64_t n_paths, const double *endpoints,
+                            const int32_t *status, double rel, int64_t *pairs,
+                            int64_t max_pairs) {
+  int64_t count = 0;
+  for (int64_t a = 0; a < n_paths; ++a) {
+    if (status[a] != REF_CONVERGED) continue;
+    cplx xa[MAXN];
+    for (int i = 0; i < n; ++i) xa[i] = load(endpoints + (size_t)2 * n * a, i);
+    double scale = norm_inf(n, xa);
+    if (scale < 1.0) scale = 1.0;
+    for (int64_t b = a + 1; b < n_paths; ++b) {
+      if (status[b] != REF_CONVERGED) continue;
+      cplx d[MAXN];
+      for (int i = 0; i < n; ++i) d[i] = load(endpoints + (size_t)2 * n * b, i) - xa[i];
+      if (norm_inf(n, d) <= rel * scale) {
+        if (count < max_pairs) { pairs[2 * count] = a; pairs[2 * count + 1] = b; }
+        ++count;
+      }
+    }
+  }
+  return count;
+}
