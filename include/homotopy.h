@@ -1,0 +1,216 @@
+/*
+ * homotopy.h -- C ABI of libhomotopy, a batched path tracker for polynomial
+ * homotopies on AMD Instinct MI355X (gfx950), complex FP64 throughout.
+ *
+ * What it computes.  For a square polynomial system f(x) = 0 in n unknowns,
+ * the library tracks the solution paths of
+ *
+ *     H(x, t) = gamma (1 - t) g(x) + t f(x),   t from 0 to 1,
+ *
+ * with the total-degree start system g_i(x) = x_i^{d_i} - 1 (d_i the degree
+ * of f_i) and a random complex constant gamma.  The paths are independent of
+ * each other, which is what makes the tracking "pleasingly parallel" and
+ * lets the work be handed out dynamically (paper: Section 1, the problem
+ * statement and the work crew model; Section 2.2, tracking the paths of a
+ * start system with dynamic load balancing; Section 3.2, Theorem 3.1 on the
+ * speedup of tracking n paths with p workers).  Each endpoint comes back
+ * classified, the finite / "at infinity" split of Section 3.1 (Figure 3).
+ *
+ * The tracking step itself is not given in the paper; the library follows
+ * this reading: a fourth-order Runge-Kutta predictor on dx/dt = -J_x^{-1} H_t,
+ * a Newton corrector at the new t (at most max_newton iterations, success
+ * when ||dx||_inf <= tol_corr * max(1, ||x||_inf), failure when an iteration
+ * does not halve the update), step halving on failure and doubling after
+ * three successes (capped at h_max, last step clipped to t = 1), truncation
+ * of paths with ||x||_inf > div_radius, and a final Newton at t = 1 with the
+ * residual test ||f(x)||_inf <= tol_residual.
+ *
+ * Start points.  Path p (0 <= p < prod d_i) starts at x_i = exp(2 pi i k_i / d_i)
+ * where p = sum_i k_i prod_{j<i} d_j (k_1 varies fastest).  Endpoint arrays
+ * are indexed by path id.
+ *
+ * Conventions.
+ *   - Return values: 0 on success or a negative HP_E_* code; the message of
+ *     the last error on the calling thread is hp_last_error().
+ *   - Ownership: the caller owns every buffer it passes.  Host inputs are
+ *     copied before a call returns; the library never frees caller memory.
+ *     A context owns its device workspace and stream.
+ *   - Host arrays are plain host memory.  "_device" entry points take device
+ *     pointers (e.g. from torch tensors) and run asynchronously on the given
+ *     HIP stream (NULL: the context's stream).
+ *   - Threads: one context per host thread.  A server is internally
+ *     synchronised.
+ */
+#ifndef HOMOTOPY_H
+#define HOMOTOPY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HP_MAX_N 12        /* largest number of unknowns */
+#define HP_MAX_EXPONENT 15 /* largest exponent of one variable in a term */
+
+/* error codes */
+#define HP_OK 0
+#define HP_E_INVALID_ARG (-1)
+#define HP_E_UNSUPPORTED_N (-2)
+#define HP_E_OOM (-3)
+#define HP_E_DEVICE (-4)
+#define HP_E_BUDGET (-5)
+
+/* tracking modes */
+#define HP_PLAIN 0   /* one kernel launch per step, host loop, static path map */
+#define HP_BATCHED 1 /* one persistent launch, device atomic path-refill queue */
+
+typedef struct { double re, im; } hp_c64;
+
+/* A square system, CSR over equations.  Equation i owns the terms
+ * eq_ptr[i] .. eq_ptr[i+1]-1; term k is coeff[k] * prod_j x_j^exps[k*n+j].
+ * Requirements: 1 <= n <= HP_MAX_N, every exponent <= HP_MAX_EXPONENT, every
+ * equation of degree >= 1 and at most HP_MAX_N variables per term. */
+typedef struct {
+  int32_t n;
+  int32_t n_terms;
+  const int32_t *eq_ptr; /* [n+1] */
+  const hp_c64 *coeff;   /* [n_terms] */
+  const uint8_t *exps;   /* [n_terms*n], dense exponent vectors */
+} hp_system;
+
+typedef struct {
+  double tol_residual; /* 1e-10: CONVERGED needs ||f(x_end)||_inf <= this    */
+  double tol_corr;     /* 1e-8:  Newton corrector relative update size        */
+  double tol_final;    /* 1e-13: final Newton at t = 1, relative update size  */
+  double div_radius;   /* 1e8:   ||x||_inf beyond this -> DIVERGED (truncate)  */
+  double h_init;       /* 0.01 */
+  double h_min;        /* 1e-13: smaller step -> FAILED_MINSTEP               */
+  double h_max;        /* 0.1 */
+  int32_t max_steps;        /* 10000: more attempts -> FAILED_MAXSTEPS */
+  int32_t max_newton;       /* 3 */
+  int32_t max_newton_final; /* 6 */
+} hp_tolerances;
+
+typedef enum {
+  HP_CONVERGED = 0,        /* finite endpoint, residual test passed          */
+  HP_DIVERGED = 1,         /* ||x||_inf > div_radius ("at infinity")         */
+  HP_FAILED_MINSTEP = 2,   /* step size fell below h_min before t = 1        */
+  HP_FAILED_MAXSTEPS = 3,  /* more than max_steps attempts                   */
+  HP_FAILED_NEWTON_T1 = 4  /* reached t = 1 but the residual test failed     */
+} hp_status;
+
+typedef struct {
+  int32_t steps;        /* predictor-corrector attempts                       */
+  int32_t rejections;   /* rejected attempts                                  */
+  int32_t newton_iters; /* corrector iterations, final Newton included        */
+  int32_t evals;        /* evaluations of H and J_x (predictor + corrector)   */
+  int32_t solves;       /* linear solves                                      */
+  int32_t pad;
+  double t_final;       /* t where tracking stopped                           */
+  double residual;      /* ||f(x_end)||_inf                                   */
+} hp_path_stats;
+
+typedef struct {
+  double kernel_ms;   /* device time of the tracking kernels (HIP events)     */
+  double total_ms;    /* host wall time of the whole call                     */
+  int64_t launches;   /* tracking kernel launches                             */
+  int32_t waves_per_group; /* kernel variant used (rows of J split over waves) */
+  int32_t max_n;      /* compiled size bound of the variant used              */
+  int32_t groups;     /* workgroups launched (persistent: resident groups)    */
+  int32_t pad;
+} hp_timing;
+
+typedef struct hp_context hp_context;
+typedef struct hp_plan hp_plan;
+typedef struct hp_server hp_server;
+
+/* Context on HIP device `device`.  Creates a stream of default priority. */
+int hp_context_create(int device, hp_context **out);
+void hp_context_destroy(hp_context *ctx);
+/* Message of the last failed call on this thread ("" if none). */
+const char *hp_last_error(void);
+void hp_default_tolerances(hp_tolerances *tol);
+/* Timing of the last tracking call made with ctx. */
+int hp_last_timing(const hp_context *ctx, hp_timing *out);
+/* Number of total-degree paths of f (prod of equation degrees); -1 if invalid
+ * or larger than 2^62. */
+int64_t hp_path_count(const hp_system *f);
+
+/* Host-memory convenience call: tracks paths 0..n_paths-1 of f.
+ *   g must be NULL and start must be NULL (total-degree start system,
+ *     start points decoded from path ids); other values are rejected.
+ *   endpoints [n_paths*n], status [n_paths], stats [n_paths] or NULL.
+ *   mode: HP_PLAIN or HP_BATCHED. */
+int hp_track_paths(hp_context *ctx, const hp_system *f, const hp_system *g, const hp_c64 *start,
+                   int64_t n_paths, hp_c64 gamma, const hp_tolerances *tol, hp_c64 *endpoints,
+                   int32_t *status, hp_path_stats *stats, int32_t mode);
+
+/* A plan: f packed and resident on the device, with a kernel variant chosen
+ * (autotuned when tune != 0 and no cached choice exists). */
+int hp_plan_create(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
+                   int32_t tune, hp_plan **out);
+void hp_plan_destroy(hp_plan *plan);
+/* Forces the kernel variant (waves per workgroup: 1, 2, 4 or 8; 0 = automatic). */
+int hp_plan_set_variant(hp_plan *plan, int32_t waves_per_group);
+
+/* Device-memory call: tracks the paths whose ids are ids[0..n_paths-1]
+ * (device int64 array; NULL means ids 0..n_paths-1).  Outputs are device
+ * arrays indexed like ids: endpoints [n_paths*n] hp_c64, status [n_paths],
+ * stats [n_paths] or NULL.  Asynchronous on `stream` (NULL: context stream)
+ * except in HP_PLAIN mode, whose host step loop reads an active-path count
+ * back after every launch.  Ids must be < hp_path_count. */
+int hp_plan_track_device(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endpoints,
+                         int32_t *status, hp_path_stats *stats, int32_t mode, void *stream);
+
+/* Many systems of different n in one persistent launch (one refill queue per
+ * system).  System s owns the paths path_offsets[s] .. path_offsets[s+1]-1
+ * of the output (path_offsets[0] = 0, path_offsets[s+1] - path_offsets[s] =
+ * hp_path_count(&fs[s])); its endpoints start at hp_c64 index x_offsets[s]
+ * (x_offsets[s+1] = x_offsets[s] + paths_s * n_s).  Both offset arrays have
+ * n_systems+1 entries and are written by hp_batch_layout.  Host memory. */
+int hp_batch_layout(const hp_system *fs, int32_t n_systems, int64_t *path_offsets,
+                    int64_t *x_offsets);
+int hp_track_batch(hp_context *ctx, const hp_system *fs, int32_t n_systems,
+                   const hp_c64 *gammas, const hp_tolerances *tol, hp_c64 *endpoints,
+                   int32_t *status, hp_path_stats *stats);
+
+/* Endpoint post-pass (host): pairs (a, b), a < b, of CONVERGED endpoints with
+ * ||x_a - x_b||_inf <= rel * max(1, ||x_a||_inf), found by sorting on a random
+ * real projection and comparing within a window.  Writes up to max_pairs
+ * pairs to pairs[2k], pairs[2k+1]; returns the number of pairs found. */
+int64_t hp_find_duplicates(int32_t n, int64_t n_paths, const hp_c64 *endpoints,
+                           const int32_t *status, double rel, int64_t *pairs, int64_t max_pairs);
+
+/* Tracks all paths of f (HP_BATCHED), then re-tracks both paths of every
+ * duplicate pair once with h_max = min(h_max, 0.01) and tol_corr =
+ * min(tol_corr, 1e-10).  *remaining_pairs receives the duplicate pairs left
+ * afterwards.  Host memory, like hp_track_paths. */
+int hp_solve(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
+             hp_c64 *endpoints, int32_t *status, hp_path_stats *stats, int64_t *remaining_pairs);
+
+/* Serving: a request loop with continuous batching.  Requests (one system
+ * each, all its total-degree paths) are admitted while the resident path
+ * state of admitted requests fits in hbm_budget_bytes; larger requests are
+ * split into path chunks.  Work of requests admitted while others run
+ * overlaps on the device. */
+int hp_server_create(hp_context *ctx, size_t hbm_budget_bytes, hp_server **out);
+/* Queues a request; the system is copied.  *req_id receives its id. */
+int hp_server_submit(hp_server *srv, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
+                     int64_t *req_id);
+/* *done = 1 once every path of the request has finished (non-blocking). */
+int hp_server_poll(hp_server *srv, int64_t req_id, int32_t *done);
+/* Blocks until the request is done, then copies its results (host arrays
+ * sized for hp_path_count paths; stats may be NULL) and forgets it.
+ * *latency_ms (nullable) receives completion time minus submission time. */
+int hp_server_wait(hp_server *srv, int64_t req_id, hp_c64 *endpoints, int32_t *status,
+                   hp_path_stats *stats, double *latency_ms);
+/* Peak resident path-state bytes admitted so far. */
+int hp_server_peak_bytes(hp_server *srv, size_t *out);
+void hp_server_destroy(hp_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

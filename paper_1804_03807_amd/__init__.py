@@ -1,0 +1,268 @@
+"""Batched FP64 homotopy path tracking on AMD Instinct MI355X (gfx950).
+
+Python binding of libhomotopy (include/homotopy.h): argument marshalling
+only.  Host entry points take and return numpy arrays; device entry points
+take torch tensors on the GPU (torch supplies device memory and streams).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (CONVERGED, DIVERGED, FAILED_MAXSTEPS, FAILED_MINSTEP, FAILED_NEWTON_T1,
+                   HP_BATCHED, HP_MAX_N, HP_PLAIN, STATS_DTYPE, HomotopyError, HpC64,
+                   HpSystem, HpTiming, HpTolerances, check, load)
+
+__all__ = [
+    "Context", "Plan", "Server", "default_tolerances", "path_count", "batch_layout",
+    "find_duplicates", "CONVERGED", "DIVERGED", "FAILED_MINSTEP", "FAILED_MAXSTEPS",
+    "FAILED_NEWTON_T1", "HP_PLAIN", "HP_BATCHED", "STATS_DTYPE", "HomotopyError",
+]
+
+_MODES = {"plain": HP_PLAIN, "batched": HP_BATCHED, HP_PLAIN: HP_PLAIN, HP_BATCHED: HP_BATCHED}
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return ctypes.c_void_p(a.data_ptr())
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class _SysView:
+    """HpSystem over numpy buffers kept alive by this object."""
+
+    def __init__(self, s):
+        self.eq_ptr = np.ascontiguousarray(s.eq_ptr, dtype=np.int32)
+        self.coeff = np.ascontiguousarray(s.coeff, dtype=np.complex128)
+        self.exps = np.ascontiguousarray(s.exps, dtype=np.uint8)
+        self.n = int(s.n)
+        self.c = HpSystem(self.n, int(self.coeff.shape[0]), self.eq_ptr.ctypes.data,
+                          self.coeff.ctypes.data, self.exps.ctypes.data)
+
+
+def _c64(z):
+    z = complex(z)
+    return HpC64(z.real, z.imag)
+
+
+def default_tolerances(**over) -> HpTolerances:
+    t = HpTolerances()
+    load().hp_default_tolerances(ctypes.byref(t))
+    for k, v in over.items():
+        setattr(t, k, v)
+    return t
+
+
+def path_count(system) -> int:
+    return int(load().hp_path_count(ctypes.byref(_SysView(system).c)))
+
+
+def batch_layout(systems):
+    views = [_SysView(s) for s in systems]
+    arr = (HpSystem * len(views))(*[v.c for v in views])
+    po = np.zeros(len(views) + 1, np.int64)
+    xo = np.zeros(len(views) + 1, np.int64)
+    check(load().hp_batch_layout(arr, len(views), _ptr(po), _ptr(xo)))
+    return po, xo
+
+
+def find_duplicates(endpoints, status, rel=1e-6, max_pairs=1 << 16):
+    e = np.ascontiguousarray(endpoints, dtype=np.complex128)
+    s = np.ascontiguousarray(status, dtype=np.int32)
+    pairs = np.zeros((max_pairs, 2), np.int64)
+    cnt = load().hp_find_duplicates(int(e.shape[1]), int(e.shape[0]), _ptr(e), _ptr(s),
+                                    float(rel), _ptr(pairs), int(max_pairs))
+    if cnt < 0:
+        check(-1)
+    return pairs[: min(cnt, max_pairs)].copy()
+
+
+class Context:
+    """A libhomotopy context on one HIP device (its own stream)."""
+
+    def __init__(self, device: int = 0):
+        self._L = load()
+        h = ctypes.c_void_p()
+        check(self._L.hp_context_create(int(device), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            self._L.hp_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_timing(self) -> dict:
+        t = HpTiming()
+        check(self._L.hp_last_timing(self.handle, ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in HpTiming._fields_ if k != "pad"}
+
+    def track_paths(self, system, gamma, n_paths=None, tol=None, mode="batched", stats=True):
+        """Tracks total-degree paths 0..n_paths-1 (host arrays in and out).
+        Returns (endpoints complex[P, n], status int32[P], stats or None)."""
+        v = _SysView(system)
+        P = path_count(system) if n_paths is None else int(n_paths)
+        ends = np.zeros((P, v.n), np.complex128)
+        st = np.full(P, -1, np.int32)
+        sts = np.zeros(P, STATS_DTYPE) if stats else None
+        tol = tol or default_tolerances()
+        check(self._L.hp_track_paths(self.handle, ctypes.byref(v.c), None, None, P, _c64(gamma),
+                                     ctypes.byref(tol), _ptr(ends), _ptr(st), _ptr(sts),
+                                     _MODES[mode]))
+        return ends, st, sts
+
+    def track_batch(self, systems, gammas, tol=None, stats=True):
+        """Many systems in one persistent launch.  Returns per-system lists of
+        (endpoints, status, stats)."""
+        views = [_SysView(s) for s in systems]
+        arr = (HpSystem * len(views))(*[x.c for x in views])
+        po, xo = batch_layout(systems)
+        ends = np.zeros(int(xo[-1]), np.complex128)
+        st = np.full(int(po[-1]), -1, np.int32)
+        sts = np.zeros(int(po[-1]), STATS_DTYPE) if stats else None
+        g = np.ascontiguousarray(np.asarray(gammas, dtype=np.complex128))
+        tol = tol or default_tolerances()
+        check(self._L.hp_track_batch(self.handle, arr, len(views), _ptr(g), ctypes.byref(tol),
+                                     _ptr(ends), _ptr(st), _ptr(sts)))
+        out = []
+        for i, x in enumerate(views):
+            p0, p1 = int(po[i]), int(po[i + 1])
+            e = ends[int(xo[i]):int(xo[i + 1])].reshape(p1 - p0, x.n)
+            out.append((e, st[p0:p1], sts[p0:p1] if stats else None))
+        return out
+
+    def solve(self, system, gamma, tol=None):
+        """All paths (batched), then the duplicate-endpoint re-track pass.
+        Returns (endpoints, status, stats, remaining duplicate pairs)."""
+        v = _SysView(system)
+        P = path_count(system)
+        ends = np.zeros((P, v.n), np.complex128)
+        st = np.full(P, -1, np.int32)
+        sts = np.zeros(P, STATS_DTYPE)
+        rem = ctypes.c_int64(0)
+        tol = tol or default_tolerances()
+        check(self._L.hp_solve(self.handle, ctypes.byref(v.c), _c64(gamma), ctypes.byref(tol),
+                               _ptr(ends), _ptr(st), _ptr(sts), ctypes.byref(rem)))
+        return ends, st, sts, int(rem.value)
+
+    def plan(self, system, gamma, tol=None, tune=False):
+        return Plan(self, system, gamma, tol, tune)
+
+
+class Plan:
+    """A system resident on the device; tracks paths into torch tensors."""
+
+    def __init__(self, ctx: Context, system, gamma, tol=None, tune=False):
+        self.ctx = ctx
+        self._L = ctx._L
+        self._view = _SysView(system)
+        self.n = self._view.n
+        self.paths = path_count(system)
+        self.tol = tol or default_tolerances()
+        h = ctypes.c_void_p()
+        check(self._L.hp_plan_create(ctx.handle, ctypes.byref(self._view.c), _c64(gamma),
+                                     ctypes.byref(self.tol), int(bool(tune)), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            self._L.hp_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_variant(self, waves_per_group: int):
+        check(self._L.hp_plan_set_variant(self.handle, int(waves_per_group)))
+
+    def outputs(self, n_paths, stats=True, device="cuda"):
+        """Device tensors (endpoints as float64 [P, n, 2], status, stats bytes)."""
+        import torch
+        e = torch.empty((n_paths, self.n, 2), dtype=torch.float64, device=device)
+        s = torch.empty((n_paths,), dtype=torch.int32, device=device)
+        st = torch.empty((n_paths, STATS_DTYPE.itemsize), dtype=torch.uint8, device=device) \
+            if stats else None
+        return e, s, st
+
+    def track_device(self, endpoints, status, stats=None, ids=None, n_paths=None,
+                     mode="batched", stream=None):
+        """Tracks into device tensors.  ids: optional int64 device tensor."""
+        P = int(n_paths if n_paths is not None else status.shape[0])
+        sp = None
+        if stream is not None:
+            sp = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+        check(self._L.hp_plan_track_device(self.handle, _ptr(ids), P, _ptr(endpoints),
+                                           _ptr(status), _ptr(stats), _MODES[mode], sp))
+
+    @staticmethod
+    def stats_to_numpy(stats_tensor):
+        return stats_tensor.cpu().numpy().view(STATS_DTYPE).reshape(-1)
+
+    @staticmethod
+    def endpoints_to_numpy(e):
+        a = e.cpu().numpy()
+        return a[..., 0] + 1j * a[..., 1]
+
+
+class Server:
+    """Request loop with continuous batching (hp_server_*)."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int):
+        self.ctx = ctx
+        self._L = ctx._L
+        h = ctypes.c_void_p()
+        check(self._L.hp_server_create(ctx.handle, int(hbm_budget_bytes), ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, system, gamma, tol=None) -> int:
+        v = _SysView(system)
+        tol = tol or default_tolerances()
+        rid = ctypes.c_int64(-1)
+        check(self._L.hp_server_submit(self.handle, ctypes.byref(v.c), _c64(gamma),
+                                       ctypes.byref(tol), ctypes.byref(rid)))
+        self._keep[int(rid.value)] = (v.n, path_count(system))
+        return int(rid.value)
+
+    def poll(self, rid) -> bool:
+        d = ctypes.c_int32(0)
+        check(self._L.hp_server_poll(self.handle, int(rid), ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, rid, stats=False):
+        n, P = self._keep.pop(int(rid))
+        ends = np.zeros((P, n), np.complex128)
+        st = np.full(P, -1, np.int32)
+        sts = np.zeros(P, STATS_DTYPE) if stats else None
+        lat = ctypes.c_double(0.0)
+        check(self._L.hp_server_wait(self.handle, int(rid), _ptr(ends), _ptr(st), _ptr(sts),
+                                     ctypes.byref(lat)))
+        return ends, st, sts, float(lat.value)
+
+    def peak_bytes(self) -> int:
+        v = ctypes.c_size_t(0)
+        check(self._L.hp_server_peak_bytes(self.handle, ctypes.byref(v)))
+        return int(v.value)
+
+    def close(self):
+        if self.handle:
+            self._L.hp_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,81 @@
+"""CPU-side checks of libhomotopy: it loads, exports every entry point the
+header declares, and its host-only logic (path counts, batch layout,
+duplicate detection, argument checks) behaves.  No GPU calls."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def hp():
+    import paper_1804_03807_amd as hp
+    hp.load()
+    return hp
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "homotopy.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(hp):
+    import ctypes
+    lib = ctypes.CDLL(hp._lib.SO_PATH)
+    names = declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(hp._lib.EXPORTED) == names
+
+
+def test_path_counts(hp):
+    assert hp.path_count(W.cyclic8().systems[0]) == 40320
+    assert hp.path_count(W.cyclic10().systems[0]) == 3628800
+    assert hp.path_count(W.dense_small().systems[0]) == 32
+    b = W.dense_batch(8)
+    for s in b.systems:
+        assert hp.path_count(s) == s.bezout()
+
+
+def test_rejects_bad_systems(hp):
+    s = W.cyclic_system(12, np.random.default_rng(0))
+    assert hp.path_count(s) == 479001600
+    bad = W.PolySystem(13, np.zeros(14, np.int32), np.zeros(0, np.complex128),
+                       np.zeros((0, 13), np.uint8))
+    assert hp.path_count(bad) == -1
+    s2 = W.dense_system(3, [2, 2, 2], np.random.default_rng(1))
+    s2.exps[0, 0] = 16  # exponent above the supported maximum
+    assert hp.path_count(s2) == -1
+    s3 = W.dense_system(3, [2, 2, 2], np.random.default_rng(1))
+    s3.eq_ptr[1] = s3.eq_ptr[2] + 1  # not monotone
+    assert hp.path_count(s3) == -1
+
+
+def test_batch_layout(hp):
+    b = W.dense_batch(5)
+    po, xo = hp.batch_layout(b.systems)
+    counts = [s.bezout() for s in b.systems]
+    assert list(np.diff(po)) == counts
+    assert list(np.diff(xo)) == [c * s.n for c, s in zip(counts, b.systems)]
+
+
+def test_find_duplicates_matches_oracle(hp, oracle_lib):
+    rng = np.random.default_rng(5)
+    n, P = 4, 600
+    x = (rng.standard_normal((P, n)) + 1j * rng.standard_normal((P, n))) * 3
+    for k in range(0, P, 37):  # plant near-copies, some inside and some outside 1e-6
+        j = (k * 7 + 11) % P
+        x[j] = x[k] * (1 + (3e-7 if k % 2 else 5e-6))
+    st = np.zeros(P, np.int32)
+    st[::9] = 2  # not converged: ignored
+    got = {tuple(p) for p in hp.find_duplicates(x, st)}
+    ref = {tuple(p) for p in oracle.find_duplicates(x, st)}
+    assert got == ref and len(ref) > 3
