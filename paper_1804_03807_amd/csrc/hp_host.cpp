@@ -173,6 +173,13 @@ struct Packed {
   std::vector<double2> roots;
   std::vector<DevSys> sys;
   int nl = 1, emax = 1, kmax = 0;
+  // workgroup LDS bytes of the n_max variant: largest over the systems
+  size_t lds(int nmax) const {
+    size_t b = 0;
+    for (const DevSys &d : sys)
+      b = std::max(b, hp::system_lds_bytes(nmax, d.n, d.emax, d.n_terms));
+    return b;
+  }
 };
 
 // Appends system f (already checked, info from check_system).
@@ -186,6 +193,8 @@ void pack_append(Packed &P, const hp_system *f, const SysInfo &info, hp_c64 gamm
   d.emax = info.emax;
   d.eq_base = (int32_t)P.kp.size();
   d.root_base = (int32_t)P.roots.size();
+  d.term_base = (int32_t)P.terms.size();
+  d.n_terms = f->n_terms;
   int64_t radix = 1;
   int roff = 0;
   for (int i = 0; i < n; ++i) {
@@ -205,43 +214,45 @@ void pack_append(Packed &P, const hp_system *f, const SysInfo &info, hp_c64 gamm
   d.out_path_base = out_path_base;
   d.out_x_base = out_x_base;
   d.ids = dev_ids;
-  for (int i = 0; i < n; ++i) {
-    // terms of equation i sorted by factor count (stable)
-    std::vector<std::pair<int, int>> order;  // (k, term)
+  // all terms of the system sorted by factor count (stable), equation in byte 15
+  std::vector<std::pair<int, int>> order;  // (k, term)
+  std::vector<int> eq_of(f->n_terms);
+  for (int i = 0; i < n; ++i)
     for (int t = f->eq_ptr[i]; t < f->eq_ptr[i + 1]; ++t) {
       int k = 0;
       for (int j = 0; j < n; ++j) k += f->exps[(size_t)t * n + j] > 0;
       order.push_back({k, t});
+      eq_of[t] = i;
     }
-    std::stable_sort(order.begin(), order.end(),
-                     [](const std::pair<int, int> &a, const std::pair<int, int> &b) {
-                       return a.first < b.first;
-                     });
-    int32_t kp[hp::kKSlots];
-    size_t pos = 0;
-    for (int k = 0; k <= HP_MAX_N; ++k) {
-      kp[k] = (int32_t)(P.terms.size());
-      while (pos < order.size() && order[pos].first == k) {
-        const int t = order[pos].second;
-        DevTerm T;
-        std::memset(&T, 0, sizeof(T));
-        T.cre = f->coeff[t].re;
-        T.cim = f->coeff[t].im;
-        uint8_t bytes[16] = {0};
-        bytes[0] = (uint8_t)k;
-        int m = 0;
-        for (int j = 0; j < n; ++j) {
-          const int e = f->exps[(size_t)t * n + j];
-          if (e > 0) bytes[1 + m++] = (uint8_t)(j | (e << 4));
-        }
-        std::memcpy(T.w, bytes, 16);
-        P.terms.push_back(T);
-        ++pos;
+  std::stable_sort(order.begin(), order.end(),
+                   [](const std::pair<int, int> &a, const std::pair<int, int> &b) {
+                     return a.first < b.first;
+                   });
+  int32_t kp[hp::kKSlots];
+  size_t pos = 0;
+  for (int k = 0; k <= HP_MAX_N; ++k) {
+    kp[k] = (int32_t)(P.terms.size()) - d.term_base;
+    while (pos < order.size() && order[pos].first == k) {
+      const int t = order[pos].second;
+      DevTerm T;
+      std::memset(&T, 0, sizeof(T));
+      T.cre = f->coeff[t].re;
+      T.cim = f->coeff[t].im;
+      uint8_t bytes[16] = {0};
+      bytes[0] = (uint8_t)k;
+      int m = 0;
+      for (int j = 0; j < n; ++j) {
+        const int e = f->exps[(size_t)t * n + j];
+        if (e > 0) bytes[1 + m++] = (uint8_t)(j | (e << 4));
       }
+      bytes[15] = (uint8_t)eq_of[t];
+      std::memcpy(T.w, bytes, 16);
+      P.terms.push_back(T);
+      ++pos;
     }
-    kp[HP_MAX_N + 1] = (int32_t)P.terms.size();
-    P.kp.insert(P.kp.end(), kp, kp + hp::kKSlots);
   }
+  kp[HP_MAX_N + 1] = (int32_t)P.terms.size() - d.term_base;
+  P.kp.insert(P.kp.end(), kp, kp + hp::kKSlots);
   P.sys.push_back(d);
   P.nl = std::max(P.nl, n);
   P.emax = std::max(P.emax, info.emax);
@@ -250,15 +261,25 @@ void pack_append(Packed &P, const hp_system *f, const SysInfo &info, hp_c64 gamm
 
 // Device copy of a Packed image.
 struct DevTables {
-  DevBuf terms, kp, roots, sys, qhead;
+  DevBuf tcoef, tmeta, kp, roots, sys, qhead;
   int upload(const Packed &P, hipStream_t s) {
     int rc;
-    if ((rc = terms.alloc(std::max<size_t>(1, P.terms.size()) * sizeof(DevTerm)))) return rc;
+    const size_t nt = std::max<size_t>(1, P.terms.size());
+    if ((rc = tcoef.alloc(nt * sizeof(double2)))) return rc;
+    if ((rc = tmeta.alloc(nt * sizeof(uint4)))) return rc;
     if ((rc = kp.alloc(std::max<size_t>(1, P.kp.size()) * sizeof(int32_t)))) return rc;
     if ((rc = roots.alloc(std::max<size_t>(1, P.roots.size()) * sizeof(double2)))) return rc;
     if ((rc = sys.alloc(std::max<size_t>(1, P.sys.size()) * sizeof(DevSys)))) return rc;
     if ((rc = qhead.alloc(std::max<size_t>(1, P.sys.size()) * sizeof(unsigned long long)))) return rc;
-    HIP_TRY(hipMemcpyAsync(terms.p, P.terms.data(), P.terms.size() * sizeof(DevTerm),
+    std::vector<double2> coef(P.terms.size());
+    std::vector<uint4> meta(P.terms.size());
+    for (size_t i = 0; i < P.terms.size(); ++i) {
+      coef[i] = make_double2(P.terms[i].cre, P.terms[i].cim);
+      std::memcpy(&meta[i], P.terms[i].w, sizeof(uint4));
+    }
+    HIP_TRY(hipMemcpyAsync(tcoef.p, coef.data(), coef.size() * sizeof(double2),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(tmeta.p, meta.data(), meta.size() * sizeof(uint4),
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(kp.p, P.kp.data(), P.kp.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, s));
@@ -276,25 +297,15 @@ struct DevTables {
 // ---------------------------------------------------------------------------
 
 int nmax_for(int n) {
-  for (const auto &v : hp::kVariants)
-    if (v.nmax >= n) return v.nmax;
+  for (int v : hp::kNmaxVariants)
+    if (v >= n) return v;
   return -1;
 }
 
-std::vector<int> waves_for(int nmax) {
-  std::vector<int> w;
-  for (const auto &v : hp::kVariants)
-    if (v.nmax == nmax) w.push_back(v.waves);
-  return w;
-}
-
-// default: one Jacobian row per wave when n fills the variant, else two
-int default_waves(int n, int nmax) {
-  std::vector<int> ws = waves_for(nmax);
-  int best = ws.back();
-  for (int w : ws)
-    if (w >= n && w < best) best = w;
-  return best;
+bool is_variant(int nmax) {
+  for (int v : hp::kNmaxVariants)
+    if (v == nmax) return true;
+  return false;
 }
 
 std::mutex g_tune_mu;
@@ -325,13 +336,13 @@ int tune_lookup(const std::string &key) {
   return it == g_tune_mem.end() ? 0 : it->second;
 }
 
-void tune_store(const std::string &key, int waves) {
+void tune_store(const std::string &key, int nmax) {
   std::lock_guard<std::mutex> g(g_tune_mu);
-  g_tune_mem[key] = waves;
+  g_tune_mem[key] = nmax;
   std::string path = tune_path();
   if (path.empty()) return;
   std::ofstream out(path, std::ios::app);
-  out << key << " " << waves << "\n";
+  out << key << " " << nmax << "\n";
 }
 
 }  // namespace
@@ -357,7 +368,7 @@ struct hp_plan {
   DevTables dev;
   hp_tolerances tol{};
   hp_c64 gamma{};
-  int nmax = 0, waves = 0;
+  int nmax = 0;
   // plain-mode state
   DevBuf px0, pt, ph, piv, pactive;
   DevBuf ids_scratch;
@@ -431,33 +442,33 @@ int64_t hp_path_count(const hp_system *f) {
 
 namespace {
 
-int variant_lds(hp_context *ctx, int nl, int waves, int emax, size_t *lds) {
-  *lds = hp::lds_bytes(nl, waves, emax);
-  if (*lds > ctx->max_lds)
-    return fail(HP_E_UNSUPPORTED_N, "workgroup LDS " + std::to_string(*lds) +
+int check_lds(hp_context *ctx, size_t lds) {
+  if (lds > ctx->max_lds)
+    return fail(HP_E_UNSUPPORTED_N, "workgroup LDS " + std::to_string(lds) +
                                         " B exceeds the device limit");
   return HP_OK;
 }
 
 // Persistent launch over the systems in `dev` (already uploaded).
-int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, int nmax, int waves,
+int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, int nmax,
                       const hp_tolerances &tol, int64_t total_paths, hp_c64 *endpoints,
                       int32_t *status, hp_path_stats *stats, hipStream_t s, int *groups_out) {
-  size_t lds;
-  int rc = variant_lds(ctx, P.nl, waves, P.emax, &lds);
+  const size_t lds = P.lds(nmax);
+  int rc = check_lds(ctx, lds);
   if (rc) return rc;
   int per_cu = 0;
-  HIP_TRY((hipError_t)hp_max_groups_per_cu(nmax, waves, lds, &per_cu));
+  HIP_TRY((hipError_t)hp_max_groups_per_cu(nmax, lds, &per_cu));
   if (per_cu < 1) return fail(HP_E_DEVICE, "kernel variant does not fit on a compute unit");
-  int64_t want = (total_paths + 63) / 64;
+  // enough wavefronts to hold every path once, at most a full device
+  int64_t per_wave = hp::kLanes / std::max(1, P.nl);
+  int64_t want = (total_paths + per_wave - 1) / per_wave;
   int64_t groups = std::min<int64_t>((int64_t)ctx->cus * per_cu, std::max<int64_t>(1, want));
   KArgs a;
   std::memset(&a, 0, sizeof(a));
   a.sys = dev.sys.as<DevSys>();
   a.n_systems = (int32_t)P.sys.size();
-  a.emax_all = P.emax;
-  a.nl = P.nl;
-  a.terms = dev.terms.as<DevTerm>();
+  a.tcoef = dev.tcoef.as<double2>();
+  a.tmeta = dev.tmeta.as<uint4>();
   a.eqp = dev.kp.as<int32_t>();
   a.roots = dev.roots.as<double2>();
   a.qhead = dev.qhead.as<unsigned long long>();
@@ -467,21 +478,18 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, int nmax
   a.tol = dev_tol(tol);
   HIP_TRY(hipMemsetAsync(dev.qhead.p, 0, P.sys.size() * sizeof(unsigned long long), s));
   HIP_TRY(hipEventRecord(ctx->ev0, s));
-  HIP_TRY((hipError_t)hp_launch_persistent(nmax, waves, a, (int)groups, lds, s));
+  HIP_TRY((hipError_t)hp_launch_persistent(nmax, a, (int)groups, lds, s));
   HIP_TRY(hipEventRecord(ctx->ev1, s));
   if (groups_out) *groups_out = (int)groups;
   return HP_OK;
 }
 
-int plan_variant(hp_plan *plan, int waves) {
-  plan->nmax = nmax_for(plan->info.n);
-  if (plan->nmax < 0) return fail(HP_E_UNSUPPORTED_N, "no kernel variant for this n");
-  std::vector<int> ws = waves_for(plan->nmax);
-  if (waves == 0) waves = default_waves(plan->info.n, plan->nmax);
-  if (std::find(ws.begin(), ws.end(), waves) == ws.end())
-    return fail(HP_E_INVALID_ARG, "waves_per_group " + std::to_string(waves) +
-                                      " not compiled for n_max " + std::to_string(plan->nmax));
-  plan->waves = waves;
+int plan_variant(hp_plan *plan, int nmax) {
+  if (nmax == 0) nmax = nmax_for(plan->info.n);
+  if (nmax < plan->info.n || !is_variant(nmax))
+    return fail(HP_E_INVALID_ARG, "no compiled kernel variant with n_max " + std::to_string(nmax) +
+                                      " for n = " + std::to_string(plan->info.n));
+  plan->nmax = nmax;
   return HP_OK;
 }
 
@@ -495,8 +503,8 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
   if ((rc = plan->ph.alloc((size_t)n_paths * sizeof(double)))) return rc;
   if ((rc = plan->piv.alloc((size_t)8 * n_paths * sizeof(int32_t)))) return rc;
   if ((rc = plan->pactive.alloc(sizeof(unsigned int)))) return rc;
-  size_t lds;
-  if ((rc = variant_lds(ctx, plan->P.nl, plan->waves, plan->P.emax, &lds))) return rc;
+  const size_t lds = plan->P.lds(plan->nmax);
+  if ((rc = check_lds(ctx, lds))) return rc;
   // system descriptor with this call's queue and ids
   DevSys d = plan->P.sys[0];
   d.n_paths = n_paths;
@@ -506,9 +514,8 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
   std::memset(&a, 0, sizeof(a));
   a.sys = plan->dev.sys.as<DevSys>();
   a.n_systems = 1;
-  a.emax_all = plan->P.emax;
-  a.nl = plan->P.nl;
-  a.terms = plan->dev.terms.as<DevTerm>();
+  a.tcoef = plan->dev.tcoef.as<double2>();
+  a.tmeta = plan->dev.tmeta.as<uint4>();
   a.eqp = plan->dev.kp.as<int32_t>();
   a.roots = plan->dev.roots.as<double2>();
   a.endpoints = (double2 *)endpoints;
@@ -522,21 +529,23 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
   a.ps.P = n_paths;
   a.ps.active = plan->pactive.as<unsigned int>();
   HIP_TRY(hipEventRecord(ctx->ev0, s));
-  HIP_TRY((hipError_t)hp_launch_plain_init(plan->nmax, a, s));
+  HIP_TRY((hipError_t)hp_launch_plain_init(a, s));
+  const int64_t per_wave = hp::kLanes / n;
+  const int wgs = (int)((n_paths + per_wave - 1) / per_wave);
   // every path ends within max_steps + 1 attempts plus the final Newton
   const int64_t max_launches = (int64_t)plan->tol.max_steps + 4;
   int64_t launches = 0;
   unsigned int active = 1;
   while (active > 0 && launches < max_launches) {
     HIP_TRY(hipMemsetAsync(plan->pactive.p, 0, sizeof(unsigned int), s));
-    HIP_TRY((hipError_t)hp_launch_plain_step(plan->nmax, plan->waves, a, lds, s));
+    HIP_TRY((hipError_t)hp_launch_plain_step(plan->nmax, a, wgs, lds, s));
     HIP_TRY(hipMemcpyAsync(&active, plan->pactive.p, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     ++launches;
   }
   HIP_TRY(hipEventRecord(ctx->ev1, s));
   ctx->last.launches = launches;
-  ctx->last.groups = (int32_t)((n_paths + 63) / 64);
+  ctx->last.groups = wgs;
   if (active > 0) return fail(HP_E_DEVICE, "plain tracker did not finish");
   return HP_OK;
 }
@@ -544,44 +553,43 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
 int autotune(hp_plan *plan) {
   const std::string key = tune_key(plan->info, plan->n_terms);
   int cached = tune_lookup(key);
-  std::vector<int> ws = waves_for(plan->nmax);
-  if (cached && std::find(ws.begin(), ws.end(), cached) != ws.end()) {
-    plan->waves = cached;
+  if (cached && is_variant(cached) && cached >= plan->info.n) {
+    plan->nmax = cached;
     return HP_OK;
   }
   hp_context *ctx = plan->ctx;
   // sample: enough paths to fill the device twice
-  const int64_t sample = std::min<int64_t>(plan->info.paths, (int64_t)ctx->cus * 64 * 2);
+  const int64_t per_wave = hp::kLanes / plan->info.n;
+  const int64_t sample = std::min<int64_t>(plan->info.paths, (int64_t)ctx->cus * 8 * per_wave * 2);
   DevBuf e, st;
   int rc;
   if ((rc = e.alloc((size_t)sample * plan->info.n * sizeof(hp_c64)))) return rc;
   if ((rc = st.alloc((size_t)sample * sizeof(int32_t)))) return rc;
   double best = 1e300;
-  int best_w = plan->waves;
-  for (int w : ws) {
-    size_t lds;
-    if (variant_lds(ctx, plan->P.nl, w, plan->P.emax, &lds) != HP_OK) continue;
+  int best_v = plan->nmax;
+  for (int v : hp::kNmaxVariants) {
+    if (v < plan->info.n) continue;
     double tms = 0.0;
-    for (int rep = 0; rep < 2; ++rep) {
+    for (int rep = 0; rep < 2; ++rep) {  // the second repetition counts
       DevSys d = plan->P.sys[0];
       d.n_paths = sample;
       d.ids = nullptr;
       HIP_TRY(hipMemcpyAsync(plan->dev.sys.p, &d, sizeof(d), hipMemcpyHostToDevice, ctx->stream));
-      rc = launch_persistent(ctx, plan->dev, plan->P, plan->nmax, w, plan->tol, sample,
-                             e.as<hp_c64>(), st.as<int32_t>(), nullptr, ctx->stream, nullptr);
+      rc = launch_persistent(ctx, plan->dev, plan->P, v, plan->tol, sample, e.as<hp_c64>(),
+                             st.as<int32_t>(), nullptr, ctx->stream, nullptr);
       if (rc) return rc;
       HIP_TRY(hipStreamSynchronize(ctx->stream));
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-      tms = ms;  // second repetition counts (first warms up)
+      tms = ms;
     }
     if (tms < best) {
       best = tms;
-      best_w = w;
+      best_v = v;
     }
   }
-  plan->waves = best_w;
-  tune_store(key, best_w);
+  plan->nmax = best_v;
+  tune_store(key, best_v);
   return HP_OK;
 }
 
@@ -608,8 +616,7 @@ int hp_plan_create(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_t
   pack_append(p->P, f, p->info, gamma, p->info.paths, 0, 0, nullptr);
   if ((rc = p->dev.upload(p->P, ctx->stream))) return rc;
   if ((rc = plan_variant(p.get(), 0))) return rc;
-  size_t lds;
-  if ((rc = variant_lds(ctx, p->P.nl, p->waves, p->P.emax, &lds))) return rc;
+  if ((rc = check_lds(ctx, p->P.lds(p->nmax)))) return rc;
   if (tune && (rc = autotune(p.get()))) return rc;
   *out = p.release();
   return HP_OK;
@@ -622,9 +629,9 @@ void hp_plan_destroy(hp_plan *plan) {
   delete plan;
 }
 
-int hp_plan_set_variant(hp_plan *plan, int32_t waves) {
+int hp_plan_set_variant(hp_plan *plan, int32_t max_n) {
   if (!plan) return fail(HP_E_INVALID_ARG, "plan is NULL");
-  return plan_variant(plan, waves);
+  return plan_variant(plan, max_n);
 }
 
 int hp_plan_track_device(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endpoints,
@@ -640,7 +647,7 @@ int hp_plan_track_device(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_
   hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
   const double t0 = now_ms();
   ctx->last = hp_timing{};
-  ctx->last.waves_per_group = plan->waves;
+  ctx->last.waves_per_group = 1;
   ctx->last.max_n = plan->nmax;
   if (n_paths == 0) return HP_OK;
   int rc;
@@ -652,8 +659,8 @@ int hp_plan_track_device(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_
     d.ids = ids;
     HIP_TRY(hipMemcpyAsync(plan->dev.sys.p, &d, sizeof(d), hipMemcpyHostToDevice, s));
     int groups = 0;
-    if ((rc = launch_persistent(ctx, plan->dev, plan->P, plan->nmax, plan->waves, plan->tol,
-                                n_paths, endpoints, status, stats, s, &groups)))
+    if ((rc = launch_persistent(ctx, plan->dev, plan->P, plan->nmax, plan->tol, n_paths,
+                                endpoints, status, stats, s, &groups)))
       return rc;
     ctx->last.launches = 1;
     ctx->last.groups = groups;
@@ -738,7 +745,6 @@ int hp_track_batch(hp_context *ctx, const hp_system *fs, int32_t n_systems, cons
   }
   const int nmax = nmax_for(P.nl);
   if (nmax < 0) return fail(HP_E_UNSUPPORTED_N, "no kernel variant");
-  const int waves = default_waves(P.nl, nmax);
   DevTables dev;
   if ((rc = dev.upload(P, ctx->stream))) return rc;
   DevBuf e, st, sts;
@@ -749,7 +755,7 @@ int hp_track_batch(hp_context *ctx, const hp_system *fs, int32_t n_systems, cons
     return rc;
   int groups = 0;
   ctx->last = hp_timing{};
-  if ((rc = launch_persistent(ctx, dev, P, nmax, waves, T, total, e.as<hp_c64>(),
+  if ((rc = launch_persistent(ctx, dev, P, nmax, T, total, e.as<hp_c64>(),
                               st.as<int32_t>(), stats ? sts.as<hp_path_stats>() : nullptr,
                               ctx->stream, &groups)))
     return rc;
@@ -763,7 +769,7 @@ int hp_track_batch(hp_context *ctx, const hp_system *fs, int32_t n_systems, cons
   ctx->last.kernel_ms = ms;
   ctx->last.launches = 1;
   ctx->last.groups = groups;
-  ctx->last.waves_per_group = waves;
+  ctx->last.waves_per_group = 1;
   ctx->last.max_n = nmax;
   ctx->last.total_ms = now_ms() - t0;
   return HP_OK;

@@ -11,13 +11,15 @@
 namespace hp {
 
 constexpr int kLanes = 64;  // CDNA wavefront width: one path per lane
-// Per equation, terms are sorted by their number of factors k; the term
-// index array holds kKSlots entries per equation: terms with k factors are
-// [kp[k], kp[k+1]).
+// The terms of a system are sorted by their number of factors k; the kp
+// array holds kKSlots entries per system: the system's terms with k factors
+// are its terms kp[k] .. kp[k+1]-1, counted from its first term.
 constexpr int kKSlots = HP_MAX_N + 2;
 
-// One term c * prod x_v^e, packed for 256-bit scalar loads:
-// w byte 0 = number of factors k (<= HP_MAX_N), bytes 1..k = (v | e << 4).
+// One term c * prod x_v^e of equation i.  On the device the coefficient and
+// the 16-byte factor word live in two arrays (16-byte strides keep the lanes
+// of a group on distinct LDS banks).  Factor word: byte 0 = number of
+// factors k (<= HP_MAX_N), bytes 1..k = (v | e << 4), byte 15 = equation i.
 struct alignas(32) DevTerm {
   double cre, cim;
   uint32_t w[4];
@@ -28,8 +30,10 @@ struct alignas(32) DevTerm {
 struct alignas(16) DevSys {
   int32_t n;          // unknowns
   int32_t emax;       // largest exponent of any variable in any term
-  int32_t eq_base;    // index of this system's first kKSlots block in the kp array
+  int32_t eq_base;    // index of this system's kKSlots block in the kp array
   int32_t root_base;  // index of the first root of unity of this system
+  int32_t term_base;  // index of the first term of this system
+  int32_t n_terms;    // terms of this system (staged in LDS if <= kMaxStagedTerms)
   int32_t deg[HP_MAX_N];       // equation degrees d_i
   int32_t root_off[HP_MAX_N];  // roots of x_i^{d_i} = 1 start at root_base + root_off[i]
   int64_t radix[HP_MAX_N];     // prod_{j<i} d_j
@@ -59,11 +63,9 @@ struct PlainState {
 struct KArgs {
   const DevSys *sys;
   int32_t n_systems;
-  int32_t emax_all;      // LDS power table depth of the launch
-  int32_t nl;            // LDS row stride: largest n of the launch
-  int32_t pad;
-  const DevTerm *terms;
-  const int32_t *eqp;    // kp blocks: absolute term indices, kKSlots per equation
+  const double2 *tcoef;  // term coefficients
+  const uint4 *tmeta;    // term factor words
+  const int32_t *eqp;    // kp blocks: kKSlots term offsets per system
   const double2 *roots;  // roots of unity, (cos, sin)
   unsigned long long *qhead;  // per system queue heads (persistent mode)
   double2 *endpoints;
@@ -75,34 +77,52 @@ struct KArgs {
 
 enum Mode : int32_t { M_IDLE = 0, M_TRACK = 1, M_FINAL = 2 };
 
-// Kernel variants compiled into the library: (n_max, waves per workgroup),
-// i.e. one or two Jacobian rows per wave.
-struct Variant {
-  int nmax, waves;
-};
-constexpr Variant kVariants[] = {{4, 2}, {4, 4}, {8, 4}, {8, 8}, {12, 6}};
+// Kernel variants compiled into the library: the register arrays hold up to
+// n_max unknowns; a system of n unknowns runs on the smallest n_max >= n.
+constexpr int kNmaxVariants[] = {4, 8, 12};
 
-// LDS shared by the Jacobian accumulators (eval) and the pivot row,
-// solution and pivot candidates (solve), for row stride nl.
-__host__ __device__ constexpr size_t lds_union_bytes(int nl, int waves) {
-  size_t acc = (size_t)waves * nl * 16 * kLanes;
-  size_t sol = ((size_t)(2 * nl + 1) * 16 + (size_t)nl * 8) * kLanes;
-  return acc > sol ? acc : sol;
+// LDS layout of a workgroup (one wavefront): a 64-entry refill broadcast,
+// then one region per lane group (floor(64/n) groups plus one spare group
+// for the lanes past the last full group).
+constexpr size_t kCtlBytes = 64 * 8;
+// Fixed part of a group's region, laid out for the n_max of the kernel so
+// that every access is a compile-time offset from one base address; the
+// power table [n][emax] follows it.
+template <int NMAX>
+struct GroupLds {
+  double2 J[NMAX][NMAX + 1];  // Jacobian accumulator of f (rows padded: bank spread)
+  double2 fv[NMAX];       // f values
+  double2 prow[NMAX + 1]; // normalised pivot row, [NMAX] = right-hand side
+  double2 dsol[NMAX];     // solution of the last linear solve
+  double cand[NMAX];      // pivot candidates
+  double red[2 * NMAX];   // reductions
+};
+__host__ __device__ constexpr size_t group_fixed_bytes(int nmax) {
+  return (size_t)16 * ((size_t)nmax * (nmax + 1) + 3 * nmax + 1) + (size_t)8 * 3 * nmax;
 }
-// LDS bytes of a workgroup with `waves` waves, row stride nl (largest n of
-// the launch) and power tables of depth emax.
-inline size_t lds_bytes(int nl, int waves, int emax) {
-  return (size_t)nl * emax * 16 * kLanes + lds_union_bytes(nl, waves) +
-         (size_t)2 * waves * 8 * kLanes + 64 * 8 + 64;
+__host__ __device__ constexpr size_t group_lds_bytes(int nmax, int emax) {
+  return group_fixed_bytes(nmax) + (size_t)16 * nmax * emax;
+}
+static_assert(sizeof(GroupLds<8>) == group_fixed_bytes(8), "layout");
+static_assert(sizeof(GroupLds<12>) == group_fixed_bytes(12), "layout");
+// Term tables up to this size are staged in LDS at kernel start.
+constexpr int kMaxStagedTerms = 512;
+// LDS bytes of a workgroup running a system of n unknowns and n_terms
+// terms on the n_max variant: staged terms (if they fit), then floor(64/n)
+// groups plus one spare group.
+inline size_t staged_term_bytes(int n_terms) {
+  return n_terms <= kMaxStagedTerms ? (size_t)n_terms * 32 : 0;
+}
+inline size_t system_lds_bytes(int nmax, int n, int emax, int n_terms) {
+  return kCtlBytes + staged_term_bytes(n_terms) + (size_t)(kLanes / n + 1) * group_lds_bytes(nmax, emax);
 }
 
 }  // namespace hp
 
 // Kernel launchers (tracker.hip).  Return a hipError_t value.
 extern "C++" {
-int hp_launch_persistent(int nmax, int waves, const hp::KArgs &a, int groups, size_t lds,
-                         void *stream);
-int hp_launch_plain_init(int nmax, const hp::KArgs &a, void *stream);
-int hp_launch_plain_step(int nmax, int waves, const hp::KArgs &a, size_t lds, void *stream);
-int hp_max_groups_per_cu(int nmax, int waves, size_t lds, int *out);
+int hp_launch_persistent(int nmax, const hp::KArgs &a, int groups, size_t lds, void *stream);
+int hp_launch_plain_init(const hp::KArgs &a, void *stream);
+int hp_launch_plain_step(int nmax, const hp::KArgs &a, int groups, size_t lds, void *stream);
+int hp_max_groups_per_cu(int nmax, size_t lds, int *out);
 }
