@@ -452,7 +452,10 @@ int check_lds(hp_context *ctx, size_t lds) {
 // Persistent launch over the systems in `dev` (already uploaded).
 int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, int nmax,
                       const hp_tolerances &tol, int64_t total_paths, hp_c64 *endpoints,
-                      int32_t *status, hp_path_stats *stats, hipStream_t s, int *groups_out) {
+                      int32_t *status, hp_path_stats *stats, hipStream_t s, int *groups_out,
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  if (!e0) e0 = ctx->ev0;
+  if (!e1) e1 = ctx->ev1;
   const size_t lds = P.lds(nmax);
   int rc = check_lds(ctx, lds);
   if (rc) return rc;
@@ -460,7 +463,7 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, int nmax
   HIP_TRY((hipError_t)hp_max_groups_per_cu(nmax, lds, &per_cu));
   if (per_cu < 1) return fail(HP_E_DEVICE, "kernel variant does not fit on a compute unit");
   // enough wavefronts to hold every path once, at most a full device
-  int64_t per_wave = hp::kLanes / std::max(1, P.nl);
+  int64_t per_wave = hp::kLanes / std::max(1, P.nl);  // paths per wavefront
   int64_t want = (total_paths + per_wave - 1) / per_wave;
   int64_t groups = std::min<int64_t>((int64_t)ctx->cus * per_cu, std::max<int64_t>(1, want));
   KArgs a;
@@ -477,9 +480,9 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, int nmax
   a.stats = stats;
   a.tol = dev_tol(tol);
   HIP_TRY(hipMemsetAsync(dev.qhead.p, 0, P.sys.size() * sizeof(unsigned long long), s));
-  HIP_TRY(hipEventRecord(ctx->ev0, s));
+  HIP_TRY(hipEventRecord(e0, s));
   HIP_TRY((hipError_t)hp_launch_persistent(nmax, a, (int)groups, lds, s));
-  HIP_TRY(hipEventRecord(ctx->ev1, s));
+  HIP_TRY(hipEventRecord(e1, s));
   if (groups_out) *groups_out = (int)groups;
   return HP_OK;
 }
@@ -896,6 +899,340 @@ int hp_solve(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_toleran
   ctx->last.kernel_ms = kms;
   ctx->last.total_ms = now_ms() - t0;
   return HP_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Serving: continuous batching over the persistent tracker
+// ---------------------------------------------------------------------------
+//
+// A worker thread owns a stream and an output arena in HBM of at most the
+// budget.  Requests are admitted in arrival order while their regions (path
+// slots of the arena) fit; a request whose outputs exceed the free room gets
+// a region for one chunk of its paths and runs chunk by chunk.
+// Every epoch packs the next chunk of each admitted request into one
+// multi-system persistent launch (one refill queue per chunk), so requests
+// that arrive while others run join at the next epoch and share launches.
+// After an epoch the finished chunks are copied to host memory; a request
+// whose last chunk finished is complete.
+
+namespace {
+
+constexpr int64_t kEpochPaths = 1 << 18;  // paths per epoch over all requests
+constexpr int64_t kMinChunk = 4096;
+
+struct Request {
+  int64_t id = 0;
+  std::vector<int32_t> eq_ptr;
+  std::vector<hp_c64> coeff;
+  std::vector<uint8_t> exps;
+  hp_system sys{};
+  SysInfo info;
+  hp_c64 gamma{};
+  hp_tolerances tol{};
+  double t_submit = 0.0, t_done = 0.0;
+  // host results
+  std::vector<hp_c64> ends;
+  std::vector<int32_t> status;
+  std::vector<hp_path_stats> stats;
+  // progress
+  int64_t next_path = 0;  // first path not yet handed to an epoch
+  int64_t done_paths = 0;
+  // arena region (resident path outputs of one chunk)
+  int64_t region_paths = 0;  // capacity in paths
+  int64_t region_off = -1;   // offset in paths into the arena
+  bool admitted = false, done = false, failed = false;
+};
+
+}  // namespace
+
+struct hp_server {
+  hp_context *ctx = nullptr;
+  size_t budget = 0, resident = 0, peak = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<Request>> pending;
+  std::vector<std::shared_ptr<Request>> active;
+  std::map<int64_t, std::shared_ptr<Request>> all;
+  int64_t next_id = 1;
+  bool stop = false;
+  std::string error;
+  std::thread worker;
+  // arena: paths are slots of (endpoints up to HP_MAX_N, status, stats)
+  DevBuf a_ends, a_status, a_stats;
+  int64_t arena_paths = 0;
+  std::vector<std::pair<int64_t, int64_t>> free_list;  // (offset, length) in paths
+
+  int64_t largest_free() const {
+    int64_t m = 0;
+    for (auto &f : free_list) m = std::max(m, f.second);
+    return m;
+  }
+  int64_t alloc_region(int64_t len) {
+    for (size_t i = 0; i < free_list.size(); ++i) {
+      if (free_list[i].second >= len) {
+        const int64_t off = free_list[i].first;
+        free_list[i].first += len;
+        free_list[i].second -= len;
+        if (free_list[i].second == 0) free_list.erase(free_list.begin() + i);
+        return off;
+      }
+    }
+    return -1;
+  }
+  void free_region(int64_t off, int64_t len) {
+    free_list.push_back({off, len});
+    std::sort(free_list.begin(), free_list.end());
+    std::vector<std::pair<int64_t, int64_t>> merged;
+    for (auto &f : free_list) {
+      if (!merged.empty() && merged.back().first + merged.back().second == f.first)
+        merged.back().second += f.second;
+      else
+        merged.push_back(f);
+    }
+    free_list.swap(merged);
+  }
+};
+
+namespace {
+
+size_t slot_bytes() { return (size_t)HP_MAX_N * sizeof(hp_c64) + sizeof(int32_t) + sizeof(hp_path_stats); }
+
+// Admits pending requests in arrival order while the arena has room (called
+// with mu held).  A request gets a region for all of its paths if one is
+// free, else (when it is larger than the free room) a region of at least
+// kMinChunk paths that it fills chunk by chunk.
+void admit(hp_server *S) {
+  while (!S->pending.empty()) {
+    auto &R = S->pending.front();
+    int64_t want = std::min<int64_t>(R->info.paths, S->arena_paths);
+    const int64_t room = S->largest_free();
+    if (room < want) {
+      if (room < std::min<int64_t>(want, kMinChunk)) break;
+      want = room;
+    }
+    const int64_t off = S->alloc_region(want);
+    if (off < 0) break;
+    R->region_paths = want;
+    R->region_off = off;
+    R->admitted = true;
+    S->resident += (size_t)want * slot_bytes();
+    S->peak = std::max(S->peak, S->resident);
+    S->active.push_back(R);
+    S->pending.pop_front();
+  }
+}
+
+int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
+  hp_context *ctx = S->ctx;
+  // chunk sizes: share the epoch among the admitted requests
+  // one launch has one tolerance set: take the requests that share the
+  // oldest active request's tolerances; the others wait for a later epoch
+  const hp_tolerances tol = batch[0]->tol;
+  size_t same = 0;
+  for (auto &R : batch) same += std::memcmp(&R->tol, &tol, sizeof(tol)) == 0;
+  const int64_t share = std::max<int64_t>(kMinChunk, kEpochPaths / (int64_t)same);
+  Packed P;
+  std::vector<int64_t> chunk(batch.size(), 0);
+  int64_t total = 0;
+  for (size_t i = 0; i < batch.size(); ++i) {
+    Request &R = *batch[i];
+    if (std::memcmp(&R.tol, &tol, sizeof(tol)) != 0) continue;
+    chunk[i] = std::min(std::min(R.info.paths - R.next_path, R.region_paths), share);
+    // chunk outputs go to the request's arena region; slots are HP_MAX_N wide
+    pack_append(P, &R.sys, R.info, R.gamma, chunk[i], R.region_off,
+                R.region_off * HP_MAX_N, nullptr);
+    P.sys.back().id_base = R.next_path;
+    // endpoints of a chunk are packed with stride n inside its region
+    total += chunk[i];
+  }
+  const int nmax = nmax_for(P.nl);
+  DevTables dev;
+  int rc = dev.upload(P, S->stream);
+  if (rc) return rc;
+  rc = launch_persistent(ctx, dev, P, nmax, tol, total, S->a_ends.as<hp_c64>(),
+                         S->a_status.as<int32_t>(), S->a_stats.as<hp_path_stats>(), S->stream,
+                         nullptr, S->ev0, S->ev1);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  // copy finished chunks to the requests' host results
+  for (size_t i = 0; i < batch.size(); ++i) {
+    Request &R = *batch[i];
+    const int64_t c = chunk[i], p0 = R.next_path, n = R.info.n;
+    if (c == 0) continue;
+    HIP_TRY(hipMemcpyAsync(R.ends.data() + p0 * n, S->a_ends.as<hp_c64>() + R.region_off * HP_MAX_N,
+                           (size_t)c * n * sizeof(hp_c64), hipMemcpyDeviceToHost, S->stream));
+    HIP_TRY(hipMemcpyAsync(R.status.data() + p0, S->a_status.as<int32_t>() + R.region_off,
+                           (size_t)c * sizeof(int32_t), hipMemcpyDeviceToHost, S->stream));
+    HIP_TRY(hipMemcpyAsync(R.stats.data() + p0, S->a_stats.as<hp_path_stats>() + R.region_off,
+                           (size_t)c * sizeof(hp_path_stats), hipMemcpyDeviceToHost, S->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  for (size_t i = 0; i < batch.size(); ++i) {
+    batch[i]->next_path += chunk[i];
+    batch[i]->done_paths += chunk[i];
+  }
+  return HP_OK;
+}
+
+void worker_main(hp_server *S) {
+  (void)hipSetDevice(S->ctx->device);
+  for (;;) {
+    std::vector<std::shared_ptr<Request>> batch;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_work.wait(lk, [&] { return S->stop || !S->pending.empty() || !S->active.empty(); });
+      if (S->stop) {
+        // requests still queued or running end as failed, so waiters return
+        for (auto &R : S->pending) R->done = R->failed = true;
+        for (auto &R : S->active) R->done = R->failed = true;
+        S->error = "server destroyed before the request finished";
+        S->cv_done.notify_all();
+        return;
+      }
+      admit(S);
+      batch = S->active;
+    }
+    if (batch.empty()) continue;
+    const int rc = run_epoch(S, batch);
+    const double now = now_ms();
+    std::lock_guard<std::mutex> lk(S->mu);
+    std::vector<std::shared_ptr<Request>> keep;
+    for (auto &R : S->active) {
+      if (rc != HP_OK) {
+        R->failed = true;
+        S->error = g_err;
+      }
+      if (rc != HP_OK || R->done_paths >= R->info.paths) {
+        R->done = true;
+        R->t_done = now;
+        S->resident -= (size_t)R->region_paths * slot_bytes();
+        S->free_region(R->region_off, R->region_paths);
+      } else {
+        keep.push_back(R);
+      }
+    }
+    S->active.swap(keep);
+    S->cv_done.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int hp_server_create(hp_context *ctx, size_t hbm_budget_bytes, hp_server **out) {
+  if (!ctx || !out) return fail(HP_E_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  if (hbm_budget_bytes < slot_bytes() * kMinChunk)
+    return fail(HP_E_BUDGET, "budget below one chunk of " + std::to_string(kMinChunk) + " paths");
+  HIP_TRY(hipSetDevice(ctx->device));
+  std::unique_ptr<hp_server> S(new hp_server());
+  S->ctx = ctx;
+  S->budget = hbm_budget_bytes;
+  // arena sized by the budget (in path slots of the widest system)
+  S->arena_paths = (int64_t)(hbm_budget_bytes / slot_bytes());
+  int rc;
+  if ((rc = S->a_ends.alloc((size_t)S->arena_paths * HP_MAX_N * sizeof(hp_c64)))) return rc;
+  if ((rc = S->a_status.alloc((size_t)S->arena_paths * sizeof(int32_t)))) return rc;
+  if ((rc = S->a_stats.alloc((size_t)S->arena_paths * sizeof(hp_path_stats)))) return rc;
+  S->free_list.push_back({0, S->arena_paths});
+  HIP_TRY(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreate(&S->ev0));
+  HIP_TRY(hipEventCreate(&S->ev1));
+  hp_server *raw = S.get();
+  S->worker = std::thread(worker_main, raw);
+  *out = S.release();
+  return HP_OK;
+}
+
+int hp_server_submit(hp_server *S, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
+                     int64_t *req_id) {
+  if (!S || !req_id) return fail(HP_E_INVALID_ARG, "NULL argument");
+  auto R = std::make_shared<Request>();
+  int rc = check_system(f, R->info);
+  if (rc) return rc;
+  if ((rc = check_tol(tol))) return rc;
+  if (!std::isfinite(gamma.re) || !std::isfinite(gamma.im) || (gamma.re == 0 && gamma.im == 0))
+    return fail(HP_E_INVALID_ARG, "gamma must be finite and nonzero");
+  const int n = f->n;
+  {
+    const size_t lds = hp::system_lds_bytes(nmax_for(n), n, R->info.emax, f->n_terms);
+    if ((rc = check_lds(S->ctx, lds))) return rc;
+  }
+  R->eq_ptr.assign(f->eq_ptr, f->eq_ptr + n + 1);
+  R->coeff.assign(f->coeff, f->coeff + f->n_terms);
+  R->exps.assign(f->exps, f->exps + (size_t)f->n_terms * n);
+  R->sys = hp_system{n, f->n_terms, R->eq_ptr.data(), R->coeff.data(), R->exps.data()};
+  R->gamma = gamma;
+  if (tol) R->tol = *tol;
+  else hp_default_tolerances(&R->tol);
+  R->ends.resize((size_t)R->info.paths * n);
+  R->status.resize(R->info.paths);
+  R->stats.resize(R->info.paths);
+  R->t_submit = now_ms();
+  std::lock_guard<std::mutex> lk(S->mu);
+  R->id = S->next_id++;
+  S->all[R->id] = R;
+  S->pending.push_back(R);
+  *req_id = R->id;
+  S->cv_work.notify_one();
+  return HP_OK;
+}
+
+int hp_server_poll(hp_server *S, int64_t req_id, int32_t *done) {
+  if (!S || !done) return fail(HP_E_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->all.find(req_id);
+  if (it == S->all.end()) return fail(HP_E_INVALID_ARG, "unknown request id");
+  *done = it->second->done ? 1 : 0;
+  return HP_OK;
+}
+
+int hp_server_wait(hp_server *S, int64_t req_id, hp_c64 *endpoints, int32_t *status,
+                   hp_path_stats *stats, double *latency_ms) {
+  if (!S) return fail(HP_E_INVALID_ARG, "NULL server");
+  std::shared_ptr<Request> R;
+  {
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->all.find(req_id);
+    if (it == S->all.end()) return fail(HP_E_INVALID_ARG, "unknown request id");
+    R = it->second;
+    S->cv_done.wait(lk, [&] { return R->done; });
+    S->all.erase(it);
+    if (R->failed) return fail(HP_E_DEVICE, "request failed: " + S->error);
+  }
+  if (endpoints) std::memcpy(endpoints, R->ends.data(), R->ends.size() * sizeof(hp_c64));
+  if (status) std::memcpy(status, R->status.data(), R->status.size() * sizeof(int32_t));
+  if (stats) std::memcpy(stats, R->stats.data(), R->stats.size() * sizeof(hp_path_stats));
+  if (latency_ms) *latency_ms = R->t_done - R->t_submit;
+  return HP_OK;
+}
+
+int hp_server_peak_bytes(hp_server *S, size_t *out) {
+  if (!S || !out) return fail(HP_E_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  *out = S->peak;
+  return HP_OK;
+}
+
+void hp_server_destroy(hp_server *S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    S->cv_work.notify_all();
+  }
+  if (S->worker.joinable()) S->worker.join();
+  (void)hipSetDevice(S->ctx->device);
+  if (S->stream) (void)hipStreamSynchronize(S->stream);
+  if (S->ev0) (void)hipEventDestroy(S->ev0);
+  if (S->ev1) (void)hipEventDestroy(S->ev1);
+  if (S->stream) (void)hipStreamDestroy(S->stream);
+  delete S;
 }
 
 }  // extern "C"

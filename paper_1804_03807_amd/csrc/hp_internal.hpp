@@ -41,7 +41,8 @@ struct alignas(16) DevSys {
   int64_t n_paths;             // queue length of this system
   int64_t out_path_base;       // first status/stats index of this system
   int64_t out_x_base;          // first endpoint (hp_c64) index of this system
-  const int64_t *ids;          // queue index -> path id (nullptr: identity)
+  const int64_t *ids;          // queue index -> path id (nullptr: id_base + index)
+  int64_t id_base;
 };
 
 struct DevTol {

@@ -98,7 +98,7 @@ struct Tracker {
   int nterms;
   const int32_t *kp;  // kKSlots offsets: terms with k factors are terms[kp[k] .. kp[k+1])
   cd gamma;
-  long long npaths, out_path_base, out_x_base;
+  long long npaths, out_path_base, out_x_base, id_base;
   const long long *ids;
   // ---- lane role ----
   int grp, r;   // group (path slot) and row / unknown index within it
@@ -159,6 +159,7 @@ struct Tracker {
     out_path_base = sp->out_path_base;
     out_x_base = sp->out_x_base;
     ids = (const long long *)sp->ids;
+    id_base = sp->id_base;
     grp = lane / n;  // lanes past the last full group form a spare group
     r = lane - grp * n;
     leader = (r == 0) && grp < ngroups;
@@ -373,7 +374,7 @@ struct Tracker {
   // ------------------------------------------------------------ start path
   __device__ __forceinline__ void start_path(long long q) {
     qidx = q;
-    const long long pid = ids ? ids[q] : q;
+    const long long pid = ids ? ids[q] : id_base + q;
     const long long kk = (pid / sp->radix[r]) % sp->deg[r];
     const double2 z = a.roots[sp->root_base + sp->root_off[r] + (int)kk];
     x0 = {z.x, z.y};
@@ -588,7 +589,7 @@ __global__ void __launch_bounds__(64) k_plain_init(KArgs a) {
   const long long q = (long long)blockIdx.x * 64 + threadIdx.x;
   if (q >= sd->n_paths) return;
   const long long P = a.ps.P;
-  const long long pid = sd->ids ? sd->ids[q] : q;
+  const long long pid = sd->ids ? sd->ids[q] : sd->id_base + q;
   for (int j = 0; j < sd->n; ++j) {
     long long kk = (pid / sd->radix[j]) % sd->deg[j];
     a.ps.x0[j * P + q] = a.roots[sd->root_base + sd->root_off[j] + (int)kk];

@@ -1,0 +1,151 @@
+"""GPU tests of the serving loop (hp_server_*): continuous batching of solve
+requests of different sizes, admitted by HBM budget.
+
+* every request's result in the mix equals its result alone (the same
+  batched tracker on its own), endpoint by endpoint within 1e-8 relative and
+  with identical statuses;
+* a request whose outputs exceed the budget is tracked chunk by chunk and
+  still equals the whole-system result; the arena never exceeds the budget;
+* sampled paths of mixed requests match the CPU oracle."""
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from parity import compare_paths
+
+pytestmark = pytest.mark.gpu
+
+NTHREADS = min(16, os.cpu_count() or 1)
+SLOT_BYTES = 12 * 16 + 4 + 40  # endpoint slot of the widest system + status + stats
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1804_03807_amd as hp
+    c = hp.Context(0)
+    yield c
+    c.close()
+
+
+def small_requests(count, max_paths):
+    out = []
+    rid = 0
+    while len(out) < count:
+        s, g = W.serving_request(rid)
+        if s.bezout() <= max_paths:
+            out.append((rid, s, g))
+        rid += 1
+    return out
+
+
+def assert_same(res, ref, what):
+    """res, ref: (endpoints, status, stats) of the same request."""
+    hard, flips = compare_paths(*res, *ref)
+    assert len(hard) == 0 and len(flips) == 0, f"{what}: paths {hard[:8]} {flips[:8]} differ"
+
+
+def test_alone_equals_mix(ctx):
+    import paper_1804_03807_amd as hp
+    reqs = small_requests(12, 6000)
+    log("requests", [(r, s.name, s.bezout()) for r, s, _ in reqs])
+    alone = {r: ctx.track_paths(s, g) for r, s, g in reqs}
+    srv = hp.Server(ctx, 1 << 30)
+    try:
+        ids = [(r, srv.submit(s, g)) for r, s, g in reqs]
+        bitwise = 0
+        for r, q in ids:
+            e, st, sts, lat = srv.wait(q, stats=True)
+            assert lat > 0
+            assert_same((e, st, sts), alone[r], f"request {r}")
+            bitwise += int(np.array_equal(e, alone[r][0]))
+        log(f"bitwise-identical requests: {bitwise}/{len(ids)}")
+        assert srv.peak_bytes() <= 1 << 30
+    finally:
+        srv.close()
+
+
+def test_arrivals_during_work_overlap(ctx):
+    """Requests submitted from another thread while earlier ones run; all
+    complete with the alone result."""
+    import paper_1804_03807_amd as hp
+    reqs = small_requests(24, 6000)
+    alone = {r: ctx.track_paths(s, g) for r, s, g in reqs}
+    arr = W.poisson_arrivals(len(reqs), rate=200.0)
+    srv = hp.Server(ctx, 1 << 30)
+    ids = {}
+    try:
+        def producer():
+            t0 = time.perf_counter()
+            for (r, s, g), ta in zip(reqs, arr):
+                while time.perf_counter() - t0 < ta:
+                    time.sleep(0.0005)
+                ids[r] = srv.submit(s, g)
+
+        th = threading.Thread(target=producer)
+        th.start()
+        th.join()
+        lats = []
+        for r, s, g in reqs:
+            e, st, sts, lat = srv.wait(ids[r], stats=True)
+            lats.append(lat)
+            assert_same((e, st, sts), alone[r], f"request {r}")
+        log(f"latency ms p50={np.percentile(lats, 50):.2f} p99={np.percentile(lats, 99):.2f}")
+    finally:
+        srv.close()
+
+
+def test_over_budget_request_is_chunked(ctx):
+    """Budget holds ~8.9k path slots; cyclic-8 (40320 paths) must run in
+    chunks beside a small request and equal the whole-system result."""
+    import paper_1804_03807_amd as hp
+    wl = W.cyclic8()
+    sys8, g8 = wl.systems[0], complex(wl.gammas[0])
+    ref8 = ctx.track_paths(sys8, g8)
+    (r1, s1, g1), = small_requests(1, 1000)
+    ref1 = ctx.track_paths(s1, g1)
+    budget = 2 * 1000 * 1000
+    srv = hp.Server(ctx, budget)
+    try:
+        q8 = srv.submit(sys8, g8)
+        q1 = srv.submit(s1, g1)
+        e, st, sts, _ = srv.wait(q8, stats=True)
+        assert_same((e, st, sts), ref8, "cyclic8 chunked")
+        e, st, sts, _ = srv.wait(q1, stats=True)
+        assert_same((e, st, sts), ref1, "small request beside chunks")
+        peak = srv.peak_bytes()
+        log(f"peak resident bytes {peak} budget {budget}")
+        assert 0 < peak <= budget
+    finally:
+        srv.close()
+
+
+def test_budget_too_small_rejected(ctx):
+    import paper_1804_03807_amd as hp
+    with pytest.raises(hp.HomotopyError):
+        hp.Server(ctx, 1024)
+
+
+def test_mix_matches_oracle_sample(ctx):
+    import paper_1804_03807_amd as hp
+    reqs = small_requests(6, 6000)
+    srv = hp.Server(ctx, 1 << 30)
+    try:
+        ids = [(srv.submit(s, g), s, g) for _, s, g in reqs]
+        for q, s, g in ids:
+            e, st, sts, _ = srv.wait(q, stats=True)
+            sample = W.stride_sample(s.bezout(), 64)
+            ref = oracle.track_paths(s, g, path_ids=sample, n_threads=NTHREADS)
+            hard, _ = compare_paths(e[sample], st[sample], sts[sample], *ref)
+            assert len(hard) == 0, s.name
+    finally:
+        srv.close()
