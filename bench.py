@@ -24,6 +24,21 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 
+# HBM bytes per k_persistent launch on the cyclic-8 workload from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each
+# scaled by what the counter reads for a 256 MiB device copy (FETCH_SIZE
+# reads half the copied bytes, WRITE_SIZE all of them).  Valid only for the
+# kernel sources they were taken on; reported as null once those change.
+TRAFFIC_PROFILE = {
+    "workload": "cyclic8",
+    "sources_sha256": {
+        "tracker.hip": "4e23c868f58586e8d6706726d8d6c6a14e661900ba1a779b50a040fc36791320",
+        "hp_internal.hpp": "d750f77139f0549f46d32e7b4a8172ee4d59a0a200b3346b9cb175167fa178f2",
+    },
+    "fetch_kib": 243.5, "fetch_scale": 262144 / 131089,
+    "write_kib": 8467.84375, "write_scale": 262144 / 262144,
+}
+
 WORKLOADS = {
     "cyclic8": ("cyclic8: random unit-circle coefficients on the cyclic 8-roots supports, "
                 "40320 total-degree paths, complex fp64, seed 2"),
@@ -42,6 +57,70 @@ def load_workload(name):
     if name == "dense5":
         return W.dense_small()
     raise SystemExit(f"unknown workload {name}")
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch from the counter profile, or None when the kernel
+    sources differ from the profiled ones or the workload is another one."""
+    import hashlib
+    T = TRAFFIC_PROFILE
+    if workload != T["workload"]:
+        return None
+    csrc = os.path.join(ROOT, "paper_1804_03807_amd", "csrc")
+    for name, digest in T["sources_sha256"].items():
+        with open(os.path.join(csrc, name), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != digest:
+                return None
+    return T["fetch_kib"] * 1024 * T["fetch_scale"] + T["write_kib"] * 1024 * T["write_scale"]
+
+
+def serving_run(ctx, n_requests, budget_bytes, load=0.8):
+    """Serving sample: the first n_requests of the seeded request stream.
+    Saturated pass (all submitted at once) gives the saturated request rate;
+    then a Poisson stream at load x that rate; latency = completion - arrival."""
+    import threading
+    import paper_1804_03807_amd as hp
+    import workloads as W
+    reqs = [W.serving_request(i) for i in range(n_requests)]
+    paths = sum(s.bezout() for s, _ in reqs)
+
+    def run(arrivals):
+        srv = hp.Server(ctx, budget_bytes)
+        ids = [None] * len(reqs)
+        t0 = time.perf_counter()
+
+        def producer():
+            for i, ((s, g), ta) in enumerate(zip(reqs, arrivals)):
+                while time.perf_counter() - t0 < ta:
+                    time.sleep(0.0002)
+                ids[i] = srv.submit(s, g)
+
+        th = threading.Thread(target=producer)
+        th.start()
+        th.join()
+        lat, conv = [], 0
+        for q in ids:
+            _, st, _, ms = srv.wait(q)
+            lat.append(ms)
+            conv += int((st == 0).sum())
+        makespan = time.perf_counter() - t0
+        peak = srv.peak_bytes()
+        srv.close()
+        return np.asarray(lat), makespan, peak, conv
+
+    lat_sat, span_sat, _, _ = run(np.zeros(len(reqs)))
+    rate_sat = len(reqs) / span_sat
+    lam = load * rate_sat
+    lat, span, peak, conv = run(W.poisson_arrivals(len(reqs), lam))
+    return {"requests": len(reqs), "paths": paths, "converged": conv,
+            "sample": f"request ids 0..{len(reqs) - 1} of the seeded stream (seed 4)",
+            "saturated_requests_per_s": rate_sat, "lambda_requests_per_s": lam,
+            "paths_per_s": paths / span, "makespan_s": span,
+            "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                           "p99": float(np.percentile(lat, 99))},
+            "saturated_latency_ms": {"p50": float(np.percentile(lat_sat, 50)),
+                                     "p99": float(np.percentile(lat_sat, 99))},
+            "hbm_budget_bytes": budget_bytes, "peak_resident_bytes": peak}
 
 
 def cpu_baseline(system, gamma, seconds_target=15.0):
@@ -76,6 +155,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tune", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=32,
+                    help="requests in the serving sample (0: skip)")
+    ap.add_argument("--serving-budget-gib", type=float, default=16.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -159,7 +241,8 @@ def main():
                        "p99": float(np.percentile(times, 99))},
         "kernel_ms_mean": kmean,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic(args.workload),
                      "flops_per_launch": flop},
     }
     if not resid_ok:
@@ -174,6 +257,10 @@ def main():
         out["plain"] = {"value": P / dt, "unit": "paths/s", "launches": tp["launches"],
                         "ms": dt * 1e3}
         out["batched_over_plain"] = value / (P / dt)
+
+    if args.serving_requests > 0:
+        out["serving"] = serving_run(ctx, args.serving_requests,
+                                     int(args.serving_budget_gib * (1 << 30)))
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(system, gamma)

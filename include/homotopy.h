@@ -116,8 +116,8 @@ typedef struct {
   double kernel_ms;   /* device time of the tracking kernels (HIP events)     */
   double total_ms;    /* host wall time of the whole call                     */
   int64_t launches;   /* tracking kernel launches                             */
-  int32_t waves_per_group; /* kernel variant used (rows of J split over waves) */
-  int32_t max_n;      /* compiled size bound of the variant used              */
+  int32_t waves_per_group; /* wavefronts per workgroup (1 in every variant)  */
+  int32_t max_n;      /* compiled size bound n_max of the variant used        */
   int32_t groups;     /* workgroups launched (persistent: resident groups)    */
   int32_t pad;
 } hp_timing;
@@ -152,8 +152,11 @@ int hp_track_paths(hp_context *ctx, const hp_system *f, const hp_system *g, cons
 int hp_plan_create(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
                    int32_t tune, hp_plan **out);
 void hp_plan_destroy(hp_plan *plan);
-/* Forces the kernel variant (waves per workgroup: 1, 2, 4 or 8; 0 = automatic). */
-int hp_plan_set_variant(hp_plan *plan, int32_t waves_per_group);
+/* Forces the kernel variant: the compiled size bound n_max (4, 8 or 12, at
+ * least the system's n; 0 = the smallest that fits).  HP_E_INVALID_ARG for
+ * any other value.  The autotuner of hp_plan_create chooses among the same
+ * variants by timing them on a sample of the plan's paths. */
+int hp_plan_set_variant(hp_plan *plan, int32_t max_n);
 
 /* Device-memory call: tracks the paths whose ids are ids[0..n_paths-1]
  * (device int64 array; NULL means ids 0..n_paths-1).  Outputs are device
@@ -190,11 +193,16 @@ int64_t hp_find_duplicates(int32_t n, int64_t n_paths, const hp_c64 *endpoints,
 int hp_solve(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
              hp_c64 *endpoints, int32_t *status, hp_path_stats *stats, int64_t *remaining_pairs);
 
-/* Serving: a request loop with continuous batching.  Requests (one system
- * each, all its total-degree paths) are admitted while the resident path
- * state of admitted requests fits in hbm_budget_bytes; larger requests are
- * split into path chunks.  Work of requests admitted while others run
- * overlaps on the device. */
+/* Serving: a request loop with continuous batching (a worker thread with its
+ * own stream).  The server allocates an output arena of at most
+ * hbm_budget_bytes: path slots of HP_MAX_N endpoint coordinates + status +
+ * stats (236 B each).  Requests (one system each, all its total-degree
+ * paths) are admitted in arrival order while their slot regions fit;  a
+ * request larger than the free room gets a region of at least 4096 slots
+ * and runs chunk by chunk.  Each round of work packs the next chunk of every
+ * admitted request (same tolerances) into one multi-system persistent
+ * launch, so requests that arrive while others run share the following
+ * launches.  HP_E_BUDGET if the budget holds fewer than 4096 slots. */
 int hp_server_create(hp_context *ctx, size_t hbm_budget_bytes, hp_server **out);
 /* Queues a request; the system is copied.  *req_id receives its id. */
 int hp_server_submit(hp_server *srv, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
@@ -206,7 +214,10 @@ int hp_server_poll(hp_server *srv, int64_t req_id, int32_t *done);
  * *latency_ms (nullable) receives completion time minus submission time. */
 int hp_server_wait(hp_server *srv, int64_t req_id, hp_c64 *endpoints, int32_t *status,
                    hp_path_stats *stats, double *latency_ms);
-/* Peak resident path-state bytes admitted so far. */
+/* Stops the worker; requests not yet finished end as failed.  No other
+ * thread may be inside a call on srv (hp_server_wait included) while it
+ * runs. */
+/* Peak bytes of arena slots held by admitted requests so far (<= budget). */
 int hp_server_peak_bytes(hp_server *srv, size_t *out);
 void hp_server_destroy(hp_server *srv);
 
