@@ -9,11 +9,11 @@
  *
  * with the total-degree start system g_i(x) = x_i^{d_i} - 1 (d_i the degree
  * of f_i) and a random complex constant gamma.  The paths are independent of
- * each other, which is what makes the tracking "pleasingly parallel" and
- * lets the work be handed out dynamically (paper: Section 1, the problem
- * statement and the work crew model; Section 2.2, tracking the paths of a
- * start system with dynamic load balancing; Section 3.2, Theorem 3.1 on the
- * speedup of tracking n paths with p workers).  Each endpoint comes back
+ * each other, which makes the tracking embarrassingly parallel and lets
+ * the work be handed out dynamically (paper: Section 1, the problem
+ * statement and the work crew model; end of Section 2.1, tracking the paths
+ * of a start system with dynamic load balancing; Section 3.2, Theorem 3.2 on
+ * the speedup of tracking n paths with p workers).  Each endpoint comes back
  * classified, the finite / "at infinity" split of Section 3.1 (Figure 3).
  *
  * The tracking step itself is not given in the paper; the library follows

@@ -8,9 +8,9 @@
  * What it computes: the paths of the homotopy
  *     H(x,t) = gamma (1-t) g(x) + t f(x),   t in [0,1],
  * from the solutions of a start system g to the solutions of a square
- * polynomial system f.  The paper (Section 1 and Section 2.2) states only
- * that these paths are tracked independently of each other with no
- * communication ("pleasingly parallel"), with threads of a work crew pulling
+ * polynomial system f.  The paper (Section 1 and the end of Section 2.1)
+ * states only that these paths are tracked independently of each other
+ * with no communication, with threads of a work crew pulling
  * jobs from a queue whose next-job pointer is guarded (Section 1).  It gives
  * no predictor, corrector or step control; the steps below are the reading
  * this project adopts (RK4 predictor on the Davidenko equation, Newton

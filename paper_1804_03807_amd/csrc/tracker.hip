@@ -9,7 +9,7 @@
 // order the LDS accesses of the single wavefront.
 //
 // Method.  H(x,t) = gamma(1-t) g(x) + t f(x), g_i = x_i^{d_i} - 1 (paper:
-// Section 1 and Section 2.2 for independent paths and dynamic load
+// Section 1 and the end of Section 2.1 for independent paths and dynamic load
 // balancing).  f and its Jacobian are evaluated by reverse-mode algorithmic
 // differentiation of each monomial: prefix products with the coefficient
 // folded in, then a backward sweep of suffix products.  The host sorts all
