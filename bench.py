@@ -151,7 +151,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cyclic8", choices=sorted(WORKLOADS))
-    ap.add_argument("--waves", type=int, default=0, help="force a kernel variant (waves/group)")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="force a kernel variant code (homotopy.h, hp_plan_set_variant)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tune", action="store_true")
@@ -184,8 +185,8 @@ def main():
     P = system.bezout()
     ctx = hp.Context(0)
     plan = ctx.plan(system, gamma, tune=args.tune)
-    if args.waves:
-        plan.set_variant(args.waves)
+    if args.variant:
+        plan.set_variant(args.variant)
     e, st, sts = plan.outputs(P)
     stream = torch.cuda.current_stream()
 
@@ -232,7 +233,7 @@ def main():
         "config": {"workload": WORKLOADS[args.workload], "paths": P, "n": system.n,
                    "mode": "batched (persistent, device refill queue)",
                    "kernel_variant": {"max_n": timing["max_n"],
-                                      "waves_per_group": timing["waves_per_group"],
+                                      "paths_per_wave": timing["paths_per_wave"], "code": timing["variant"],
                                       "groups": timing["groups"]}},
         "converged": int(conv.sum()),
         "not_converged": int((~conv).sum()),

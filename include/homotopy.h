@@ -116,10 +116,10 @@ typedef struct {
   double kernel_ms;   /* device time of the tracking kernels (HIP events)     */
   double total_ms;    /* host wall time of the whole call                     */
   int64_t launches;   /* tracking kernel launches                             */
-  int32_t waves_per_group; /* wavefronts per workgroup (1 in every variant)  */
+  int32_t paths_per_wave; /* paths one wavefront holds at a time          */
   int32_t max_n;      /* compiled size bound n_max of the variant used        */
-  int32_t groups;     /* workgroups launched (persistent: resident groups)    */
-  int32_t pad;
+  int32_t groups;     /* workgroups (one wavefront each) launched             */
+  int32_t variant;    /* kernel variant code (see hp_plan_set_variant)        */
 } hp_timing;
 
 typedef struct hp_context hp_context;
@@ -152,11 +152,21 @@ int hp_track_paths(hp_context *ctx, const hp_system *f, const hp_system *g, cons
 int hp_plan_create(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
                    int32_t tune, hp_plan **out);
 void hp_plan_destroy(hp_plan *plan);
-/* Forces the kernel variant: the compiled size bound n_max (4, 8 or 12, at
- * least the system's n; 0 = the smallest that fits).  HP_E_INVALID_ARG for
- * any other value.  The autotuner of hp_plan_create chooses among the same
- * variants by timing them on a sample of the plan's paths. */
-int hp_plan_set_variant(hp_plan *plan, int32_t max_n);
+/* Forces the kernel variant.  Two kernel families are compiled:
+ *   n_max = 4, 8, 12       group kernels: n lanes of a wavefront per path
+ *                          (lane r owns equation r), floor(64/n) paths, for
+ *                          any n <= n_max;
+ *   100 + n (n = 1..8)     lane kernels: one path per lane, 64 paths per
+ *                          wavefront, Jacobian in LDS, compiled for exactly
+ *                          this n;
+ *   200 + n (n = 7, 8)     lane kernels with 32 paths per wavefront (half the
+ *                          LDS, for systems whose power table is large).
+ * The variant must fit the system's n and its LDS must fit the device; 0
+ * selects the default (the narrowest group kernel).  HP_E_INVALID_ARG for other values,
+ * HP_E_UNSUPPORTED_N if the LDS does not fit.  The autotuner of
+ * hp_plan_create times every candidate on a sample of the plan's paths and
+ * caches the choice per system shape (file named by $HP_TUNE_CACHE). */
+int hp_plan_set_variant(hp_plan *plan, int32_t variant);
 
 /* Device-memory call: tracks the paths whose ids are ids[0..n_paths-1]
  * (device int64 array; NULL means ids 0..n_paths-1).  Outputs are device

@@ -104,7 +104,7 @@ class Context:
     def last_timing(self) -> dict:
         t = HpTiming()
         check(self._L.hp_last_timing(self.handle, ctypes.byref(t)))
-        return {k: getattr(t, k) for k, _ in HpTiming._fields_ if k != "pad"}
+        return {k: getattr(t, k) for k, _ in HpTiming._fields_}
 
     def track_paths(self, system, gamma, n_paths=None, tol=None, mode="batched", stats=True):
         """Tracks total-degree paths 0..n_paths-1 (host arrays in and out).
@@ -184,8 +184,9 @@ class Plan:
         except Exception:
             pass
 
-    def set_variant(self, waves_per_group: int):
-        check(self._L.hp_plan_set_variant(self.handle, int(waves_per_group)))
+    def set_variant(self, variant: int):
+        """Kernel variant code (see hp_plan_set_variant in homotopy.h)."""
+        check(self._L.hp_plan_set_variant(self.handle, int(variant)))
 
     def outputs(self, n_paths, stats=True, device="cuda"):
         """Device tensors (endpoints as float64 [P, n, 2], status, stats bytes)."""

@@ -47,8 +47,8 @@ class HpTolerances(ctypes.Structure):
 
 class HpTiming(ctypes.Structure):
     _fields_ = [("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
-                ("launches", ctypes.c_int64), ("waves_per_group", ctypes.c_int32),
-                ("max_n", ctypes.c_int32), ("groups", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("launches", ctypes.c_int64), ("paths_per_wave", ctypes.c_int32),
+                ("max_n", ctypes.c_int32), ("groups", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
 
 STATS_DTYPE = np.dtype([("steps", np.int32), ("rejections", np.int32),

@@ -172,7 +172,7 @@ struct Packed {
   std::vector<int32_t> kp;
   std::vector<double2> roots;
   std::vector<DevSys> sys;
-  int nl = 1, emax = 1, kmax = 0;
+  int nl = 1, nmin = HP_MAX_N, emax = 1, kmax = 0;
   // workgroup LDS bytes of the n_max variant: largest over the systems
   size_t lds(int nmax) const {
     size_t b = 0;
@@ -255,6 +255,7 @@ void pack_append(Packed &P, const hp_system *f, const SysInfo &info, hp_c64 gamm
   P.kp.insert(P.kp.end(), kp, kp + hp::kKSlots);
   P.sys.push_back(d);
   P.nl = std::max(P.nl, n);
+  P.nmin = std::min(P.nmin, n);
   P.emax = std::max(P.emax, info.emax);
   P.kmax = std::max(P.kmax, info.kmax);
 }
@@ -302,10 +303,52 @@ int nmax_for(int n) {
   return -1;
 }
 
-bool is_variant(int nmax) {
+// Kernel variant codes: n_max (4, 8, 12) for the group kernels (n lanes per
+// path), 100 + n_max for the lane kernels with 64 paths per wavefront and
+// 200 + n_max for those with 32.
+struct Kv {
+  int code = 0;
+  bool lanes = false;
+  int nmax = 0;
+  int pw = 0;  // lane kernels: paths per wavefront
+};
+
+bool kv_decode(int code, Kv &k) {
+  k = Kv{};
+  k.code = code;
   for (int v : hp::kNmaxVariants)
-    if (v == nmax) return true;
+    if (code == v) {
+      k.nmax = v;
+      return true;
+    }
+  for (const hp::LaneVariant &v : hp::kLaneVariants)
+    if (code == (v.pw == 64 ? 100 : 200) + v.n) {
+      k.lanes = true;
+      k.nmax = v.n;  // lane kernels are compiled for one exact n
+      k.pw = v.pw;
+      return true;
+    }
   return false;
+}
+
+// Variants that can run systems of up to n unknowns and exponents up to
+// emax within max_lds bytes of LDS (group kernels: checked per system).
+std::vector<int> kv_candidates(int n, int emax, size_t max_lds) {
+  std::vector<int> out;
+  for (const hp::LaneVariant &v : hp::kLaneVariants)
+    if (v.n == n && hp::lanes_lds_bytes(v.n, v.pw, emax) <= max_lds)
+      out.push_back((v.pw == 64 ? 100 : 200) + v.n);
+  for (int v : hp::kNmaxVariants)
+    if (v >= n) out.push_back(v);
+  return out;
+}
+
+// Default: the group kernel of the smallest n_max >= n (the faster family
+// on the measured workloads); the lane kernels are autotuner candidates.
+int kv_default(int n, int emax, size_t max_lds) {
+  (void)emax;
+  (void)max_lds;
+  return nmax_for(n);
 }
 
 std::mutex g_tune_mu;
@@ -368,7 +411,7 @@ struct hp_plan {
   DevTables dev;
   hp_tolerances tol{};
   hp_c64 gamma{};
-  int nmax = 0;
+  Kv kv;  // kernel variant
   // plain-mode state
   DevBuf px0, pt, ph, piv, pactive;
   DevBuf ids_scratch;
@@ -449,23 +492,39 @@ int check_lds(hp_context *ctx, size_t lds) {
   return HP_OK;
 }
 
+// LDS bytes per workgroup of variant k for the systems of P.
+size_t kv_lds(const Kv &k, const Packed &P) {
+  return k.lanes ? hp::lanes_lds_bytes(k.nmax, k.pw, P.emax) : P.lds(k.nmax);
+}
+
+// Default variant for a multi-system launch: a lane kernel needs one n for
+// all systems.
+Kv kv_pick(const Packed &P, const hp_context *ctx) {
+  Kv k;
+  kv_decode(P.nmin == P.nl ? kv_default(P.nl, P.emax, ctx->max_lds) : nmax_for(P.nl), k);
+  return k;
+}
+
 // Persistent launch over the systems in `dev` (already uploaded).
-int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, int nmax,
+int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv &k,
                       const hp_tolerances &tol, int64_t total_paths, hp_c64 *endpoints,
                       int32_t *status, hp_path_stats *stats, hipStream_t s, int *groups_out,
                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   if (!e0) e0 = ctx->ev0;
   if (!e1) e1 = ctx->ev1;
-  const size_t lds = P.lds(nmax);
+  if (P.nl > k.nmax || (k.lanes && P.nmin != k.nmax))
+    return fail(HP_E_INVALID_ARG, "kernel variant does not match the systems' n");
+  const size_t lds = kv_lds(k, P);
   int rc = check_lds(ctx, lds);
   if (rc) return rc;
   int per_cu = 0;
-  HIP_TRY((hipError_t)hp_max_groups_per_cu(nmax, lds, &per_cu));
+  if (k.lanes) HIP_TRY((hipError_t)hp_lanes_per_cu(k.nmax, k.pw, lds, &per_cu));
+  else HIP_TRY((hipError_t)hp_max_groups_per_cu(k.nmax, lds, &per_cu));
   if (per_cu < 1) return fail(HP_E_DEVICE, "kernel variant does not fit on a compute unit");
   // enough wavefronts to hold every path once, at most a full device
-  int64_t per_wave = hp::kLanes / std::max(1, P.nl);  // paths per wavefront
-  int64_t want = (total_paths + per_wave - 1) / per_wave;
-  int64_t groups = std::min<int64_t>((int64_t)ctx->cus * per_cu, std::max<int64_t>(1, want));
+  const int64_t per_wave = k.lanes ? k.pw : hp::kLanes / std::max(1, P.nl);
+  const int64_t want = (total_paths + per_wave - 1) / per_wave;
+  const int64_t groups = std::min<int64_t>((int64_t)ctx->cus * per_cu, std::max<int64_t>(1, want));
   KArgs a;
   std::memset(&a, 0, sizeof(a));
   a.sys = dev.sys.as<DevSys>();
@@ -481,18 +540,22 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, int nmax
   a.tol = dev_tol(tol);
   HIP_TRY(hipMemsetAsync(dev.qhead.p, 0, P.sys.size() * sizeof(unsigned long long), s));
   HIP_TRY(hipEventRecord(e0, s));
-  HIP_TRY((hipError_t)hp_launch_persistent(nmax, a, (int)groups, lds, s));
+  if (k.lanes) HIP_TRY((hipError_t)hp_launch_lanes(k.nmax, k.pw, a, (int)groups, lds, s));
+  else HIP_TRY((hipError_t)hp_launch_persistent(k.nmax, a, (int)groups, lds, s));
   HIP_TRY(hipEventRecord(e1, s));
   if (groups_out) *groups_out = (int)groups;
   return HP_OK;
 }
 
-int plan_variant(hp_plan *plan, int nmax) {
-  if (nmax == 0) nmax = nmax_for(plan->info.n);
-  if (nmax < plan->info.n || !is_variant(nmax))
-    return fail(HP_E_INVALID_ARG, "no compiled kernel variant with n_max " + std::to_string(nmax) +
+int plan_variant(hp_plan *plan, int code) {
+  if (code == 0) code = kv_default(plan->info.n, plan->info.emax, plan->ctx->max_lds);
+  Kv k;
+  if (!kv_decode(code, k) || k.nmax < plan->info.n || (k.lanes && k.nmax != plan->info.n))
+    return fail(HP_E_INVALID_ARG, "no compiled kernel variant " + std::to_string(code) +
                                       " for n = " + std::to_string(plan->info.n));
-  plan->nmax = nmax;
+  int rc = check_lds(plan->ctx, kv_lds(k, plan->P));
+  if (rc) return rc;
+  plan->kv = k;
   return HP_OK;
 }
 
@@ -506,7 +569,8 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
   if ((rc = plan->ph.alloc((size_t)n_paths * sizeof(double)))) return rc;
   if ((rc = plan->piv.alloc((size_t)8 * n_paths * sizeof(int32_t)))) return rc;
   if ((rc = plan->pactive.alloc(sizeof(unsigned int)))) return rc;
-  const size_t lds = plan->P.lds(plan->nmax);
+  const Kv &k = plan->kv;
+  const size_t lds = kv_lds(k, plan->P);
   if ((rc = check_lds(ctx, lds))) return rc;
   // system descriptor with this call's queue and ids
   DevSys d = plan->P.sys[0];
@@ -533,7 +597,7 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
   a.ps.active = plan->pactive.as<unsigned int>();
   HIP_TRY(hipEventRecord(ctx->ev0, s));
   HIP_TRY((hipError_t)hp_launch_plain_init(a, s));
-  const int64_t per_wave = hp::kLanes / n;
+  const int64_t per_wave = k.lanes ? k.pw : hp::kLanes / n;
   const int wgs = (int)((n_paths + per_wave - 1) / per_wave);
   // every path ends within max_steps + 1 attempts plus the final Newton
   const int64_t max_launches = (int64_t)plan->tol.max_steps + 4;
@@ -541,7 +605,8 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
   unsigned int active = 1;
   while (active > 0 && launches < max_launches) {
     HIP_TRY(hipMemsetAsync(plan->pactive.p, 0, sizeof(unsigned int), s));
-    HIP_TRY((hipError_t)hp_launch_plain_step(plan->nmax, a, wgs, lds, s));
+    if (k.lanes) HIP_TRY((hipError_t)hp_launch_lanes_plain(k.nmax, k.pw, a, wgs, lds, s));
+    else HIP_TRY((hipError_t)hp_launch_plain_step(k.nmax, a, wgs, lds, s));
     HIP_TRY(hipMemcpyAsync(&active, plan->pactive.p, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     ++launches;
@@ -555,30 +620,33 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
 
 int autotune(hp_plan *plan) {
   const std::string key = tune_key(plan->info, plan->n_terms);
-  int cached = tune_lookup(key);
-  if (cached && is_variant(cached) && cached >= plan->info.n) {
-    plan->nmax = cached;
+  const int cached = tune_lookup(key);
+  Kv ck;
+  if (cached && kv_decode(cached, ck) && ck.nmax >= plan->info.n &&
+      (!ck.lanes || ck.nmax == plan->info.n) &&
+      check_lds(plan->ctx, kv_lds(ck, plan->P)) == HP_OK) {
+    plan->kv = ck;
     return HP_OK;
   }
   hp_context *ctx = plan->ctx;
-  // sample: enough paths to fill the device twice
-  const int64_t per_wave = hp::kLanes / plan->info.n;
-  const int64_t sample = std::min<int64_t>(plan->info.paths, (int64_t)ctx->cus * 8 * per_wave * 2);
+  // sample: a few resident rounds of the widest variant
+  const int64_t sample = std::min<int64_t>(plan->info.paths, (int64_t)ctx->cus * 4 * 64 * 2);
   DevBuf e, st;
   int rc;
   if ((rc = e.alloc((size_t)sample * plan->info.n * sizeof(hp_c64)))) return rc;
   if ((rc = st.alloc((size_t)sample * sizeof(int32_t)))) return rc;
   double best = 1e300;
-  int best_v = plan->nmax;
-  for (int v : hp::kNmaxVariants) {
-    if (v < plan->info.n) continue;
+  Kv best_k = plan->kv;
+  for (int code : kv_candidates(plan->info.n, plan->info.emax, ctx->max_lds)) {
+    Kv k;
+    if (!kv_decode(code, k) || check_lds(ctx, kv_lds(k, plan->P)) != HP_OK) continue;
     double tms = 0.0;
     for (int rep = 0; rep < 2; ++rep) {  // the second repetition counts
       DevSys d = plan->P.sys[0];
       d.n_paths = sample;
       d.ids = nullptr;
       HIP_TRY(hipMemcpyAsync(plan->dev.sys.p, &d, sizeof(d), hipMemcpyHostToDevice, ctx->stream));
-      rc = launch_persistent(ctx, plan->dev, plan->P, v, plan->tol, sample, e.as<hp_c64>(),
+      rc = launch_persistent(ctx, plan->dev, plan->P, k, plan->tol, sample, e.as<hp_c64>(),
                              st.as<int32_t>(), nullptr, ctx->stream, nullptr);
       if (rc) return rc;
       HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -588,11 +656,11 @@ int autotune(hp_plan *plan) {
     }
     if (tms < best) {
       best = tms;
-      best_v = v;
+      best_k = k;
     }
   }
-  plan->nmax = best_v;
-  tune_store(key, best_v);
+  plan->kv = best_k;
+  tune_store(key, best_k.code);
   return HP_OK;
 }
 
@@ -619,7 +687,6 @@ int hp_plan_create(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_t
   pack_append(p->P, f, p->info, gamma, p->info.paths, 0, 0, nullptr);
   if ((rc = p->dev.upload(p->P, ctx->stream))) return rc;
   if ((rc = plan_variant(p.get(), 0))) return rc;
-  if ((rc = check_lds(ctx, p->P.lds(p->nmax)))) return rc;
   if (tune && (rc = autotune(p.get()))) return rc;
   *out = p.release();
   return HP_OK;
@@ -632,9 +699,9 @@ void hp_plan_destroy(hp_plan *plan) {
   delete plan;
 }
 
-int hp_plan_set_variant(hp_plan *plan, int32_t max_n) {
+int hp_plan_set_variant(hp_plan *plan, int32_t variant) {
   if (!plan) return fail(HP_E_INVALID_ARG, "plan is NULL");
-  return plan_variant(plan, max_n);
+  return plan_variant(plan, variant);
 }
 
 int hp_plan_track_device(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endpoints,
@@ -650,8 +717,9 @@ int hp_plan_track_device(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_
   hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
   const double t0 = now_ms();
   ctx->last = hp_timing{};
-  ctx->last.waves_per_group = 1;
-  ctx->last.max_n = plan->nmax;
+  ctx->last.paths_per_wave = plan->kv.lanes ? plan->kv.pw : hp::kLanes / plan->info.n;
+  ctx->last.max_n = plan->kv.nmax;
+  ctx->last.variant = plan->kv.code;
   if (n_paths == 0) return HP_OK;
   int rc;
   if (mode == HP_PLAIN) {
@@ -662,7 +730,7 @@ int hp_plan_track_device(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_
     d.ids = ids;
     HIP_TRY(hipMemcpyAsync(plan->dev.sys.p, &d, sizeof(d), hipMemcpyHostToDevice, s));
     int groups = 0;
-    if ((rc = launch_persistent(ctx, plan->dev, plan->P, plan->nmax, plan->tol, n_paths,
+    if ((rc = launch_persistent(ctx, plan->dev, plan->P, plan->kv, plan->tol, n_paths,
                                 endpoints, status, stats, s, &groups)))
       return rc;
     ctx->last.launches = 1;
@@ -746,8 +814,7 @@ int hp_track_batch(hp_context *ctx, const hp_system *fs, int32_t n_systems, cons
     check_system(&fs[s], info);
     pack_append(P, &fs[s], info, gammas[s], info.paths, po[s], xo[s], nullptr);
   }
-  const int nmax = nmax_for(P.nl);
-  if (nmax < 0) return fail(HP_E_UNSUPPORTED_N, "no kernel variant");
+  const Kv kv = kv_pick(P, ctx);
   DevTables dev;
   if ((rc = dev.upload(P, ctx->stream))) return rc;
   DevBuf e, st, sts;
@@ -758,7 +825,7 @@ int hp_track_batch(hp_context *ctx, const hp_system *fs, int32_t n_systems, cons
     return rc;
   int groups = 0;
   ctx->last = hp_timing{};
-  if ((rc = launch_persistent(ctx, dev, P, nmax, T, total, e.as<hp_c64>(),
+  if ((rc = launch_persistent(ctx, dev, P, kv, T, total, e.as<hp_c64>(),
                               st.as<int32_t>(), stats ? sts.as<hp_path_stats>() : nullptr,
                               ctx->stream, &groups)))
     return rc;
@@ -772,8 +839,9 @@ int hp_track_batch(hp_context *ctx, const hp_system *fs, int32_t n_systems, cons
   ctx->last.kernel_ms = ms;
   ctx->last.launches = 1;
   ctx->last.groups = groups;
-  ctx->last.waves_per_group = 1;
-  ctx->last.max_n = nmax;
+  ctx->last.paths_per_wave = kv.lanes ? kv.pw : hp::kLanes / P.nl;
+  ctx->last.max_n = kv.nmax;
+  ctx->last.variant = kv.code;
   ctx->last.total_ms = now_ms() - t0;
   return HP_OK;
 }
@@ -1049,11 +1117,11 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
     // endpoints of a chunk are packed with stride n inside its region
     total += chunk[i];
   }
-  const int nmax = nmax_for(P.nl);
+  const Kv kv = kv_pick(P, ctx);
   DevTables dev;
   int rc = dev.upload(P, S->stream);
   if (rc) return rc;
-  rc = launch_persistent(ctx, dev, P, nmax, tol, total, S->a_ends.as<hp_c64>(),
+  rc = launch_persistent(ctx, dev, P, kv, tol, total, S->a_ends.as<hp_c64>(),
                          S->a_status.as<int32_t>(), S->a_stats.as<hp_path_stats>(), S->stream,
                          nullptr, S->ev0, S->ev1);
   if (rc) return rc;
@@ -1160,8 +1228,13 @@ int hp_server_submit(hp_server *S, const hp_system *f, hp_c64 gamma, const hp_to
     return fail(HP_E_INVALID_ARG, "gamma must be finite and nonzero");
   const int n = f->n;
   {
-    const size_t lds = hp::system_lds_bytes(nmax_for(n), n, R->info.emax, f->n_terms);
-    if ((rc = check_lds(S->ctx, lds))) return rc;
+    // the request must fit the variant chosen for it alone; a mixed launch
+    // takes the widest variant of its requests, which fits as well
+    Packed one;
+    pack_append(one, f, R->info, gamma, 1, 0, 0, nullptr);
+    const Kv kv = kv_pick(one, S->ctx);
+    if (kv.nmax < n) return fail(HP_E_UNSUPPORTED_N, "no kernel variant for n");
+    if ((rc = check_lds(S->ctx, kv_lds(kv, one)))) return rc;
   }
   R->eq_ptr.assign(f->eq_ptr, f->eq_ptr + n + 1);
   R->coeff.assign(f->coeff, f->coeff + f->n_terms);

@@ -118,12 +118,29 @@ inline size_t system_lds_bytes(int nmax, int n, int emax, int n_terms) {
   return kCtlBytes + staged_term_bytes(n_terms) + (size_t)(kLanes / n + 1) * group_lds_bytes(nmax, emax);
 }
 
+// Lane-per-path kernels (lanes.hip): every lane tracks its own path; one
+// instantiation per exact n (1..8) with PW = 64 paths per wavefront, and
+// PW = 32 for n = 7, 8 (systems whose power table is large).  LDS per
+// wavefront: [J | rhs] and the power table, each entry PW * 16 bytes.
+struct LaneVariant {
+  int n, pw;
+};
+constexpr LaneVariant kLaneVariants[] = {{1, 64}, {2, 64}, {3, 64}, {4, 64}, {5, 64},
+                                         {6, 64}, {7, 64}, {8, 64}, {7, 32}, {8, 32}};
+inline size_t lanes_lds_bytes(int n, int pw, int emax) {
+  return (size_t)(n * (n + 1) + n * emax) * (size_t)pw * 16;
+}
+
 }  // namespace hp
 
-// Kernel launchers (tracker.hip).  Return a hipError_t value.
+// Kernel launchers (tracker.hip, lanes.hip).  Return a hipError_t value.
 extern "C++" {
 int hp_launch_persistent(int nmax, const hp::KArgs &a, int groups, size_t lds, void *stream);
 int hp_launch_plain_init(const hp::KArgs &a, void *stream);
 int hp_launch_plain_step(int nmax, const hp::KArgs &a, int groups, size_t lds, void *stream);
 int hp_max_groups_per_cu(int nmax, size_t lds, int *out);
+int hp_launch_lanes(int n, int pw, const hp::KArgs &a, int groups, size_t lds, void *stream);
+int hp_launch_lanes_plain(int n, int pw, const hp::KArgs &a, int groups, size_t lds,
+                          void *stream);
+int hp_lanes_per_cu(int n, int pw, size_t lds, int *out);
 }

@@ -30,59 +30,10 @@
 // performs one step per launch for a fixed path -> group map.
 #include <hip/hip_runtime.h>
 
+#include "hp_device.hpp"
 #include "hp_internal.hpp"
 
 namespace hp {
-
-struct cd {
-  double re, im;
-};
-
-__device__ __forceinline__ cd cadd(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
-__device__ __forceinline__ cd csub(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
-__device__ __forceinline__ cd cscale(cd a, double s) { return {a.re * s, a.im * s}; }
-__device__ __forceinline__ cd cmul(cd a, cd b) {
-  return {fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
-}
-// acc - a*b
-__device__ __forceinline__ cd cfms(cd acc, cd a, cd b) {
-  return {fma(-a.re, b.re, fma(a.im, b.im, acc.re)), fma(-a.re, b.im, fma(-a.im, b.re, acc.im))};
-}
-// 1/b by Smith's method
-__device__ __forceinline__ cd crecip(cd b) {
-  if (fabs(b.re) >= fabs(b.im)) {
-    double r = b.im / b.re;
-    double id = 1.0 / (b.re + b.im * r);
-    return {id, -r * id};
-  }
-  double r = b.re / b.im;
-  double id = 1.0 / (b.re * r + b.im);
-  return {r * id, -id};
-}
-// c ? a : b, component-wise (a conditional on the struct itself would go
-// through stack temporaries)
-__device__ __forceinline__ cd csel(bool c, cd a, cd b) { return {c ? a.re : b.re, c ? a.im : b.im}; }
-__device__ __forceinline__ double cabs1(cd a) { return fabs(a.re) + fabs(a.im); }
-__device__ __forceinline__ double cmod(cd a) { return sqrt(a.re * a.re + a.im * a.im); }
-// max that propagates NaN from a (NaN never compares <=)
-__device__ __forceinline__ double nmax(double m, double a) { return (a <= m) ? m : a; }
-
-__device__ __forceinline__ cd ld(const double2 *p) {
-  double2 v = *p;
-  return {v.x, v.y};
-}
-__device__ __forceinline__ void st(double2 *p, cd v) { *p = make_double2(v.re, v.im); }
-__device__ __forceinline__ void lds_add(double2 *p, cd v) {
-  double *q = (double *)p;
-  __hip_atomic_fetch_add(q, v.re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  __hip_atomic_fetch_add(q + 1, v.im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
-// Orders the LDS accesses of the (single-wavefront) workgroup.
-__device__ __forceinline__ void wsync() { __syncthreads(); }
-
-enum EvalMode { EV_NEG_HT = 0, EV_H = 1, EV_F = 2 };
 
 template <int NMAX>
 struct Tracker {
@@ -96,7 +47,7 @@ struct Tracker {
   const uint4 *gmeta;
   bool staged;           // terms copied to LDS (right after the refill area)
   int nterms;
-  const int32_t *kp;  // kKSlots offsets: terms with k factors are terms[kp[k] .. kp[k+1])
+  int kpv[NMAX + 2];  // terms with k factors are this system's terms kpv[k] .. kpv[k+1]-1
   cd gamma;
   long long npaths, out_path_base, out_x_base, id_base;
   const long long *ids;
@@ -135,7 +86,11 @@ struct Tracker {
     n = sp->n;
     emax = sp->emax;
     ngroups = kLanes / n;
-    kp = a.eqp + sp->eq_base;
+    {
+      const int32_t *kp = a.eqp + sp->eq_base;
+#pragma unroll
+      for (int k = 0; k <= NMAX + 1; ++k) kpv[k] = kp[k < NMAX + 1 ? k : HP_MAX_N + 1];
+    }
     // stage a small term table in LDS (all lanes copy, then order)
     const int nt = sp->n_terms;
     size_t tbytes = 0;
@@ -267,7 +222,7 @@ struct Tracker {
   __device__ __forceinline__ void terms_upto() {
     if constexpr (K >= 0) {
       terms_upto<K - 1, LDS>();
-      const int lo = kp[K], hi = kp[K + 1];
+      const int lo = kpv[K], hi = kpv[K + 1];
       if (lo < hi) terms_k<K, LDS>(lo, hi);
     }
   }

@@ -1,0 +1,100 @@
+"""Every compiled kernel variant (group kernels: n lanes per path; lane
+kernels: one path per lane, Jacobian in LDS) against the CPU oracle on the
+same seeded inputs, in batched and plain mode."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from parity import compare_paths
+
+pytestmark = pytest.mark.gpu
+
+NTHREADS = min(16, os.cpu_count() or 1)
+GROUP = [4, 8, 12]
+LANES = [100 + n for n in range(1, 9)] + [207, 208]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1804_03807_amd as hp
+    c = hp.Context(0)
+    yield c
+    c.close()
+
+
+CASES = {
+    "dense5": lambda: (W.dense_small().systems[0], complex(W.dense_small().gammas[0])),
+    "cyclic4": lambda: (W.cyclic_workload(4, 41).systems[0], complex(W.cyclic_workload(4, 41).gammas[0])),
+    "cyclic6": lambda: (W.cyclic_workload(6, 9).systems[0], complex(W.cyclic_workload(6, 9).gammas[0])),
+    "cyclic7": lambda: (W.cyclic_workload(7, 7).systems[0], complex(W.cyclic_workload(7, 7).gammas[0])),
+    "dense3_d3": lambda: (W.dense_system(3, [3, 3, 2], np.random.default_rng(33)), 0.6 + 0.8j),
+    "dense8_d2": lambda: (W.dense_system(8, [2] * 8, np.random.default_rng(34)), np.exp(0.3j)),
+}
+_oracle_cache = {}
+
+
+def oracle_ref(name, s, g):
+    if name not in _oracle_cache:
+        P = s.bezout()
+        _oracle_cache[name] = oracle.track_paths(s, g, n_paths=P, n_threads=NTHREADS)
+    return _oracle_cache[name]
+
+
+def run_variant(ctx, s, g, code, mode):
+    import torch
+    import paper_1804_03807_amd as hp
+    plan = ctx.plan(s, g)
+    plan.set_variant(code)
+    P = s.bezout()
+    e, st, sts = plan.outputs(P)
+    plan.track_device(e, st, sts, mode=mode)
+    torch.cuda.synchronize()
+    t = ctx.last_timing()
+    out = (hp.Plan.endpoints_to_numpy(e), st.cpu().numpy(), hp.Plan.stats_to_numpy(sts))
+    plan.close()
+    return out, t
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("code", GROUP + LANES)
+def test_variant_matches_oracle(ctx, name, code):
+    s, g = CASES[name]()
+    if (code >= 100 and code % 100 != s.n) or code % 100 < s.n:
+        pytest.skip("variant not compiled for this n")
+    log(f"case {name} n={s.n} paths={s.bezout()} variant={code}")
+    (e, st, sts), t = run_variant(ctx, s, g, code, "batched")
+    assert t["variant"] == code
+    ref = oracle_ref(name, s, g)
+    hard, flips = compare_paths(e, st, sts, *ref)
+    assert len(hard) == 0, f"paths {hard[:8]} differ from the oracle"
+    assert len(flips) == 0
+    assert (sts["residual"][st == 0] <= 1e-10).all()
+
+
+@pytest.mark.parametrize("name,code", [("cyclic4", 104), ("cyclic6", 106), ("dense8_d2", 208)])
+def test_lane_plain_equals_batched(ctx, name, code):
+    s, g = CASES[name]()
+    (e1, s1, t1), _ = run_variant(ctx, s, g, code, "batched")
+    (e2, s2, t2), tp = run_variant(ctx, s, g, code, "plain")
+    assert tp["launches"] > 1
+    assert np.array_equal(s1, s2)
+    assert np.array_equal(e1, e2)
+    assert np.array_equal(t1["steps"], t2["steps"])
+
+
+def test_unknown_variant_rejected(ctx):
+    import paper_1804_03807_amd as hp
+    s, g = CASES["cyclic6"]()
+    plan = ctx.plan(s, g)
+    for bad in (5, 104, 108, 207, 300, -1):
+        with pytest.raises(hp.HomotopyError):
+            plan.set_variant(bad)
+    plan.close()
