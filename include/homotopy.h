@@ -138,11 +138,20 @@ int hp_last_timing(const hp_context *ctx, hp_timing *out);
  * or larger than 2^62. */
 int64_t hp_path_count(const hp_system *f);
 
-/* Host-memory convenience call: tracks paths 0..n_paths-1 of f.
- *   g must be NULL and start must be NULL (total-degree start system,
- *     start points decoded from path ids); other values are rejected.
+/* Host-memory call, the problem statement's track_paths(system,
+ * start_solutions, gamma, tolerances): tracks n_paths paths of
+ * gamma (1 - t) g + t f from t = 0 to t = 1.
+ *   g == NULL, start == NULL: total-degree start system, paths 0..n_paths-1
+ *     with their start points decoded from the path ids (see above);
+ *   g == NULL, start != NULL: total-degree start system, path k starts at
+ *     start[k*n .. k*n+n-1] (any solutions of x_i^{d_i} = 1);
+ *   g != NULL, start != NULL: a general start system of the same n (its
+ *     own terms, e.g. f with other coefficients: coefficient-parameter
+ *     continuation), path k starting at start[k*n ..] (solutions of g);
+ *   g != NULL, start == NULL: HP_E_INVALID_ARG.
  *   endpoints [n_paths*n], status [n_paths], stats [n_paths] or NULL.
- *   mode: HP_PLAIN or HP_BATCHED. */
+ *   mode: HP_PLAIN or HP_BATCHED.  General start systems and explicit
+ *   start points run on the group kernels. */
 int hp_track_paths(hp_context *ctx, const hp_system *f, const hp_system *g, const hp_c64 *start,
                    int64_t n_paths, hp_c64 gamma, const hp_tolerances *tol, hp_c64 *endpoints,
                    int32_t *status, hp_path_stats *stats, int32_t mode);

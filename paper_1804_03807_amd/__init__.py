@@ -106,18 +106,27 @@ class Context:
         check(self._L.hp_last_timing(self.handle, ctypes.byref(t)))
         return {k: getattr(t, k) for k, _ in HpTiming._fields_}
 
-    def track_paths(self, system, gamma, n_paths=None, tol=None, mode="batched", stats=True):
-        """Tracks total-degree paths 0..n_paths-1 (host arrays in and out).
-        Returns (endpoints complex[P, n], status int32[P], stats or None)."""
+    def track_paths(self, system, gamma, n_paths=None, tol=None, mode="batched", stats=True,
+                    start=None, g=None):
+        """Tracks paths of gamma(1-t) g + t f (host arrays in and out).
+        start=None: total-degree paths 0..n_paths-1; otherwise one path per
+        row of start (complex [P, n]), from the start system g (None: total
+        degree).  Returns (endpoints complex[P, n], status int32[P], stats)."""
         v = _SysView(system)
-        P = path_count(system) if n_paths is None else int(n_paths)
+        gv = _SysView(g) if g is not None else None
+        if start is not None:
+            start = np.ascontiguousarray(start, dtype=np.complex128).reshape(-1, v.n)
+            P = int(start.shape[0])
+        else:
+            P = path_count(system) if n_paths is None else int(n_paths)
         ends = np.zeros((P, v.n), np.complex128)
         st = np.full(P, -1, np.int32)
         sts = np.zeros(P, STATS_DTYPE) if stats else None
         tol = tol or default_tolerances()
-        check(self._L.hp_track_paths(self.handle, ctypes.byref(v.c), None, None, P, _c64(gamma),
-                                     ctypes.byref(tol), _ptr(ends), _ptr(st), _ptr(sts),
-                                     _MODES[mode]))
+        check(self._L.hp_track_paths(self.handle, ctypes.byref(v.c),
+                                     ctypes.byref(gv.c) if gv is not None else None,
+                                     _ptr(start), P, _c64(gamma), ctypes.byref(tol), _ptr(ends),
+                                     _ptr(st), _ptr(sts), _MODES[mode]))
         return ends, st, sts
 
     def track_batch(self, systems, gammas, tol=None, stats=True):

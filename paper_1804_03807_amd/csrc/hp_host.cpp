@@ -173,6 +173,7 @@ struct Packed {
   std::vector<double2> roots;
   std::vector<DevSys> sys;
   int nl = 1, nmin = HP_MAX_N, emax = 1, kmax = 0;
+  bool general = false;  // a general start system or explicit start points
   // workgroup LDS bytes of the n_max variant: largest over the systems
   size_t lds(int nmax) const {
     size_t b = 0;
@@ -183,9 +184,56 @@ struct Packed {
 };
 
 // Appends system f (already checked, info from check_system).
+// Appends the terms of s (sorted by factor count, equation in byte 15) to
+// P.terms and its kKSlots block to P.kp; returns the block's index.
+int32_t pack_terms(Packed &P, const hp_system *f, int32_t term_base) {
+  const int n = f->n;
+  std::vector<std::pair<int, int>> order;  // (k, term)
+  std::vector<int> eq_of(f->n_terms);
+  for (int i = 0; i < n; ++i)
+    for (int t = f->eq_ptr[i]; t < f->eq_ptr[i + 1]; ++t) {
+      int k = 0;
+      for (int j = 0; j < n; ++j) k += f->exps[(size_t)t * n + j] > 0;
+      order.push_back({k, t});
+      eq_of[t] = i;
+    }
+  std::stable_sort(order.begin(), order.end(),
+                   [](const std::pair<int, int> &a, const std::pair<int, int> &b) {
+                     return a.first < b.first;
+                   });
+  int32_t kp[hp::kKSlots];
+  size_t pos = 0;
+  for (int k = 0; k <= HP_MAX_N; ++k) {
+    kp[k] = (int32_t)(P.terms.size()) - term_base;
+    while (pos < order.size() && order[pos].first == k) {
+      const int t = order[pos].second;
+      DevTerm T;
+      std::memset(&T, 0, sizeof(T));
+      T.cre = f->coeff[t].re;
+      T.cim = f->coeff[t].im;
+      uint8_t bytes[16] = {0};
+      bytes[0] = (uint8_t)k;
+      int m = 0;
+      for (int j = 0; j < n; ++j) {
+        const int e = f->exps[(size_t)t * n + j];
+        if (e > 0) bytes[1 + m++] = (uint8_t)(j | (e << 4));
+      }
+      bytes[15] = (uint8_t)eq_of[t];
+      std::memcpy(T.w, bytes, 16);
+      P.terms.push_back(T);
+      ++pos;
+    }
+  }
+  kp[HP_MAX_N + 1] = (int32_t)P.terms.size() - term_base;
+  const int32_t block = (int32_t)P.kp.size();
+  P.kp.insert(P.kp.end(), kp, kp + hp::kKSlots);
+  return block;
+}
+
 void pack_append(Packed &P, const hp_system *f, const SysInfo &info, hp_c64 gamma,
                  int64_t queue_len, int64_t out_path_base, int64_t out_x_base,
-                 const int64_t *dev_ids) {
+                 const int64_t *dev_ids, const hp_system *g = nullptr, int g_emax = 0,
+                 const double2 *dev_start = nullptr) {
   const int n = f->n;
   DevSys d;
   std::memset(&d, 0, sizeof(d));
@@ -215,48 +263,20 @@ void pack_append(Packed &P, const hp_system *f, const SysInfo &info, hp_c64 gamm
   d.out_x_base = out_x_base;
   d.ids = dev_ids;
   // all terms of the system sorted by factor count (stable), equation in byte 15
-  std::vector<std::pair<int, int>> order;  // (k, term)
-  std::vector<int> eq_of(f->n_terms);
-  for (int i = 0; i < n; ++i)
-    for (int t = f->eq_ptr[i]; t < f->eq_ptr[i + 1]; ++t) {
-      int k = 0;
-      for (int j = 0; j < n; ++j) k += f->exps[(size_t)t * n + j] > 0;
-      order.push_back({k, t});
-      eq_of[t] = i;
-    }
-  std::stable_sort(order.begin(), order.end(),
-                   [](const std::pair<int, int> &a, const std::pair<int, int> &b) {
-                     return a.first < b.first;
-                   });
-  int32_t kp[hp::kKSlots];
-  size_t pos = 0;
-  for (int k = 0; k <= HP_MAX_N; ++k) {
-    kp[k] = (int32_t)(P.terms.size()) - d.term_base;
-    while (pos < order.size() && order[pos].first == k) {
-      const int t = order[pos].second;
-      DevTerm T;
-      std::memset(&T, 0, sizeof(T));
-      T.cre = f->coeff[t].re;
-      T.cim = f->coeff[t].im;
-      uint8_t bytes[16] = {0};
-      bytes[0] = (uint8_t)k;
-      int m = 0;
-      for (int j = 0; j < n; ++j) {
-        const int e = f->exps[(size_t)t * n + j];
-        if (e > 0) bytes[1 + m++] = (uint8_t)(j | (e << 4));
-      }
-      bytes[15] = (uint8_t)eq_of[t];
-      std::memcpy(T.w, bytes, 16);
-      P.terms.push_back(T);
-      ++pos;
-    }
+  const int32_t fblock = pack_terms(P, f, d.term_base);
+  (void)fblock;
+  if (g) {
+    d.g_term_base = (int32_t)P.terms.size();
+    d.g_n_terms = g->n_terms;
+    d.g_eq_base = pack_terms(P, g, d.g_term_base);
+    d.emax = std::max(d.emax, g_emax);
   }
-  kp[HP_MAX_N + 1] = (int32_t)P.terms.size() - d.term_base;
-  P.kp.insert(P.kp.end(), kp, kp + hp::kKSlots);
+  d.start = dev_start;
   P.sys.push_back(d);
   P.nl = std::max(P.nl, n);
   P.nmin = std::min(P.nmin, n);
-  P.emax = std::max(P.emax, info.emax);
+  P.emax = std::max(P.emax, d.emax);
+  P.general = P.general || g || dev_start;
   P.kmax = std::max(P.kmax, info.kmax);
 }
 
@@ -412,6 +432,7 @@ struct hp_plan {
   hp_tolerances tol{};
   hp_c64 gamma{};
   Kv kv;  // kernel variant
+  DevBuf start_dev;  // explicit start points [n_start][n] (general plans)
   // plain-mode state
   DevBuf px0, pt, ph, piv, pactive;
   DevBuf ids_scratch;
@@ -553,6 +574,8 @@ int plan_variant(hp_plan *plan, int code) {
   if (!kv_decode(code, k) || k.nmax < plan->info.n || (k.lanes && k.nmax != plan->info.n))
     return fail(HP_E_INVALID_ARG, "no compiled kernel variant " + std::to_string(code) +
                                       " for n = " + std::to_string(plan->info.n));
+  if (k.lanes && plan->P.general)
+    return fail(HP_E_INVALID_ARG, "lane kernels track the total-degree start system only");
   int rc = check_lds(plan->ctx, kv_lds(k, plan->P));
   if (rc) return rc;
   plan->kv = k;
@@ -623,7 +646,7 @@ int autotune(hp_plan *plan) {
   const int cached = tune_lookup(key);
   Kv ck;
   if (cached && kv_decode(cached, ck) && ck.nmax >= plan->info.n &&
-      (!ck.lanes || ck.nmax == plan->info.n) &&
+      (!ck.lanes || (ck.nmax == plan->info.n && !plan->P.general)) &&
       check_lds(plan->ctx, kv_lds(ck, plan->P)) == HP_OK) {
     plan->kv = ck;
     return HP_OK;
@@ -637,9 +660,10 @@ int autotune(hp_plan *plan) {
   if ((rc = st.alloc((size_t)sample * sizeof(int32_t)))) return rc;
   double best = 1e300;
   Kv best_k = plan->kv;
-  for (int code : kv_candidates(plan->info.n, plan->info.emax, ctx->max_lds)) {
+  for (int code : kv_candidates(plan->info.n, plan->P.emax, ctx->max_lds)) {
     Kv k;
     if (!kv_decode(code, k) || check_lds(ctx, kv_lds(k, plan->P)) != HP_OK) continue;
+    if (k.lanes && plan->P.general) continue;
     double tms = 0.0;
     for (int rep = 0; rep < 2; ++rep) {  // the second repetition counts
       DevSys d = plan->P.sys[0];
@@ -668,8 +692,15 @@ int autotune(hp_plan *plan) {
 
 extern "C" {
 
-int hp_plan_create(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
-                   int32_t tune, hp_plan **out) {
+}  // extern "C"
+
+namespace {
+
+// A plan for f; with g and/or start given, a general start system and
+// explicit start points (n_start of them, host memory, [n_start][n]).
+int plan_create(hp_context *ctx, const hp_system *f, const hp_system *g, const hp_c64 *start,
+                int64_t n_start, hp_c64 gamma, const hp_tolerances *tol, int32_t tune,
+                hp_plan **out) {
   if (!ctx || !out) return fail(HP_E_INVALID_ARG, "NULL argument");
   *out = nullptr;
   int rc = check_tol(tol);
@@ -679,17 +710,49 @@ int hp_plan_create(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_t
   std::unique_ptr<hp_plan> p(new hp_plan());
   p->ctx = ctx;
   if ((rc = check_system(f, p->info))) return rc;
+  SysInfo ginfo;
+  if (g) {
+    if ((rc = check_system(g, ginfo))) return fail(rc, "start system g: " + g_err);
+    if (g->n != f->n) return fail(HP_E_INVALID_ARG, "g and f must have the same n");
+    if (!start) return fail(HP_E_INVALID_ARG, "a general start system needs its start points");
+  }
+  if (start) {
+    if (n_start < 0) return fail(HP_E_INVALID_ARG, "n_paths < 0");
+    for (int64_t i = 0; i < n_start * f->n; ++i)
+      if (!std::isfinite(start[i].re) || !std::isfinite(start[i].im))
+        return fail(HP_E_INVALID_ARG, "start points must be finite");
+    p->info.paths = n_start;
+  }
   p->n_terms = f->n_terms;
   if (tol) p->tol = *tol;
   else hp_default_tolerances(&p->tol);
   p->gamma = gamma;
   HIP_TRY(hipSetDevice(ctx->device));
-  pack_append(p->P, f, p->info, gamma, p->info.paths, 0, 0, nullptr);
+  const double2 *dstart = nullptr;
+  if (start) {
+    if ((rc = p->start_dev.alloc((size_t)std::max<int64_t>(1, n_start) * f->n * sizeof(hp_c64))))
+      return rc;
+    if (n_start > 0)
+      HIP_TRY(hipMemcpy(p->start_dev.p, start, (size_t)n_start * f->n * sizeof(hp_c64),
+                        hipMemcpyHostToDevice));
+    dstart = p->start_dev.as<double2>();
+  }
+  pack_append(p->P, f, p->info, gamma, p->info.paths, 0, 0, nullptr, g, g ? ginfo.emax : 0,
+              dstart);
   if ((rc = p->dev.upload(p->P, ctx->stream))) return rc;
   if ((rc = plan_variant(p.get(), 0))) return rc;
   if (tune && (rc = autotune(p.get()))) return rc;
   *out = p.release();
   return HP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hp_plan_create(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
+                   int32_t tune, hp_plan **out) {
+  return plan_create(ctx, f, nullptr, nullptr, 0, gamma, tol, tune, out);
 }
 
 void hp_plan_destroy(hp_plan *plan) {
@@ -748,13 +811,12 @@ int hp_track_paths(hp_context *ctx, const hp_system *f, const hp_system *g, cons
                    int64_t n_paths, hp_c64 gamma, const hp_tolerances *tol, hp_c64 *endpoints,
                    int32_t *status, hp_path_stats *stats, int32_t mode) {
   if (!ctx) return fail(HP_E_INVALID_ARG, "context is NULL");
-  if (g || start)
-    return fail(HP_E_INVALID_ARG, "only the total-degree start system is supported (g, start NULL)");
+  if (g && !start) return fail(HP_E_INVALID_ARG, "a general start system needs its start points");
   if (n_paths < 0 || (n_paths > 0 && (!endpoints || !status)))
     return fail(HP_E_INVALID_ARG, "bad outputs");
   const double t0 = now_ms();
   hp_plan *plan = nullptr;
-  int rc = hp_plan_create(ctx, f, gamma, tol, 0, &plan);
+  int rc = plan_create(ctx, f, g, start, n_paths, gamma, tol, 0, &plan);
   if (rc) return rc;
   std::unique_ptr<hp_plan, void (*)(hp_plan *)> guard(plan, hp_plan_destroy);
   if (n_paths > plan->info.paths)

@@ -43,6 +43,12 @@ struct alignas(16) DevSys {
   int64_t out_x_base;          // first endpoint (hp_c64) index of this system
   const int64_t *ids;          // queue index -> path id (nullptr: id_base + index)
   int64_t id_base;
+  // general start system g (g_n_terms == 0: total degree, g_i = x_i^{d_i} - 1)
+  int32_t g_term_base;         // first term of g
+  int32_t g_n_terms;
+  int32_t g_eq_base;           // g's kKSlots block in the kp array
+  int32_t g_pad;
+  const double2 *start;        // [path id][n] start points (nullptr: roots of unity)
 };
 
 struct DevTol {
@@ -93,13 +99,14 @@ template <int NMAX>
 struct GroupLds {
   double2 J[NMAX][NMAX + 1];  // Jacobian accumulator of f (rows padded: bank spread)
   double2 fv[NMAX];       // f values
+  double2 gv[NMAX];       // g values (general start system)
   double2 prow[NMAX + 1]; // normalised pivot row, [NMAX] = right-hand side
   double2 dsol[NMAX];     // solution of the last linear solve
   double cand[NMAX];      // pivot candidates
   double red[2 * NMAX];   // reductions
 };
 __host__ __device__ constexpr size_t group_fixed_bytes(int nmax) {
-  return (size_t)16 * ((size_t)nmax * (nmax + 1) + 3 * nmax + 1) + (size_t)8 * 3 * nmax;
+  return (size_t)16 * ((size_t)nmax * (nmax + 1) + 4 * nmax + 1) + (size_t)8 * 3 * nmax;
 }
 __host__ __device__ constexpr size_t group_lds_bytes(int nmax, int emax) {
   return group_fixed_bytes(nmax) + (size_t)16 * nmax * emax;

@@ -48,6 +48,12 @@ struct Tracker {
   bool staged;           // terms copied to LDS (right after the refill area)
   int nterms;
   int kpv[NMAX + 2];  // terms with k factors are this system's terms kpv[k] .. kpv[k+1]-1
+  // general start system g (terms in global memory) and explicit start points
+  bool has_g;
+  int gkpv[NMAX + 2];
+  const double2 *ggcoef;
+  const uint4 *ggmeta;
+  const double2 *start;
   cd gamma;
   long long npaths, out_path_base, out_x_base, id_base;
   const long long *ids;
@@ -91,6 +97,15 @@ struct Tracker {
 #pragma unroll
       for (int k = 0; k <= NMAX + 1; ++k) kpv[k] = kp[k < NMAX + 1 ? k : HP_MAX_N + 1];
     }
+    has_g = sp->g_n_terms > 0;
+    ggcoef = a.tcoef + sp->g_term_base;
+    ggmeta = a.tmeta + sp->g_term_base;
+    if (has_g) {
+      const int32_t *kp = a.eqp + sp->g_eq_base;
+#pragma unroll
+      for (int k = 0; k <= NMAX + 1; ++k) gkpv[k] = kp[k < NMAX + 1 ? k : HP_MAX_N + 1];
+    }
+    start = sp->start;
     // stage a small term table in LDS (all lanes copy, then order)
     const int nt = sp->n_terms;
     size_t tbytes = 0;
@@ -168,10 +183,14 @@ struct Tracker {
 
   // ------------------------------------------------------------------ eval
   // Terms with exactly K factors: this lane takes terms lo + r, lo + r + n, ...
-  template <int K, bool LDS>
-  __device__ __forceinline__ void terms_k(int lo, int hi) {
-    const double2 *tcoef = LDS ? staged_coef() : gcoef;
-    const uint4 *tmeta = LDS ? staged_meta() : gmeta;
+  // Term values go to vt[eq] unscaled; partial derivatives go to J[eq][v]
+  // times sigma (the backward sweep starts from sigma): sigma = t for f
+  // (CPLX false: real) and gamma (1 - t) for a general start system g.
+  template <int K, bool LDS, bool CPLX>
+  __device__ __forceinline__ void terms_k(int lo, int hi, const double2 *gc, const uint4 *gm,
+                                          cd sigma, double2 *vt) {
+    const double2 *tcoef = LDS ? staged_coef() : gc;
+    const uint4 *tmeta = LDS ? staged_meta() : gm;
 #pragma nounroll
     for (int base = lo; base < hi; base += n) {
       const int tt = base + r;
@@ -182,7 +201,7 @@ struct Tracker {
         const cd c = {cc.x, cc.y};
         const int eq = (int)(w[3] >> 24);
         if constexpr (K == 0) {
-          lds_add(&G->fv[eq], c);
+          lds_add(&vt[eq], c);
         } else {
           int vv[K], ee[K];
           cd P[K], phi[K];
@@ -199,37 +218,40 @@ struct Tracker {
             run = cmul(run, phi[m]);
             P[m] = run;
           }
-          lds_add(&G->fv[eq], run);
+          lds_add(&vt[eq], run);
           double2 *jrow = &G->J[eq][0];
-          cd S = {1.0, 0.0};
+          cd S = sigma;
 #pragma unroll
           for (int m = K - 1; m >= 0; --m) {
             const cd left = (m == 0) ? c : P[m > 0 ? m - 1 : 0];
-            cd d = (m == K - 1) ? left : cmul(left, S);
+            cd d = CPLX ? cmul(left, S) : (m == K - 1 ? cscale(left, S.re) : cmul(left, S));
             if (ee[m] > 1) {
               const cd q = ld(&xp[vv[m] * emax + ee[m] - 2]);
               d = cmul(d, cscale(q, (double)ee[m]));
             }
             lds_add(&jrow[vv[m]], d);
-            if (m > 0) S = (m == K - 1) ? phi[m] : cmul(S, phi[m]);
+            if (m > 0)
+              S = (m == K - 1 && !CPLX) ? cscale(phi[m], S.re) : cmul(S, phi[m]);
           }
         }
       }
     }
   }
 
-  template <int K, bool LDS>
-  __device__ __forceinline__ void terms_upto() {
+  template <int K, bool LDS, bool CPLX>
+  __device__ __forceinline__ void terms_upto(const int *kk, const double2 *gc, const uint4 *gm,
+                                             cd sigma, double2 *vt) {
     if constexpr (K >= 0) {
-      terms_upto<K - 1, LDS>();
-      const int lo = kpv[K], hi = kpv[K + 1];
-      if (lo < hi) terms_k<K, LDS>(lo, hi);
+      terms_upto<K - 1, LDS, CPLX>(kk, gc, gm, sigma, vt);
+      const int lo = kk[K], hi = kk[K + 1];
+      if (lo < hi) terms_k<K, LDS, CPLX>(lo, hi, gc, gm, sigma, vt);
     }
   }
 
   // Own row of J_x(xc, te) into A and, in b: -H_t (EV_NEG_HT), H (EV_H) or
   // f (EV_F) at (xc, te).
   __device__ __forceinline__ void eval(int emode, double te) {
+    const cd s = cscale(gamma, 1.0 - te);
     // powers of the own unknown; zero the own row of the accumulators
     {
       cd p = xc;
@@ -241,26 +263,33 @@ struct Tracker {
 #pragma unroll
       for (int j = 0; j < NMAX; ++j) Jr[j] = make_double2(0.0, 0.0);
       G->fv[r] = make_double2(0.0, 0.0);
+      G->gv[r] = make_double2(0.0, 0.0);
     }
     wsync();
-    if (staged) terms_upto<NMAX, true>();
-    else terms_upto<NMAX, false>();
+    const cd tsig = {te, 0.0};
+    if (staged) terms_upto<NMAX, true, false>(kpv, gcoef, gmeta, tsig, G->fv);
+    else terms_upto<NMAX, false, false>(kpv, gcoef, gmeta, tsig, G->fv);
+    if (has_g) terms_upto<NMAX, false, true>(gkpv, ggcoef, ggmeta, s, G->gv);
     wsync();
     const cd f = ld(&G->fv[r]);
-    // start system g_r = x_r^{d_r} - 1
-    const int d = deg_r;
-    cd xq = {1.0, 0.0};
-    for (int e = 1; e < d; ++e) xq = cmul(xq, xc);
-    cd g = cmul(xq, xc);
-    g.re -= 1.0;
-    const cd s = cscale(gamma, 1.0 - te);
-    const cd sdg = cmul(s, cscale(xq, (double)d));
+    cd g, sdg = {0.0, 0.0};
+    if (has_g) {
+      g = ld(&G->gv[r]);
+    } else {
+      // total-degree start system g_r = x_r^{d_r} - 1
+      const int d = deg_r;
+      cd xq = {1.0, 0.0};
+      for (int e = 1; e < d; ++e) xq = cmul(xq, xc);
+      g = cmul(xq, xc);
+      g.re -= 1.0;
+      sdg = cmul(s, cscale(xq, (double)d));
+    }
     const cd hv = cadd(cmul(s, g), cscale(f, te));
     const cd ht = csub(f, cmul(gamma, g));
     b = csel(emode == EV_F, f, csel(emode == EV_H, hv, cd{-ht.re, -ht.im}));
 #pragma unroll
     for (int j = 0; j < NMAX; ++j) {
-      const cd v = cscale(ld(&Jr[j]), te);
+      const cd v = ld(&Jr[j]);
       A[j] = csel(j == r, cadd(v, sdg), v);
     }
   }
@@ -330,9 +359,14 @@ struct Tracker {
   __device__ __forceinline__ void start_path(long long q) {
     qidx = q;
     const long long pid = ids ? ids[q] : id_base + q;
-    const long long kk = (pid / sp->radix[r]) % sp->deg[r];
-    const double2 z = a.roots[sp->root_base + sp->root_off[r] + (int)kk];
-    x0 = {z.x, z.y};
+    if (start) {
+      const double2 z = start[pid * n + (r < n ? r : 0)];
+      x0 = {z.x, z.y};
+    } else {
+      const long long kk = (pid / sp->radix[r]) % sp->deg[r];
+      const double2 z = a.roots[sp->root_base + sp->root_off[r] + (int)kk];
+      x0 = {z.x, z.y};
+    }
     mode = M_TRACK;
     t = 0.0;
     h = a.tol.h_init;
@@ -546,8 +580,12 @@ __global__ void __launch_bounds__(64) k_plain_init(KArgs a) {
   const long long P = a.ps.P;
   const long long pid = sd->ids ? sd->ids[q] : sd->id_base + q;
   for (int j = 0; j < sd->n; ++j) {
-    long long kk = (pid / sd->radix[j]) % sd->deg[j];
-    a.ps.x0[j * P + q] = a.roots[sd->root_base + sd->root_off[j] + (int)kk];
+    if (sd->start) {
+      a.ps.x0[j * P + q] = sd->start[pid * sd->n + j];
+    } else {
+      long long kk = (pid / sd->radix[j]) % sd->deg[j];
+      a.ps.x0[j * P + q] = a.roots[sd->root_base + sd->root_off[j] + (int)kk];
+    }
   }
   a.ps.t[q] = 0.0;
   a.ps.h[q] = a.tol.h_init;

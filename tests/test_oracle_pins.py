@@ -376,3 +376,53 @@ def test_work_crew_matches_single_thread(oracle_lib):
     e8, s8, st8 = oracle.track_paths(s, wl.gammas[0], n_paths=720, n_threads=8)
     assert np.array_equal(s1, s8) and np.array_equal(e1, e8)
     assert np.array_equal(st1["steps"], st8["steps"])
+
+
+def _linear_product_roots(n, degs, Ls, betas):
+    import itertools
+    out = []
+    for choice in itertools.product(*[range(d) for d in degs]):
+        M = np.array([Ls[i][choice[i]] for i in range(n)])
+        r = np.array([betas[i][choice[i]] for i in range(n)])
+        out.append(np.linalg.solve(M, r))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("n,degs", [(3, [2, 3, 2]), (5, [2, 2, 1, 3, 2])])
+def test_general_start_system_linear_products(oracle_lib, n, degs):
+    """Coefficient-parameter continuation: from the solved system g (a linear
+    product system, start points = its closed-form roots) to another linear
+    product system f of the same degrees.  Every path converges and the
+    endpoints are f's closed-form roots."""
+    g, Lg, bg = W.linear_products(n, degs, np.random.default_rng(60 + n))
+    f, Lf, bf = W.linear_products(n, degs, np.random.default_rng(70 + n))
+    start = _linear_product_roots(n, degs, Lg, bg)
+    e, st, _ = oracle.track_paths(f, np.exp(0.4j), start=start, g=g, n_threads=4)
+    assert (st == oracle.CONVERGED).all()
+    assert _match_sets(e, _linear_product_roots(n, degs, Lf, bf))
+
+
+def test_general_start_system_univariate(oracle_lib):
+    """n = 1: from the roots of one random quintic to the roots of another
+    (numpy.roots, companion eigenvalues)."""
+    g, pg = W.univariate(5, np.random.default_rng(81))
+    f, pf = W.univariate(5, np.random.default_rng(82))
+    start = np.roots(pg).reshape(-1, 1)
+    e, st, _ = oracle.track_paths(f, np.exp(2.2j), start=start, g=g)
+    assert (st == oracle.CONVERGED).all()
+    assert _match_sets(e, np.roots(pf).reshape(-1, 1))
+
+
+def test_explicit_start_points_total_degree(oracle_lib):
+    """Total-degree start system with the start points passed in (a shuffled
+    subset of the roots of unity) tracks the same paths as the decoded ids."""
+    wl = W.dense_small()
+    s, gam = wl.systems[0], wl.gammas[0]
+    ids = np.array([7, 0, 31, 12, 5], np.int64)
+    degs = s.degrees()
+    start = np.array([[np.exp(2j * np.pi * ((p // int(np.prod(degs[:i]))) % degs[i]) / degs[i])
+                       for i in range(s.n)] for p in ids])
+    e1, s1, _ = oracle.track_paths(s, gam, path_ids=ids)
+    e2, s2, _ = oracle.track_paths(s, gam, start=start)
+    assert (s1 == s2).all()
+    assert np.abs(e1 - e2).max() <= 1e-12
