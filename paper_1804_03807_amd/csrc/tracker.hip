@@ -18,8 +18,9 @@
 // straight-line code, and add the partial derivatives into the path's
 // Jacobian in LDS (ds_add_f64).  Linear systems are solved by Gauss-Jordan
 // elimination with partial pivoting (largest |re|+|im| in the column, ties
-// to the lowest row), one row per lane, the normalised pivot row going
-// through LDS.  One RK4 predictor step and up to max_newton Newton
+// to the lowest row), one row per lane: the pivot search is a DPP butterfly
+// in registers when the groups are aligned (n = 2, 4, 8), else an exchange
+// through LDS; the normalised pivot row goes through LDS.  One RK4 predictor step and up to max_newton Newton
 // iterations form a step; the step control and the final Newton at t = 1
 // follow the library's documented reading.
 //
@@ -34,6 +35,23 @@
 #include "hp_internal.hpp"
 
 namespace hp {
+
+// One butterfly step of a (value, index) max over aligned lane groups,
+// ties to the lowest index: read the DPP partner's pair, keep the larger.
+// CTRL: quad_perm [1,0,3,2] (0xB1, lane ^ 1), quad_perm [2,3,0,1] (0x4E,
+// lane ^ 2) or row_half_mirror (0x141, lane 7 - lane within 8).
+template <int CTRL>
+__device__ __forceinline__ double dpp_max_step(double v, int &idx) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)bits, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(bits >> 32), CTRL, 0xf, 0xf, false);
+  const int oi = __builtin_amdgcn_mov_dpp(idx, CTRL, 0xf, 0xf, false);
+  const double ov =
+      __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+  const bool take = (ov > v) || (ov == v && oi < idx);
+  idx = take ? oi : idx;
+  return take ? ov : v;
+}
 
 template <int NMAX>
 struct Tracker {
@@ -310,23 +328,34 @@ struct Tracker {
 #pragma unroll
     for (int k = 0; k < NMAX; ++k) {
       if (k < n) {
-        G->cand[r] = used ? -1.0 : cabs1(M[k]);
-        wsync();
-        double c[NMAX];
-#pragma unroll
-        for (int q = 0; q < NMAX; ++q) c[q] = G->cand[q];
         double best = -1.0;
         int p = -1;
+        if (n == 2 || n == 4 || (n == 8 && NMAX >= 8)) {
+          // groups of 2, 4 or 8 aligned lanes: butterfly max over (value,
+          // row) in registers (DPP: xor 1, xor 2 within quads, mirror
+          // within 8 lanes), no LDS round trip
+          best = used ? -1.0 : cabs1(M[k]);
+          p = r;
+          best = dpp_max_step<0xB1>(best, p);
+          if (n >= 4) best = dpp_max_step<0x4E>(best, p);
+          if (n >= 8) best = dpp_max_step<0x141>(best, p);
+        } else {
+          G->cand[r] = used ? -1.0 : cabs1(M[k]);
+          wsync();
+          double c[NMAX];
 #pragma unroll
-        for (int q = 0; q < NMAX; ++q) {
-          const bool take = (q < n) && (c[q] > best);
-          best = take ? c[q] : best;
-          p = take ? q : p;
+          for (int q = 0; q < NMAX; ++q) c[q] = G->cand[q];
+#pragma unroll
+          for (int q = 0; q < NMAX; ++q) {
+            const bool take = (q < n) && (c[q] > best);
+            best = take ? c[q] : best;
+            p = take ? q : p;
+          }
         }
         if (!(best > 0.0)) sing = true;
         const bool piv = (r == p);
         if (piv) {
-          const cd inv = crecip(M[k]);
+          const cd inv = crecip_nr(M[k]);
 #pragma unroll
           for (int j = 0; j <= NMAX; ++j) {
             if (j > k) {
