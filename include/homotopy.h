@@ -162,7 +162,7 @@ int hp_plan_create(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_t
                    int32_t tune, hp_plan **out);
 void hp_plan_destroy(hp_plan *plan);
 /* Forces the kernel variant.  Two kernel families are compiled:
- *   n_max = 4, 8, 12       group kernels: n lanes of a wavefront per path
+ *   n_max = 4, 8, 10, 12   group kernels: n lanes of a wavefront per path
  *                          (lane r owns equation r), floor(64/n) paths, for
  *                          any n <= n_max;
  *   100 + n (n = 1..8)     lane kernels: one path per lane, 64 paths per

@@ -174,11 +174,12 @@ struct Packed {
   std::vector<DevSys> sys;
   int nl = 1, nmin = HP_MAX_N, emax = 1, kmax = 0;
   bool general = false;  // a general start system or explicit start points
-  // workgroup LDS bytes of the n_max variant: largest over the systems
-  size_t lds(int nmax) const {
+  // workgroup LDS bytes of the n_max group variant: largest over the
+  // systems, with or without the term tables staged in LDS
+  size_t lds(int nmax, bool stage = true) const {
     size_t b = 0;
     for (const DevSys &d : sys)
-      b = std::max(b, hp::system_lds_bytes(nmax, d.n, d.emax, d.n_terms));
+      b = std::max(b, hp::system_lds_bytes(nmax, d.n, d.emax, d.n_terms, stage));
     return b;
   }
 };
@@ -515,7 +516,33 @@ int check_lds(hp_context *ctx, size_t lds) {
 
 // LDS bytes per workgroup of variant k for the systems of P.
 size_t kv_lds(const Kv &k, const Packed &P) {
-  return k.lanes ? hp::lanes_lds_bytes(k.nmax, k.pw, P.emax) : P.lds(k.nmax);
+  return k.lanes ? hp::lanes_lds_bytes(k.nmax, k.pw, P.emax) : P.lds(k.nmax, false);
+}
+
+// LDS bytes, resident workgroups per CU and term staging of variant k for
+// the systems of P.  Group kernels stage small term tables in LDS unless
+// that lowers the number of resident workgroups.
+int kv_occupancy(hp_context *ctx, const Kv &k, const Packed &P, size_t *lds, int *per_cu,
+                 int *stage) {
+  *stage = 0;
+  if (k.lanes) {
+    *lds = kv_lds(k, P);
+    int rc = check_lds(ctx, *lds);
+    if (rc) return rc;
+    HIP_TRY((hipError_t)hp_lanes_per_cu(k.nmax, k.pw, *lds, per_cu));
+  } else {
+    const size_t ln = P.lds(k.nmax, false), ls = P.lds(k.nmax, true);
+    int rc = check_lds(ctx, ln);
+    if (rc) return rc;
+    int on = 0, os = 0;
+    HIP_TRY((hipError_t)hp_max_groups_per_cu(k.nmax, P.general, ln, &on));
+    if (ls <= ctx->max_lds) HIP_TRY((hipError_t)hp_max_groups_per_cu(k.nmax, P.general, ls, &os));
+    *stage = (ls <= ctx->max_lds && os >= on) ? 1 : 0;
+    *lds = *stage ? ls : ln;
+    *per_cu = *stage ? os : on;
+  }
+  if (*per_cu < 1) return fail(HP_E_DEVICE, "kernel variant does not fit on a compute unit");
+  return HP_OK;
 }
 
 // Default variant for a multi-system launch: a lane kernel needs one n for
@@ -535,13 +562,10 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
   if (!e1) e1 = ctx->ev1;
   if (P.nl > k.nmax || (k.lanes && P.nmin != k.nmax))
     return fail(HP_E_INVALID_ARG, "kernel variant does not match the systems' n");
-  const size_t lds = kv_lds(k, P);
-  int rc = check_lds(ctx, lds);
+  size_t lds = 0;
+  int per_cu = 0, stage = 0;
+  int rc = kv_occupancy(ctx, k, P, &lds, &per_cu, &stage);
   if (rc) return rc;
-  int per_cu = 0;
-  if (k.lanes) HIP_TRY((hipError_t)hp_lanes_per_cu(k.nmax, k.pw, lds, &per_cu));
-  else HIP_TRY((hipError_t)hp_max_groups_per_cu(k.nmax, lds, &per_cu));
-  if (per_cu < 1) return fail(HP_E_DEVICE, "kernel variant does not fit on a compute unit");
   // enough wavefronts to hold every path once, at most a full device
   const int64_t per_wave = k.lanes ? k.pw : hp::kLanes / std::max(1, P.nl);
   const int64_t want = (total_paths + per_wave - 1) / per_wave;
@@ -559,10 +583,11 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
   a.status = status;
   a.stats = stats;
   a.tol = dev_tol(tol);
+  a.stage = stage;
   HIP_TRY(hipMemsetAsync(dev.qhead.p, 0, P.sys.size() * sizeof(unsigned long long), s));
   HIP_TRY(hipEventRecord(e0, s));
   if (k.lanes) HIP_TRY((hipError_t)hp_launch_lanes(k.nmax, k.pw, a, (int)groups, lds, s));
-  else HIP_TRY((hipError_t)hp_launch_persistent(k.nmax, a, (int)groups, lds, s));
+  else HIP_TRY((hipError_t)hp_launch_persistent(k.nmax, P.general, a, (int)groups, lds, s));
   HIP_TRY(hipEventRecord(e1, s));
   if (groups_out) *groups_out = (int)groups;
   return HP_OK;
@@ -593,8 +618,9 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
   if ((rc = plan->piv.alloc((size_t)8 * n_paths * sizeof(int32_t)))) return rc;
   if ((rc = plan->pactive.alloc(sizeof(unsigned int)))) return rc;
   const Kv &k = plan->kv;
-  const size_t lds = kv_lds(k, plan->P);
-  if ((rc = check_lds(ctx, lds))) return rc;
+  size_t lds = 0;
+  int per_cu = 0, stage = 0;
+  if ((rc = kv_occupancy(ctx, k, plan->P, &lds, &per_cu, &stage))) return rc;
   // system descriptor with this call's queue and ids
   DevSys d = plan->P.sys[0];
   d.n_paths = n_paths;
@@ -618,6 +644,7 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
   a.ps.iv = plan->piv.as<int32_t>();
   a.ps.P = n_paths;
   a.ps.active = plan->pactive.as<unsigned int>();
+  a.stage = stage;
   HIP_TRY(hipEventRecord(ctx->ev0, s));
   HIP_TRY((hipError_t)hp_launch_plain_init(a, s));
   const int64_t per_wave = k.lanes ? k.pw : hp::kLanes / n;
@@ -629,7 +656,7 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
   while (active > 0 && launches < max_launches) {
     HIP_TRY(hipMemsetAsync(plan->pactive.p, 0, sizeof(unsigned int), s));
     if (k.lanes) HIP_TRY((hipError_t)hp_launch_lanes_plain(k.nmax, k.pw, a, wgs, lds, s));
-    else HIP_TRY((hipError_t)hp_launch_plain_step(k.nmax, a, wgs, lds, s));
+    else HIP_TRY((hipError_t)hp_launch_plain_step(k.nmax, plan->P.general, a, wgs, lds, s));
     HIP_TRY(hipMemcpyAsync(&active, plan->pactive.p, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     ++launches;

@@ -79,6 +79,7 @@ struct KArgs {
   int32_t *status;
   hp_path_stats *stats;  // may be null
   DevTol tol;
+  int32_t stage;         // group kernels: copy term tables of <= kMaxStagedTerms into LDS
   PlainState ps;         // plain mode only
 };
 
@@ -86,7 +87,7 @@ enum Mode : int32_t { M_IDLE = 0, M_TRACK = 1, M_FINAL = 2 };
 
 // Kernel variants compiled into the library: the register arrays hold up to
 // n_max unknowns; a system of n unknowns runs on the smallest n_max >= n.
-constexpr int kNmaxVariants[] = {4, 8, 12};
+constexpr int kNmaxVariants[] = {4, 8, 10, 12};
 
 // LDS layout of a workgroup (one wavefront): a 64-entry refill broadcast,
 // then one region per lane group (floor(64/n) groups plus one spare group
@@ -108,10 +109,15 @@ struct GroupLds {
 __host__ __device__ constexpr size_t group_fixed_bytes(int nmax) {
   return (size_t)16 * ((size_t)nmax * (nmax + 1) + 4 * nmax + 1) + (size_t)8 * 3 * nmax;
 }
+// Stride of one group's region: the fixed part and the power table, padded
+// to an odd number of 16-byte units, so that up to 16 groups of a wavefront
+// start on distinct 16-byte bank quads (a multiple of 256 bytes would put
+// every group's copy of an entry on the same banks).
 __host__ __device__ constexpr size_t group_lds_bytes(int nmax, int emax) {
-  return group_fixed_bytes(nmax) + (size_t)16 * nmax * emax;
+  return (((group_fixed_bytes(nmax) + (size_t)16 * nmax * emax + 15) / 16) | 1) * 16;
 }
 static_assert(sizeof(GroupLds<8>) == group_fixed_bytes(8), "layout");
+static_assert(sizeof(GroupLds<10>) == group_fixed_bytes(10), "layout");
 static_assert(sizeof(GroupLds<12>) == group_fixed_bytes(12), "layout");
 // Term tables up to this size are staged in LDS at kernel start.
 constexpr int kMaxStagedTerms = 512;
@@ -121,8 +127,9 @@ constexpr int kMaxStagedTerms = 512;
 inline size_t staged_term_bytes(int n_terms) {
   return n_terms <= kMaxStagedTerms ? (size_t)n_terms * 32 : 0;
 }
-inline size_t system_lds_bytes(int nmax, int n, int emax, int n_terms) {
-  return kCtlBytes + staged_term_bytes(n_terms) + (size_t)(kLanes / n + 1) * group_lds_bytes(nmax, emax);
+inline size_t system_lds_bytes(int nmax, int n, int emax, int n_terms, bool stage) {
+  return kCtlBytes + (stage ? staged_term_bytes(n_terms) : 0) +
+         (size_t)(kLanes / n + 1) * group_lds_bytes(nmax, emax);
 }
 
 // Lane-per-path kernels (lanes.hip): every lane tracks its own path; one
@@ -142,10 +149,13 @@ inline size_t lanes_lds_bytes(int n, int pw, int emax) {
 
 // Kernel launchers (tracker.hip, lanes.hip).  Return a hipError_t value.
 extern "C++" {
-int hp_launch_persistent(int nmax, const hp::KArgs &a, int groups, size_t lds, void *stream);
+// general: the systems use a general start system or explicit start points
+int hp_launch_persistent(int nmax, bool general, const hp::KArgs &a, int groups, size_t lds,
+                         void *stream);
 int hp_launch_plain_init(const hp::KArgs &a, void *stream);
-int hp_launch_plain_step(int nmax, const hp::KArgs &a, int groups, size_t lds, void *stream);
-int hp_max_groups_per_cu(int nmax, size_t lds, int *out);
+int hp_launch_plain_step(int nmax, bool general, const hp::KArgs &a, int groups, size_t lds,
+                         void *stream);
+int hp_max_groups_per_cu(int nmax, bool general, size_t lds, int *out);
 int hp_launch_lanes(int n, int pw, const hp::KArgs &a, int groups, size_t lds, void *stream);
 int hp_launch_lanes_plain(int n, int pw, const hp::KArgs &a, int groups, size_t lds,
                           void *stream);

@@ -53,7 +53,10 @@ __device__ __forceinline__ double dpp_max_step(double v, int &idx) {
   return take ? ov : v;
 }
 
-template <int NMAX>
+// GEN: the general start system / explicit start point code is compiled in
+// (a separate instantiation, so that the total-degree kernels do not carry
+// its registers).
+template <int NMAX, bool GEN>
 struct Tracker {
   const KArgs &a;
   const int lane;
@@ -65,10 +68,14 @@ struct Tracker {
   const uint4 *gmeta;
   bool staged;           // terms copied to LDS (right after the refill area)
   int nterms;
-  int kpv[NMAX + 2];  // terms with k factors are this system's terms kpv[k] .. kpv[k+1]-1
+  // terms with k factors are this system's terms kp[k] .. kp[k+1]-1; cached
+  // in registers for the narrow variants (the wide ones would spill)
+  static constexpr bool kCacheKp = NMAX <= 8;
+  int kpv[NMAX + 2];
+  const int *kpm;
   // general start system g (terms in global memory) and explicit start points
   bool has_g;
-  int gkpv[NMAX + 2];
+  const int *gkpm;
   const double2 *ggcoef;
   const uint4 *ggmeta;
   const double2 *start;
@@ -110,19 +117,15 @@ struct Tracker {
     n = sp->n;
     emax = sp->emax;
     ngroups = kLanes / n;
-    {
-      const int32_t *kp = a.eqp + sp->eq_base;
+    kpm = a.eqp + sp->eq_base;
+    if constexpr (kCacheKp) {
 #pragma unroll
-      for (int k = 0; k <= NMAX + 1; ++k) kpv[k] = kp[k < NMAX + 1 ? k : HP_MAX_N + 1];
+      for (int k = 0; k <= NMAX + 1; ++k) kpv[k] = kpm[k < NMAX + 1 ? k : HP_MAX_N + 1];
     }
     has_g = sp->g_n_terms > 0;
     ggcoef = a.tcoef + sp->g_term_base;
     ggmeta = a.tmeta + sp->g_term_base;
-    if (has_g) {
-      const int32_t *kp = a.eqp + sp->g_eq_base;
-#pragma unroll
-      for (int k = 0; k <= NMAX + 1; ++k) gkpv[k] = kp[k < NMAX + 1 ? k : HP_MAX_N + 1];
-    }
+    gkpm = a.eqp + sp->g_eq_base;
     start = sp->start;
     // stage a small term table in LDS (all lanes copy, then order)
     const int nt = sp->n_terms;
@@ -130,7 +133,7 @@ struct Tracker {
     gcoef = a.tcoef + sp->term_base;
     gmeta = a.tmeta + sp->term_base;
     nterms = nt;
-    staged = nt <= kMaxStagedTerms;
+    staged = a.stage && nt <= kMaxStagedTerms;
     if (staged) {
       double2 *sc = staged_coef();
       uint4 *sm = staged_meta();
@@ -281,17 +284,20 @@ struct Tracker {
 #pragma unroll
       for (int j = 0; j < NMAX; ++j) Jr[j] = make_double2(0.0, 0.0);
       G->fv[r] = make_double2(0.0, 0.0);
-      G->gv[r] = make_double2(0.0, 0.0);
+      if constexpr (GEN) G->gv[r] = make_double2(0.0, 0.0);
     }
     wsync();
     const cd tsig = {te, 0.0};
-    if (staged) terms_upto<NMAX, true, false>(kpv, gcoef, gmeta, tsig, G->fv);
-    else terms_upto<NMAX, false, false>(kpv, gcoef, gmeta, tsig, G->fv);
-    if (has_g) terms_upto<NMAX, false, true>(gkpv, ggcoef, ggmeta, s, G->gv);
+    const int *kk = kCacheKp ? kpv : kpm;
+    if (staged) terms_upto<NMAX, true, false>(kk, gcoef, gmeta, tsig, G->fv);
+    else terms_upto<NMAX, false, false>(kk, gcoef, gmeta, tsig, G->fv);
+    if constexpr (GEN) {
+      if (has_g) terms_upto<NMAX, false, true>(gkpm, ggcoef, ggmeta, s, G->gv);
+    }
     wsync();
     const cd f = ld(&G->fv[r]);
     cd g, sdg = {0.0, 0.0};
-    if (has_g) {
+    if (GEN && has_g) {
       g = ld(&G->gv[r]);
     } else {
       // total-degree start system g_r = x_r^{d_r} - 1
@@ -388,7 +394,7 @@ struct Tracker {
   __device__ __forceinline__ void start_path(long long q) {
     qidx = q;
     const long long pid = ids ? ids[q] : id_base + q;
-    if (start) {
+    if (GEN && start) {
       const double2 z = start[pid * n + (r < n ? r : 0)];
       x0 = {z.x, z.y};
     } else {
@@ -549,10 +555,10 @@ struct Tracker {
 // drained.  A wavefront works on one system at a time and moves on to the
 // next system once its queue is empty and its own groups are idle.
 // ------------------------------------------------------------------------
-template <int NMAX>
+template <int NMAX, bool GEN>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) k_persistent(KArgs a) {
   extern __shared__ __align__(16) char smem[];
-  Tracker<NMAX> tr(a, smem);
+  Tracker<NMAX, GEN> tr(a, smem);
   const int first_sys = blockIdx.x % a.n_systems;
   for (int v = 0; v < a.n_systems; ++v) {
     const int s = (first_sys + v) % a.n_systems;
@@ -622,10 +628,10 @@ __global__ void __launch_bounds__(64) k_plain_init(KArgs a) {
   for (int f = 1; f < 8; ++f) a.ps.iv[f * P + q] = 0;
 }
 
-template <int NMAX>
+template <int NMAX, bool GEN>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) k_plain_step(KArgs a) {
   extern __shared__ __align__(16) char smem[];
-  Tracker<NMAX> tr(a, smem);
+  Tracker<NMAX, GEN> tr(a, smem);
   tr.load_system(0);
   const long long P = a.ps.P;
   const long long q = (long long)blockIdx.x * tr.ngroups + tr.grp;
@@ -686,50 +692,57 @@ static int allow_lds(K kernel, size_t lds) {
                                   (int)lds);
 }
 
-template <int NMAX>
+template <int NMAX, bool GEN>
 static int launch_persistent_t(const KArgs &a, int groups, size_t lds, hipStream_t s) {
-  int rc = allow_lds(k_persistent<NMAX>, lds);
+  int rc = allow_lds(k_persistent<NMAX, GEN>, lds);
   if (rc) return rc;
-  hipLaunchKernelGGL((k_persistent<NMAX>), dim3(groups), dim3(64), lds, s, a);
+  hipLaunchKernelGGL((k_persistent<NMAX, GEN>), dim3(groups), dim3(64), lds, s, a);
   return (int)hipGetLastError();
 }
-template <int NMAX>
+template <int NMAX, bool GEN>
 static int launch_plain_t(const KArgs &a, int groups, size_t lds, hipStream_t s) {
-  int rc = allow_lds(k_plain_step<NMAX>, lds);
+  int rc = allow_lds(k_plain_step<NMAX, GEN>, lds);
   if (rc) return rc;
-  hipLaunchKernelGGL((k_plain_step<NMAX>), dim3(groups), dim3(64), lds, s, a);
+  hipLaunchKernelGGL((k_plain_step<NMAX, GEN>), dim3(groups), dim3(64), lds, s, a);
   return (int)hipGetLastError();
 }
-template <int NMAX>
+template <int NMAX, bool GEN>
 static int occupancy_t(size_t lds, int *out) {
-  int rc = allow_lds(k_persistent<NMAX>, lds);
+  int rc = allow_lds(k_persistent<NMAX, GEN>, lds);
   if (rc) return rc;
-  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_persistent<NMAX>, 64, lds);
+  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_persistent<NMAX, GEN>, 64, lds);
 }
 
-#define HP_DISPATCH(NM, CALL)                  \
-  switch (NM) {                                \
-    case 4: return CALL(4);                    \
-    case 8: return CALL(8);                    \
-    case 12: return CALL(12);                  \
-    default: return (int)hipErrorInvalidValue; \
+#define HP_DISPATCH(NM, GN, CALL)                 \
+  switch ((NM) * 2 + ((GN) ? 1 : 0)) {            \
+    case 8: return CALL(4, false);                \
+    case 9: return CALL(4, true);                 \
+    case 16: return CALL(8, false);               \
+    case 17: return CALL(8, true);                \
+    case 20: return CALL(10, false);              \
+    case 21: return CALL(10, true);               \
+    case 24: return CALL(12, false);              \
+    case 25: return CALL(12, true);               \
+    default: return (int)hipErrorInvalidValue;    \
   }
 
-int hp_launch_persistent(int nmax, const KArgs &a, int groups, size_t lds, void *stream) {
-#define CALLP(N) launch_persistent_t<N>(a, groups, lds, (hipStream_t)stream)
-  HP_DISPATCH(nmax, CALLP)
+int hp_launch_persistent(int nmax, bool general, const KArgs &a, int groups, size_t lds,
+                         void *stream) {
+#define CALLP(N, G) launch_persistent_t<N, G>(a, groups, lds, (hipStream_t)stream)
+  HP_DISPATCH(nmax, general, CALLP)
 #undef CALLP
 }
 
-int hp_launch_plain_step(int nmax, const KArgs &a, int groups, size_t lds, void *stream) {
-#define CALLS(N) launch_plain_t<N>(a, groups, lds, (hipStream_t)stream)
-  HP_DISPATCH(nmax, CALLS)
+int hp_launch_plain_step(int nmax, bool general, const KArgs &a, int groups, size_t lds,
+                         void *stream) {
+#define CALLS(N, G) launch_plain_t<N, G>(a, groups, lds, (hipStream_t)stream)
+  HP_DISPATCH(nmax, general, CALLS)
 #undef CALLS
 }
 
-int hp_max_groups_per_cu(int nmax, size_t lds, int *out) {
-#define CALLO(N) occupancy_t<N>(lds, out)
-  HP_DISPATCH(nmax, CALLO)
+int hp_max_groups_per_cu(int nmax, bool general, size_t lds, int *out) {
+#define CALLO(N, G) occupancy_t<N, G>(lds, out)
+  HP_DISPATCH(nmax, general, CALLO)
 #undef CALLO
 }
 

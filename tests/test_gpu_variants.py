@@ -14,7 +14,7 @@ from parity import compare_paths
 pytestmark = pytest.mark.gpu
 
 NTHREADS = min(16, os.cpu_count() or 1)
-GROUP = [4, 8, 12]
+GROUP = [4, 8, 10, 12]
 LANES = [100 + n for n in range(1, 9)] + [207, 208]
 
 
