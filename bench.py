@@ -32,11 +32,12 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 TRAFFIC_PROFILE = {
     "workload": "cyclic8",
     "sources_sha256": {
-        "tracker.hip": "4e23c868f58586e8d6706726d8d6c6a14e661900ba1a779b50a040fc36791320",
-        "hp_internal.hpp": "d750f77139f0549f46d32e7b4a8172ee4d59a0a200b3346b9cb175167fa178f2",
+        "tracker.hip": "b94dad49817963e56eb37286044992017de1210b7181ac1e9d2384295516dfcd",
+        "hp_internal.hpp": "64ebf229d4058cabc9f7f8becee4fe35f0ae258e57177d767e6d57e22754445b",
+        "hp_device.hpp": "a6d29c9a468b66c02d70054e33dbfdf6215e4ed3f10d96f59df50875c25877c1",
     },
-    "fetch_kib": 243.5, "fetch_scale": 262144 / 131089,
-    "write_kib": 8467.84375, "write_scale": 262144 / 262144,
+    "fetch_kib": 255.0, "fetch_scale": 262144 / 131088.875,
+    "write_kib": 8463.4375, "write_scale": 262144 / 262144,
 }
 
 WORKLOADS = {
