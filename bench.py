@@ -124,6 +124,48 @@ def serving_run(ctx, n_requests, budget_bytes, load=0.8):
             "hbm_budget_bytes": budget_bytes, "peak_resident_bytes": peak}
 
 
+def batch_run(ctx, n_systems=256):
+    """Many dense systems (n 3..10, degrees 2..3 per equation, seed 3) in one
+    persistent launch with one refill queue per system."""
+    import workloads as W
+    wl = W.dense_batch(n_systems, seed=3)
+    gam = [complex(g) for g in wl.gammas]
+    from paper_1804_03807_amd import flops
+    ctx.track_batch(wl.systems, gam, stats=False)  # warm-up (code load, tables)
+    t0 = time.perf_counter()
+    res = ctx.track_batch(wl.systems, gam, stats=True)
+    dt = time.perf_counter() - t0
+    tm = ctx.last_timing()
+    conv = sum(int((st == 0).sum()) for _, st, _ in res)
+    flop = sum(flops.run_flops(sy, sts) for sy, (_, _, sts) in zip(wl.systems, res))
+    tfs = flop / (tm["kernel_ms"] * 1e-3) / 1e12
+    return {"systems": n_systems, "paths": wl.total_paths, "converged": conv,
+            "kernel_ms": tm["kernel_ms"], "paths_per_s": wl.total_paths / (tm["kernel_ms"] * 1e-3),
+            "end_to_end_ms": dt * 1e3, "kernel_variant": tm["variant"],
+            "achieved_tflops": tfs, "frac_of_fp64_peak": tfs / FP64_PEAK_TFLOPS}
+
+
+def cyclic10_run(ctx):
+    """All 10! = 3,628,800 paths of the cyclic-10 supports (seed 5): the
+    persistent tracker with divergence truncation, then the duplicate pass."""
+    import workloads as W
+    wl = W.cyclic10()
+    s, g = wl.systems[0], complex(wl.gammas[0])
+    t0 = time.perf_counter()
+    e, st, sts, remaining = ctx.solve(s, g)
+    dt = time.perf_counter() - t0
+    tm = ctx.last_timing()
+    from paper_1804_03807_amd import flops
+    conv = st == 0
+    tfs = flops.run_flops(s, sts) / (dt) / 1e12
+    return {"paths": s.bezout(), "converged": int(conv.sum()),
+            "achieved_tflops_end_to_end": tfs, "frac_of_fp64_peak_end_to_end": tfs / FP64_PEAK_TFLOPS,
+            "diverged": int((st == 1).sum()), "failed": int((st >= 2).sum()),
+            "duplicate_pairs_left": remaining,
+            "residual_gate_ok": bool((sts["residual"][conv] <= 1e-10).all()),
+            "solve_ms": dt * 1e3, "paths_per_s": s.bezout() / dt}
+
+
 def cpu_baseline(system, gamma, seconds_target=15.0):
     """The oracle as it stands, on a stride sample of path ids, with every
     host thread; extrapolated to paths/s."""
@@ -141,9 +183,15 @@ def cpu_baseline(system, gamma, seconds_target=15.0):
     t0 = time.perf_counter()
     _, st, _ = oracle.track_paths(system, gamma, path_ids=ids, n_threads=threads)
     dt = time.perf_counter() - t0
+    # one thread on a sixteenth of the sample
+    ids1 = ids[::16]
+    t1 = time.perf_counter()
+    oracle.track_paths(system, gamma, path_ids=ids1, n_threads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": len(ids) / dt, "unit": "paths/s", "cores": threads, "kind": "oracle",
             "sample": f"every {stride}-th path id ({len(ids)} of {total} paths), "
-                      f"{threads} threads, {dt:.1f} s"}
+                      f"{threads} threads, {dt:.1f} s",
+            "one_thread_value": len(ids1) / dt1}
 
 
 def main():
@@ -160,6 +208,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=32,
                     help="requests in the serving sample (0: skip)")
     ap.add_argument("--serving-budget-gib", type=float, default=16.0)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 256-system batch and the cyclic-10 runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -238,6 +288,7 @@ def main():
                                       "groups": timing["groups"]}},
         "converged": int(conv.sum()),
         "not_converged": int((~conv).sum()),
+        "converged_per_s": int(conv.sum()) * args.steps / elapsed,
         "residual_gate_ok": resid_ok,
         "latency_ms": {"p50": float(np.percentile(times, 50)),
                        "p99": float(np.percentile(times, 99))},
@@ -259,6 +310,10 @@ def main():
         out["plain"] = {"value": P / dt, "unit": "paths/s", "launches": tp["launches"],
                         "ms": dt * 1e3}
         out["batched_over_plain"] = value / (P / dt)
+
+    if not args.no_extra:
+        out["batch256"] = batch_run(ctx)
+        out["cyclic10"] = cyclic10_run(ctx)
 
     if args.serving_requests > 0:
         out["serving"] = serving_run(ctx, args.serving_requests,

@@ -98,3 +98,35 @@ def test_unknown_variant_rejected(ctx):
         with pytest.raises(hp.HomotopyError):
             plan.set_variant(bad)
     plan.close()
+
+
+def test_autotune_chooses_a_valid_variant(ctx, tmp_path, monkeypatch):
+    """tune=1 times every candidate variant on a sample, keeps the fastest,
+    records it in $HP_TUNE_CACHE; a second plan reads the cache; the tuned
+    plan's results match the oracle."""
+    import torch
+    import paper_1804_03807_amd as hp
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("HP_TUNE_CACHE", str(cache))
+    s, g = CASES["cyclic6"]()
+    plan = ctx.plan(s, g, tune=True)
+    P = s.bezout()
+    e, st, sts = plan.outputs(P)
+    plan.track_device(e, st, sts)
+    torch.cuda.synchronize()
+    code = ctx.last_timing()["variant"]
+    log(f"autotuned variant {code}")
+    assert code in GROUP + LANES
+    assert code < 100 or code % 100 == s.n
+    text = cache.read_text().split()
+    assert len(text) == 2 and int(text[1]) == code
+    hard, flips = compare_paths(hp.Plan.endpoints_to_numpy(e), st.cpu().numpy(),
+                                hp.Plan.stats_to_numpy(sts), *oracle_ref("cyclic6", s, g))
+    assert len(hard) == 0 and len(flips) == 0
+    plan.close()
+    plan2 = ctx.plan(s, g, tune=True)  # cached: same choice
+    e2, st2, _ = plan2.outputs(P)
+    plan2.track_device(e2, st2)
+    torch.cuda.synchronize()
+    assert ctx.last_timing()["variant"] == code
+    plan2.close()
