@@ -207,54 +207,80 @@ struct Tracker {
   // Term values go to vt[eq] unscaled; partial derivatives go to J[eq][v]
   // times sigma (the backward sweep starts from sigma): sigma = t for f
   // (CPLX false: real) and gamma (1 - t) for a general start system g.
+  // One term c * prod phi_m: value to vt[eq], partials times sigma to J[eq][.].
+  template <int K, bool CPLX>
+  __device__ __forceinline__ void one_term(const double2 cc, const uint4 mw, cd sigma,
+                                           double2 *vt) {
+    const uint32_t w[4] = {mw.x, mw.y, mw.z, mw.w};
+    const cd c = {cc.x, cc.y};
+    const int eq = (int)(w[3] >> 24);
+    if constexpr (K == 0) {
+      lds_add(&vt[eq], c);
+    } else {
+      int vv[K], ee[K];
+      cd P[K], phi[K];
+      cd run = c;
+#pragma unroll
+      for (int m = 0; m < K; ++m) {
+        const int byte = (w[(m + 1) >> 2] >> (8 * ((m + 1) & 3))) & 0xff;
+        ee[m] = byte >> 4;
+        vv[m] = byte & 15;
+        phi[m] = ld(&xp[vv[m] * emax + ee[m] - 1]);
+      }
+#pragma unroll
+      for (int m = 0; m < K; ++m) {
+        run = cmul(run, phi[m]);
+        P[m] = run;
+      }
+      lds_add(&vt[eq], run);
+      double2 *jrow = &G->J[eq][0];
+      cd S = sigma;
+#pragma unroll
+      for (int m = K - 1; m >= 0; --m) {
+        const cd left = (m == 0) ? c : P[m > 0 ? m - 1 : 0];
+        cd d = CPLX ? cmul(left, S) : (m == K - 1 ? cscale(left, S.re) : cmul(left, S));
+        if (ee[m] > 1) {
+          const cd q = ld(&xp[vv[m] * emax + ee[m] - 2]);
+          d = cmul(d, cscale(q, (double)ee[m]));
+        }
+        lds_add(&jrow[vv[m]], d);
+        if (m > 0) S = (m == K - 1 && !CPLX) ? cscale(phi[m], S.re) : cmul(S, phi[m]);
+      }
+    }
+  }
+
+  // Terms with exactly K factors: this lane takes terms lo + r, lo + r + n, ...
+  // Term values go to vt[eq] unscaled; partial derivatives go to J[eq][v]
+  // times sigma (the backward sweep starts from sigma): sigma = t for f
+  // (CPLX false: real) and gamma (1 - t) for a general start system g.
+  // From the staged table (LDS) a term is read where it is used; from global
+  // memory (large systems: many terms of at most a few factors per class)
+  // the lane's next term is read while this one is processed.
   template <int K, bool LDS, bool CPLX>
   __device__ __forceinline__ void terms_k(int lo, int hi, const double2 *gc, const uint4 *gm,
                                           cd sigma, double2 *vt) {
-    const double2 *tcoef = LDS ? staged_coef() : gc;
-    const uint4 *tmeta = LDS ? staged_meta() : gm;
+    if constexpr (LDS || K > 4) {
+      const double2 *tcoef = LDS ? staged_coef() : gc;
+      const uint4 *tmeta = LDS ? staged_meta() : gm;
 #pragma nounroll
-    for (int base = lo; base < hi; base += n) {
-      const int tt = base + r;
-      if (tt < hi) {
-        const double2 cc = tcoef[tt];
-        const uint4 mw = tmeta[tt];
-        const uint32_t w[4] = {mw.x, mw.y, mw.z, mw.w};
-        const cd c = {cc.x, cc.y};
-        const int eq = (int)(w[3] >> 24);
-        if constexpr (K == 0) {
-          lds_add(&vt[eq], c);
-        } else {
-          int vv[K], ee[K];
-          cd P[K], phi[K];
-          cd run = c;
-#pragma unroll
-          for (int m = 0; m < K; ++m) {
-            const int byte = (w[(m + 1) >> 2] >> (8 * ((m + 1) & 3))) & 0xff;
-            ee[m] = byte >> 4;
-            vv[m] = byte & 15;
-            phi[m] = ld(&xp[vv[m] * emax + ee[m] - 1]);
-          }
-#pragma unroll
-          for (int m = 0; m < K; ++m) {
-            run = cmul(run, phi[m]);
-            P[m] = run;
-          }
-          lds_add(&vt[eq], run);
-          double2 *jrow = &G->J[eq][0];
-          cd S = sigma;
-#pragma unroll
-          for (int m = K - 1; m >= 0; --m) {
-            const cd left = (m == 0) ? c : P[m > 0 ? m - 1 : 0];
-            cd d = CPLX ? cmul(left, S) : (m == K - 1 ? cscale(left, S.re) : cmul(left, S));
-            if (ee[m] > 1) {
-              const cd q = ld(&xp[vv[m] * emax + ee[m] - 2]);
-              d = cmul(d, cscale(q, (double)ee[m]));
-            }
-            lds_add(&jrow[vv[m]], d);
-            if (m > 0)
-              S = (m == K - 1 && !CPLX) ? cscale(phi[m], S.re) : cmul(S, phi[m]);
-          }
-        }
+      for (int base = lo; base < hi; base += n) {
+        const int tt = base + r;
+        if (tt < hi) one_term<K, CPLX>(tcoef[tt], tmeta[tt], sigma, vt);
+      }
+    } else {
+      const int last = hi - 1;
+      int ti = lo + r < last ? lo + r : last;
+      double2 pc = gc[ti];
+      uint4 pm = gm[ti];
+#pragma nounroll
+      for (int base = lo; base < hi; base += n) {
+        const int tt = base + r;
+        const double2 cc = pc;
+        const uint4 mw = pm;
+        ti = tt + n < last ? tt + n : last;
+        pc = gc[ti];
+        pm = gm[ti];
+        if (tt < hi) one_term<K, CPLX>(cc, mw, sigma, vt);
       }
     }
   }
