@@ -203,10 +203,6 @@ struct Tracker {
   }
 
   // ------------------------------------------------------------------ eval
-  // Terms with exactly K factors: this lane takes terms lo + r, lo + r + n, ...
-  // Term values go to vt[eq] unscaled; partial derivatives go to J[eq][v]
-  // times sigma (the backward sweep starts from sigma): sigma = t for f
-  // (CPLX false: real) and gamma (1 - t) for a general start system g.
   // One term c * prod phi_m: value to vt[eq], partials times sigma to J[eq][.].
   template <int K, bool CPLX>
   __device__ __forceinline__ void one_term(const double2 cc, const uint4 mw, cd sigma,
