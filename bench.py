@@ -32,12 +32,12 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 TRAFFIC_PROFILE = {
     "workload": "cyclic8",
     "sources_sha256": {
-        "tracker.hip": "b94dad49817963e56eb37286044992017de1210b7181ac1e9d2384295516dfcd",
+        "tracker.hip": "67f23e3a4c4c1e14776316a95dfcedb27422619c2ff71889dd27b9cbd0ace2af",
         "hp_internal.hpp": "64ebf229d4058cabc9f7f8becee4fe35f0ae258e57177d767e6d57e22754445b",
         "hp_device.hpp": "a6d29c9a468b66c02d70054e33dbfdf6215e4ed3f10d96f59df50875c25877c1",
     },
-    "fetch_kib": 255.0, "fetch_scale": 262144 / 131088.875,
-    "write_kib": 8463.4375, "write_scale": 262144 / 262144,
+    "fetch_kib": 263.5, "fetch_scale": 262144 / 131088.0625,
+    "write_kib": 8465.3125, "write_scale": 262144 / 262144,
 }
 
 WORKLOADS = {
