@@ -68,6 +68,11 @@ __device__ __forceinline__ void lds_add(double2 *p, cd v) {
   __hip_atomic_fetch_add(q + 1, v.im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+__device__ __forceinline__ void lds_add2(double *re, double *im, cd v) {
+  __hip_atomic_fetch_add(re, v.re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __hip_atomic_fetch_add(im, v.im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 // Orders the LDS accesses of the (single-wavefront) workgroup.
 __device__ __forceinline__ void wsync() { __syncthreads(); }

@@ -98,9 +98,10 @@ constexpr size_t kCtlBytes = 64 * 8;
 // power table [n][emax] follows it.
 template <int NMAX>
 struct GroupLds {
-  double2 J[NMAX][NMAX + 1];  // Jacobian accumulator of f (rows padded: bank spread)
-  double2 fv[NMAX];       // f values
-  double2 gv[NMAX];       // g values (general start system)
+  double Jre[NMAX][NMAX + 1];  // Jacobian accumulator, real parts (rows padded)
+  double Jim[NMAX][NMAX + 1];  // imaginary parts
+  double fre[NMAX], fim[NMAX];  // f values
+  double gre[NMAX], gim[NMAX];  // g values (general start system)
   double2 prow[NMAX + 1]; // normalised pivot row, [NMAX] = right-hand side
   double2 dsol[NMAX];     // solution of the last linear solve
   double cand[NMAX];      // pivot candidates

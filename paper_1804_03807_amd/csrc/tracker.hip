@@ -16,7 +16,9 @@
 // terms of a system by their number of factors k; the lanes of a group take
 // consecutive terms of one k at a time, so every lane runs the same
 // straight-line code, and add the partial derivatives into the path's
-// Jacobian in LDS (ds_add_f64).  Linear systems are solved by Gauss-Jordan
+// Jacobian in LDS (ds_add_f64), whose real and imaginary parts are separate
+// planes so that the 8-byte atomics of a group's lanes spread over the
+// banks.  Linear systems are solved by Gauss-Jordan
 // elimination with partial pivoting (largest |re|+|im| in the column, ties
 // to the lowest row), one row per lane: the pivot search is a DPP butterfly
 // in registers when the groups are aligned (n = 2, 4, 8), else an exchange
@@ -88,7 +90,7 @@ struct Tracker {
   bool leader;  // r == 0 of a real group
   // ---- LDS region of this lane's group (compile-time strides) ----
   GroupLds<NMAX> *G;
-  double2 *Jr;    // own row of the Jacobian accumulator
+  double *Jrr, *Jri;  // own row of the Jacobian accumulator (real, imaginary)
   double2 *xp;    // [n][emax] powers x_v^e, e = 1..emax (after the fixed part)
   long long *ctl; // [64] refill broadcast (wave-wide)
   // ---- per-path state (replicated in the group's lanes) ----
@@ -157,7 +159,8 @@ struct Tracker {
     deg_r = sp->deg[r < n ? r : 0];
     char *g = smem + kCtlBytes + tbytes + (size_t)grp * group_lds_bytes(NMAX, emax);
     G = (GroupLds<NMAX> *)g;
-    Jr = &G->J[r][0];
+    Jrr = &G->Jre[r][0];
+    Jri = &G->Jim[r][0];
     xp = (double2 *)(g + sizeof(GroupLds<NMAX>));
   }
 
@@ -206,12 +209,12 @@ struct Tracker {
   // One term c * prod phi_m: value to vt[eq], partials times sigma to J[eq][.].
   template <int K, bool CPLX>
   __device__ __forceinline__ void one_term(const double2 cc, const uint4 mw, cd sigma,
-                                           double2 *vt) {
+                                           double *vre, double *vim) {
     const uint32_t w[4] = {mw.x, mw.y, mw.z, mw.w};
     const cd c = {cc.x, cc.y};
     const int eq = (int)(w[3] >> 24);
     if constexpr (K == 0) {
-      lds_add(&vt[eq], c);
+      lds_add2(&vre[eq], &vim[eq], c);
     } else {
       int vv[K], ee[K];
       cd P[K], phi[K];
@@ -228,8 +231,9 @@ struct Tracker {
         run = cmul(run, phi[m]);
         P[m] = run;
       }
-      lds_add(&vt[eq], run);
-      double2 *jrow = &G->J[eq][0];
+      lds_add2(&vre[eq], &vim[eq], run);
+      double *jre = &G->Jre[eq][0];
+      double *jim = &G->Jim[eq][0];
       cd S = sigma;
 #pragma unroll
       for (int m = K - 1; m >= 0; --m) {
@@ -239,7 +243,7 @@ struct Tracker {
           const cd q = ld(&xp[vv[m] * emax + ee[m] - 2]);
           d = cmul(d, cscale(q, (double)ee[m]));
         }
-        lds_add(&jrow[vv[m]], d);
+        lds_add2(&jre[vv[m]], &jim[vv[m]], d);
         if (m > 0) S = (m == K - 1 && !CPLX) ? cscale(phi[m], S.re) : cmul(S, phi[m]);
       }
     }
@@ -254,14 +258,14 @@ struct Tracker {
   // the lane's next term is read while this one is processed.
   template <int K, bool LDS, bool CPLX>
   __device__ __forceinline__ void terms_k(int lo, int hi, const double2 *gc, const uint4 *gm,
-                                          cd sigma, double2 *vt) {
+                                          cd sigma, double *vre, double *vim) {
     if constexpr (LDS || K > 4) {
       const double2 *tcoef = LDS ? staged_coef() : gc;
       const uint4 *tmeta = LDS ? staged_meta() : gm;
 #pragma nounroll
       for (int base = lo; base < hi; base += n) {
         const int tt = base + r;
-        if (tt < hi) one_term<K, CPLX>(tcoef[tt], tmeta[tt], sigma, vt);
+        if (tt < hi) one_term<K, CPLX>(tcoef[tt], tmeta[tt], sigma, vre, vim);
       }
     } else {
       const int last = hi - 1;
@@ -276,18 +280,18 @@ struct Tracker {
         ti = tt + n < last ? tt + n : last;
         pc = gc[ti];
         pm = gm[ti];
-        if (tt < hi) one_term<K, CPLX>(cc, mw, sigma, vt);
+        if (tt < hi) one_term<K, CPLX>(cc, mw, sigma, vre, vim);
       }
     }
   }
 
   template <int K, bool LDS, bool CPLX>
   __device__ __forceinline__ void terms_upto(const int *kk, const double2 *gc, const uint4 *gm,
-                                             cd sigma, double2 *vt) {
+                                             cd sigma, double *vre, double *vim) {
     if constexpr (K >= 0) {
-      terms_upto<K - 1, LDS, CPLX>(kk, gc, gm, sigma, vt);
+      terms_upto<K - 1, LDS, CPLX>(kk, gc, gm, sigma, vre, vim);
       const int lo = kk[K], hi = kk[K + 1];
-      if (lo < hi) terms_k<K, LDS, CPLX>(lo, hi, gc, gm, sigma, vt);
+      if (lo < hi) terms_k<K, LDS, CPLX>(lo, hi, gc, gm, sigma, vre, vim);
     }
   }
 
@@ -304,23 +308,30 @@ struct Tracker {
         st(&xp[r * emax + e - 1], p);
       }
 #pragma unroll
-      for (int j = 0; j < NMAX; ++j) Jr[j] = make_double2(0.0, 0.0);
-      G->fv[r] = make_double2(0.0, 0.0);
-      if constexpr (GEN) G->gv[r] = make_double2(0.0, 0.0);
+      for (int j = 0; j < NMAX; ++j) {
+        Jrr[j] = 0.0;
+        Jri[j] = 0.0;
+      }
+      G->fre[r] = 0.0;
+      G->fim[r] = 0.0;
+      if constexpr (GEN) {
+        G->gre[r] = 0.0;
+        G->gim[r] = 0.0;
+      }
     }
     wsync();
     const cd tsig = {te, 0.0};
     const int *kk = kCacheKp ? kpv : kpm;
-    if (staged) terms_upto<NMAX, true, false>(kk, gcoef, gmeta, tsig, G->fv);
-    else terms_upto<NMAX, false, false>(kk, gcoef, gmeta, tsig, G->fv);
+    if (staged) terms_upto<NMAX, true, false>(kk, gcoef, gmeta, tsig, G->fre, G->fim);
+    else terms_upto<NMAX, false, false>(kk, gcoef, gmeta, tsig, G->fre, G->fim);
     if constexpr (GEN) {
-      if (has_g) terms_upto<NMAX, false, true>(gkpm, ggcoef, ggmeta, s, G->gv);
+      if (has_g) terms_upto<NMAX, false, true>(gkpm, ggcoef, ggmeta, s, G->gre, G->gim);
     }
     wsync();
-    const cd f = ld(&G->fv[r]);
+    const cd f = {G->fre[r], G->fim[r]};
     cd g, sdg = {0.0, 0.0};
     if (GEN && has_g) {
-      g = ld(&G->gv[r]);
+      g = {G->gre[r], G->gim[r]};
     } else {
       // total-degree start system g_r = x_r^{d_r} - 1
       const int d = deg_r;
@@ -335,7 +346,7 @@ struct Tracker {
     b = csel(emode == EV_F, f, csel(emode == EV_H, hv, cd{-ht.re, -ht.im}));
 #pragma unroll
     for (int j = 0; j < NMAX; ++j) {
-      const cd v = ld(&Jr[j]);
+      const cd v = {Jrr[j], Jri[j]};
       A[j] = csel(j == r, cadd(v, sdg), v);
     }
   }
