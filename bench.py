@@ -32,12 +32,12 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 TRAFFIC_PROFILE = {
     "workload": "cyclic8",
     "sources_sha256": {
-        "tracker.hip": "67f23e3a4c4c1e14776316a95dfcedb27422619c2ff71889dd27b9cbd0ace2af",
-        "hp_internal.hpp": "64ebf229d4058cabc9f7f8becee4fe35f0ae258e57177d767e6d57e22754445b",
-        "hp_device.hpp": "a6d29c9a468b66c02d70054e33dbfdf6215e4ed3f10d96f59df50875c25877c1",
+        "tracker.hip": "6492a16b9465eaee80ca23c26ede10731dbbbde3c4d79b6614a639f3aed8c089",
+        "hp_internal.hpp": "c7f8cece0fea903bcf92b428c942c27b08d75e01276364113c38025c3bd5db70",
+        "hp_device.hpp": "f174e9baadd11815ab244a02b2dd3a227cd609097421486823a63c8ca0c37d6d",
     },
-    "fetch_kib": 263.5, "fetch_scale": 262144 / 131088.0625,
-    "write_kib": 8465.3125, "write_scale": 262144 / 262144,
+    "fetch_kib": 264.5, "fetch_scale": 262144 / 131088.25,
+    "write_kib": 8472.90625, "write_scale": 262144 / 262144,
 }
 
 WORKLOADS = {
