@@ -205,7 +205,8 @@ int32_t pack_terms(Packed &P, const hp_system *f, int32_t term_base) {
   int32_t kp[hp::kKSlots];
   size_t pos = 0;
   for (int k = 0; k <= HP_MAX_N; ++k) {
-    kp[k] = (int32_t)(P.terms.size()) - term_base;
+    const size_t cls = P.terms.size();
+    kp[k] = (int32_t)cls - term_base;
     while (pos < order.size() && order[pos].first == k) {
       const int t = order[pos].second;
       DevTerm T;
@@ -223,6 +224,14 @@ int32_t pack_terms(Packed &P, const hp_system *f, int32_t term_base) {
       std::memcpy(T.w, bytes, 16);
       P.terms.push_back(T);
       ++pos;
+    }
+    // flag the chunks of this class whose terms all lie in one equation
+    for (size_t c0 = cls; c0 < P.terms.size(); c0 += (size_t)n) {
+      const size_t c1 = std::min(P.terms.size(), c0 + (size_t)n);
+      bool uni = true;
+      for (size_t i = c0 + 1; i < c1; ++i) uni = uni && P.terms[i].w[3] >> 24 == P.terms[c0].w[3] >> 24;
+      if (uni)
+        for (size_t i = c0; i < c1; ++i) P.terms[i].w[0] |= hp::kChunkUniform;
     }
   }
   kp[HP_MAX_N + 1] = (int32_t)P.terms.size() - term_base;

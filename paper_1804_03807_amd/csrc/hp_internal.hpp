@@ -19,7 +19,11 @@ constexpr int kKSlots = HP_MAX_N + 2;
 // One term c * prod x_v^e of equation i.  On the device the coefficient and
 // the 16-byte factor word live in two arrays (16-byte strides keep the lanes
 // of a group on distinct LDS banks).  Factor word: byte 0 = number of
-// factors k (<= HP_MAX_N), bytes 1..k = (v | e << 4), byte 15 = equation i.
+// factors k (<= HP_MAX_N) in its low bits, plus kChunkUniform when every
+// term of the term's chunk (the n consecutive terms of its k class that one
+// group of n lanes takes at once) belongs to the same equation; bytes 1..k =
+// (v | e << 4), byte 15 = equation i.
+constexpr uint32_t kChunkUniform = 0x80;
 struct alignas(32) DevTerm {
   double cre, cim;
   uint32_t w[4];

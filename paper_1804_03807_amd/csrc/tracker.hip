@@ -43,13 +43,16 @@ namespace hp {
 // CTRL: quad_perm [1,0,3,2] (0xB1, lane ^ 1), quad_perm [2,3,0,1] (0x4E,
 // lane ^ 2) or row_half_mirror (0x141, lane 7 - lane within 8).
 template <int CTRL>
-__device__ __forceinline__ double dpp_max_step(double v, int &idx) {
+__device__ __forceinline__ double dpp_double(double v) {
   const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
   const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)bits, CTRL, 0xf, 0xf, false);
   const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(bits >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_max_step(double v, int &idx) {
+  const double ov = dpp_double<CTRL>(v);
   const int oi = __builtin_amdgcn_mov_dpp(idx, CTRL, 0xf, 0xf, false);
-  const double ov =
-      __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
   const bool take = (ov > v) || (ov == v && oi < idx);
   idx = take ? oi : idx;
   return take ? ov : v;
@@ -206,15 +209,54 @@ struct Tracker {
   }
 
   // ------------------------------------------------------------------ eval
-  // One term c * prod phi_m: value to vt[eq], partials times sigma to J[eq][.].
-  template <int K, bool CPLX>
-  __device__ __forceinline__ void one_term(const double2 cc, const uint4 mw, cd sigma,
-                                           double *vre, double *vim) {
+  // Groups of 2, 4 or 8 aligned lanes: cross-lane sums and maxima in
+  // registers (DPP) instead of LDS.
+  __device__ __forceinline__ bool dpp_groups() const {
+    return n == 2 || n == 4 || (n == 8 && NMAX >= 8);
+  }
+
+  // Sum of v over this lane's group (DPP butterfly: xor 1, xor 2 within
+  // quads, mirror within 8 lanes); every lane of the wave must be active.
+  __device__ __forceinline__ cd group_sum_dpp(cd v) {
+    v.re += dpp_double<0xB1>(v.re);
+    v.im += dpp_double<0xB1>(v.im);
+    if (n >= 4) {
+      v.re += dpp_double<0x4E>(v.re);
+      v.im += dpp_double<0x4E>(v.im);
+    }
+    if (n >= 8) {
+      v.re += dpp_double<0x141>(v.re);
+      v.im += dpp_double<0x141>(v.im);
+    }
+    return v;
+  }
+
+  // Adds the term values of one chunk (the n consecutive terms a group takes
+  // at once) into vt[eq] for DPP-aligned groups.  When every chunk of the
+  // wave lies in one equation (the host flags such chunks), the group sums
+  // its values in registers and lane 0 makes the one LDS add; otherwise
+  // every lane with a term adds its own (same-address atomics serialise).
+  __device__ __forceinline__ void add_values(bool act, bool uni, int eq, cd v, double *vre,
+                                             double *vim) {
+    if (ballot(act && !uni) == 0) {
+      v = group_sum_dpp(v);
+      if (act && r == 0) lds_add2(&vre[eq], &vim[eq], v);
+    } else if (act) {
+      lds_add2(&vre[eq], &vim[eq], v);
+    }
+  }
+
+  // One term c * prod phi_m: partials times sigma go to J[eq][.]; the value
+  // goes to vt[eq] (DV false) or is returned for add_values (DV true).
+  template <int K, bool CPLX, bool DV>
+  __device__ __forceinline__ cd one_term(const double2 cc, const uint4 mw, cd sigma,
+                                         double *vre, double *vim) {
     const uint32_t w[4] = {mw.x, mw.y, mw.z, mw.w};
     const cd c = {cc.x, cc.y};
     const int eq = (int)(w[3] >> 24);
     if constexpr (K == 0) {
-      lds_add2(&vre[eq], &vim[eq], c);
+      if constexpr (!DV) lds_add2(&vre[eq], &vim[eq], c);
+      return c;
     } else {
       int vv[K], ee[K];
       cd P[K], phi[K];
@@ -231,7 +273,7 @@ struct Tracker {
         run = cmul(run, phi[m]);
         P[m] = run;
       }
-      lds_add2(&vre[eq], &vim[eq], run);
+      if constexpr (!DV) lds_add2(&vre[eq], &vim[eq], run);
       double *jre = &G->Jre[eq][0];
       double *jim = &G->Jim[eq][0];
       cd S = sigma;
@@ -246,6 +288,7 @@ struct Tracker {
         lds_add2(&jre[vv[m]], &jim[vv[m]], d);
         if (m > 0) S = (m == K - 1 && !CPLX) ? cscale(phi[m], S.re) : cmul(S, phi[m]);
       }
+      return run;
     }
   }
 
@@ -256,7 +299,7 @@ struct Tracker {
   // From the staged table (LDS) a term is read where it is used; from global
   // memory (large systems: many terms of at most a few factors per class)
   // the lane's next term is read while this one is processed.
-  template <int K, bool LDS, bool CPLX>
+  template <int K, bool LDS, bool CPLX, bool DV>
   __device__ __forceinline__ void terms_k(int lo, int hi, const double2 *gc, const uint4 *gm,
                                           cd sigma, double *vre, double *vim) {
     if constexpr (LDS || K > 4) {
@@ -265,7 +308,18 @@ struct Tracker {
 #pragma nounroll
       for (int base = lo; base < hi; base += n) {
         const int tt = base + r;
-        if (tt < hi) one_term<K, CPLX>(tcoef[tt], tmeta[tt], sigma, vre, vim);
+        const bool act = tt < hi;
+        if constexpr (DV) {
+          cd v = {0.0, 0.0};
+          uint4 mw = {0u, 0u, 0u, 0u};
+          if (act) {
+            mw = tmeta[tt];
+            v = one_term<K, CPLX, true>(tcoef[tt], mw, sigma, vre, vim);
+          }
+          add_values(act, (mw.x & kChunkUniform) != 0, (int)(mw.w >> 24), v, vre, vim);
+        } else {
+          if (act) one_term<K, CPLX, false>(tcoef[tt], tmeta[tt], sigma, vre, vim);
+        }
       }
     } else {
       const int last = hi - 1;
@@ -280,18 +334,25 @@ struct Tracker {
         ti = tt + n < last ? tt + n : last;
         pc = gc[ti];
         pm = gm[ti];
-        if (tt < hi) one_term<K, CPLX>(cc, mw, sigma, vre, vim);
+        const bool act = tt < hi;
+        if constexpr (DV) {
+          cd v = {0.0, 0.0};
+          if (act) v = one_term<K, CPLX, true>(cc, mw, sigma, vre, vim);
+          add_values(act, (mw.x & kChunkUniform) != 0, (int)(mw.w >> 24), v, vre, vim);
+        } else {
+          if (act) one_term<K, CPLX, false>(cc, mw, sigma, vre, vim);
+        }
       }
     }
   }
 
-  template <int K, bool LDS, bool CPLX>
+  template <int K, bool LDS, bool CPLX, bool DV>
   __device__ __forceinline__ void terms_upto(const int *kk, const double2 *gc, const uint4 *gm,
                                              cd sigma, double *vre, double *vim) {
     if constexpr (K >= 0) {
-      terms_upto<K - 1, LDS, CPLX>(kk, gc, gm, sigma, vre, vim);
+      terms_upto<K - 1, LDS, CPLX, DV>(kk, gc, gm, sigma, vre, vim);
       const int lo = kk[K], hi = kk[K + 1];
-      if (lo < hi) terms_k<K, LDS, CPLX>(lo, hi, gc, gm, sigma, vre, vim);
+      if (lo < hi) terms_k<K, LDS, CPLX, DV>(lo, hi, gc, gm, sigma, vre, vim);
     }
   }
 
@@ -322,10 +383,16 @@ struct Tracker {
     wsync();
     const cd tsig = {te, 0.0};
     const int *kk = kCacheKp ? kpv : kpm;
-    if (staged) terms_upto<NMAX, true, false>(kk, gcoef, gmeta, tsig, G->fre, G->fim);
-    else terms_upto<NMAX, false, false>(kk, gcoef, gmeta, tsig, G->fre, G->fim);
+    // DPP value sums only where the groups are aligned (wave-uniform choice)
+    if (dpp_groups()) {
+      if (staged) terms_upto<NMAX, true, false, true>(kk, gcoef, gmeta, tsig, G->fre, G->fim);
+      else terms_upto<NMAX, false, false, true>(kk, gcoef, gmeta, tsig, G->fre, G->fim);
+    } else {
+      if (staged) terms_upto<NMAX, true, false, false>(kk, gcoef, gmeta, tsig, G->fre, G->fim);
+      else terms_upto<NMAX, false, false, false>(kk, gcoef, gmeta, tsig, G->fre, G->fim);
+    }
     if constexpr (GEN) {
-      if (has_g) terms_upto<NMAX, false, true>(gkpm, ggcoef, ggmeta, s, G->gre, G->gim);
+      if (has_g) terms_upto<NMAX, false, true, false>(gkpm, ggcoef, ggmeta, s, G->gre, G->gim);
     }
     wsync();
     const cd f = {G->fre[r], G->fim[r]};
@@ -369,7 +436,7 @@ struct Tracker {
       if (k < n) {
         double best = -1.0;
         int p = -1;
-        if (n == 2 || n == 4 || (n == 8 && NMAX >= 8)) {
+        if (dpp_groups()) {
           // groups of 2, 4 or 8 aligned lanes: butterfly max over (value,
           // row) in registers (DPP: xor 1, xor 2 within quads, mirror
           // within 8 lanes), no LDS round trip
