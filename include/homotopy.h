@@ -128,6 +128,7 @@ typedef struct hp_server hp_server;
 
 /* Context on HIP device `device`.  Creates a stream of default priority. */
 int hp_context_create(int device, hp_context **out);
+/* Every plan and server made from ctx must be destroyed first. */
 void hp_context_destroy(hp_context *ctx);
 /* Message of the last failed call on this thread ("" if none). */
 const char *hp_last_error(void);
@@ -157,11 +158,17 @@ int hp_track_paths(hp_context *ctx, const hp_system *f, const hp_system *g, cons
                    int32_t *status, hp_path_stats *stats, int32_t mode);
 
 /* A plan: f packed and resident on the device, with a kernel variant chosen
- * (autotuned when tune != 0 and no cached choice exists). */
+ * (autotuned when tune != 0 and no cached choice exists).  Without tuning,
+ * a plan for n <= 8 whose terms have at most 1024 factors in all runs on a
+ * kernel specialised to f's support (variant 300 + n): its source is written
+ * and compiled (hiprtc) at plan creation, which takes up to a few seconds
+ * the first time a support is seen in the process; plans for systems of the
+ * same support share the compiled module.  Errors of that compilation are
+ * HP_E_DEVICE with the compiler log in hp_last_error. */
 int hp_plan_create(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
                    int32_t tune, hp_plan **out);
 void hp_plan_destroy(hp_plan *plan);
-/* Forces the kernel variant.  Two kernel families are compiled:
+/* Forces the kernel variant.  Three kernel families:
  *   n_max = 4, 8, 10, 12   group kernels: n lanes of a wavefront per path
  *                          (lane r owns equation r), floor(64/n) paths, for
  *                          any n <= n_max;
@@ -169,13 +176,24 @@ void hp_plan_destroy(hp_plan *plan);
  *                          wavefront, Jacobian in LDS, compiled for exactly
  *                          this n;
  *   200 + n (n = 7, 8)     lane kernels with 32 paths per wavefront (half the
- *                          LDS, for systems whose power table is large).
+ *                          LDS, for systems whose power table is large);
+ *   300 + n (n = 1..8)     the kernel specialised to the plan's system (one
+ *                          path per lane, [J | rhs] in registers, compiled at
+ *                          run time; total-degree start system only).
  * The variant must fit the system's n and its LDS must fit the device; 0
- * selects the default (the narrowest group kernel).  HP_E_INVALID_ARG for other values,
+ * selects the default (the specialised kernel where it applies, else the
+ * narrowest group kernel).  HP_E_INVALID_ARG for other values,
  * HP_E_UNSUPPORTED_N if the LDS does not fit.  The autotuner of
  * hp_plan_create times every candidate on a sample of the plan's paths and
  * caches the choice per system shape (file named by $HP_TUNE_CACHE). */
 int hp_plan_set_variant(hp_plan *plan, int32_t variant);
+
+/* Writes and compiles the kernel specialised to f (variant 300 + n) for
+ * gfx950 without loading it, so it needs no device; *code_bytes = size of
+ * the code object.  HP_E_UNSUPPORTED_N when f cannot have one (n > 8, or more
+ * than 1024 factors in all), HP_E_DEVICE when compilation fails (compiler log
+ * in hp_last_error), HP_E_INVALID_ARG for a malformed system. */
+int hp_spec_compile(const hp_system *f, int64_t *code_bytes);
 
 /* Device-memory call: tracks the paths whose ids are ids[0..n_paths-1]
  * (device int64 array; NULL means ids 0..n_paths-1).  Outputs are device

@@ -7,6 +7,7 @@ take torch tensors on the GPU (torch supplies device memory and streams).
 from __future__ import annotations
 
 import ctypes
+import weakref
 
 import numpy as np
 
@@ -17,7 +18,7 @@ from ._lib import (CONVERGED, DIVERGED, FAILED_MAXSTEPS, FAILED_MINSTEP, FAILED_
 
 __all__ = [
     "Context", "Plan", "Server", "default_tolerances", "path_count", "batch_layout",
-    "find_duplicates", "CONVERGED", "DIVERGED", "FAILED_MINSTEP", "FAILED_MAXSTEPS",
+    "find_duplicates", "spec_compile", "CONVERGED", "DIVERGED", "FAILED_MINSTEP", "FAILED_MAXSTEPS",
     "FAILED_NEWTON_T1", "HP_PLAIN", "HP_BATCHED", "STATS_DTYPE", "HomotopyError",
 ]
 
@@ -61,6 +62,14 @@ def path_count(system) -> int:
     return int(load().hp_path_count(ctypes.byref(_SysView(system).c)))
 
 
+def spec_compile(system) -> int:
+    """Writes and compiles (hiprtc, gfx950) the kernel specialised to the
+    system's support without a device; returns the code object's size."""
+    out = ctypes.c_int64(0)
+    check(load().hp_spec_compile(ctypes.byref(_SysView(system).c), ctypes.byref(out)))
+    return int(out.value)
+
+
 def batch_layout(systems):
     views = [_SysView(s) for s in systems]
     arr = (HpSystem * len(views))(*[v.c for v in views])
@@ -89,9 +98,14 @@ class Context:
         h = ctypes.c_void_p()
         check(self._L.hp_context_create(int(device), ctypes.byref(h)))
         self.handle = h
+        self._children = weakref.WeakSet()  # plans and servers built on this context
 
     def close(self):
+        """Destroys the context, after every plan and server made from it (the
+        C library requires them gone first)."""
         if self.handle:
+            for c in list(self._children):
+                c.close()
             self._L.hp_context_destroy(self.handle)
             self.handle = None
 
@@ -181,6 +195,7 @@ class Plan:
         check(self._L.hp_plan_create(ctx.handle, ctypes.byref(self._view.c), _c64(gamma),
                                      ctypes.byref(self.tol), int(bool(tune)), ctypes.byref(h)))
         self.handle = h
+        ctx._children.add(self)
 
     def close(self):
         if self.handle:
@@ -235,6 +250,7 @@ class Server:
         h = ctypes.c_void_p()
         check(self._L.hp_server_create(ctx.handle, int(hbm_budget_bytes), ctypes.byref(h)))
         self.handle = h
+        ctx._children.add(self)
         self._keep = {}
 
     def submit(self, system, gamma, tol=None) -> int:

@@ -24,7 +24,7 @@ EXPORTED = [
     "hp_last_timing", "hp_path_count", "hp_track_paths", "hp_plan_create", "hp_plan_destroy",
     "hp_plan_set_variant", "hp_plan_track_device", "hp_batch_layout", "hp_track_batch",
     "hp_find_duplicates", "hp_solve", "hp_server_create", "hp_server_submit", "hp_server_poll",
-    "hp_server_wait", "hp_server_peak_bytes", "hp_server_destroy",
+    "hp_server_wait", "hp_server_peak_bytes", "hp_server_destroy", "hp_spec_compile",
 ]
 
 
@@ -110,6 +110,7 @@ def load():
             "hp_server_wait": (ctypes.c_int, [vp, i64, vp, vp, vp, P(ctypes.c_double)]),
             "hp_server_peak_bytes": (ctypes.c_int, [vp, P(ctypes.c_size_t)]),
             "hp_server_destroy": (None, [vp]),
+            "hp_spec_compile": (ctypes.c_int, [P(HpSystem), P(i64)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)

@@ -10,17 +10,42 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libhomotopy.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["tracker.hip", "lanes.hip", "hp_host.cpp"]
+SOURCES = ["tracker.hip", "lanes.hip", "hp_host.cpp", "hp_jit.cpp"]
+# headers the run-time specialised kernels are compiled with (hiprtc)
+JIT_HEADERS = [("homotopy.h", os.path.join(ROOT, "include", "homotopy.h")),
+               ("hp_internal.hpp", os.path.join(CSRC, "hp_internal.hpp")),
+               ("hp_device.hpp", os.path.join(CSRC, "hp_device.hpp")),
+               ("lane_track.hpp", os.path.join(CSRC, "lane_track.hpp")),
+               ("spec_track.hpp", os.path.join(CSRC, "spec_track.hpp"))]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # no packed FP32 instructions anywhere in device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result", "-Wno-pass-failed"]
 
 
+def write_jit_headers(path: str) -> None:
+    """The JIT header texts as C++ raw string literals (hp_jit.cpp includes them)."""
+    names, texts = [], []
+    for name, src in JIT_HEADERS:
+        with open(src) as fh:
+            text = fh.read()
+        if ")HPJIT\"" in text:
+            raise RuntimeError(f"{src}: contains the raw-string delimiter")
+        names.append(f'"{name}"')
+        texts.append('R"HPJIT(' + text + ')HPJIT"')
+    out = ("const char *const kJitHeaderNames[] = {" + ", ".join(names) + "};\n"
+           "const char *const kJitHeaderTexts[] = {\n" + ",\n".join(texts) + "};\n")
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        fh.write(out)
+    os.replace(tmp, path)
+
+
 def build(verbose: bool = False) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    inc = ["-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+    write_jit_headers(os.path.join(objdir, "hp_jit_headers.inc"))
+    inc = ["-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-I" + objdir]
     objs = []
     procs = []
     for src in SOURCES:
@@ -36,8 +61,8 @@ def build(verbose: bool = False) -> str:
         if p.wait() != 0:
             raise RuntimeError("hipcc failed")
     tmp = SO + ".tmp"
-    subprocess.run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp],
-                   check=True)
+    subprocess.run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp,
+                    "-lhiprtc"], check=True)
     os.replace(tmp, SO)
     return SO
 

@@ -1,7 +1,11 @@
 // Complex FP64 helpers shared by the tracker kernels (device code only).
 #pragma once
 
+#include <stdint.h>
+
+#ifndef __HIPCC_RTC__  // hiprtc declares the HIP device API itself
 #include <hip/hip_runtime.h>
+#endif
 
 namespace hp {
 
@@ -14,6 +18,14 @@ __device__ __forceinline__ cd csub(cd a, cd b) { return {a.re - b.re, a.im - b.i
 __device__ __forceinline__ cd cscale(cd a, double s) { return {a.re * s, a.im * s}; }
 __device__ __forceinline__ cd cmul(cd a, cd b) {
   return {fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
+}
+// acc + a*b
+__device__ __forceinline__ cd cfma(cd acc, cd a, cd b) {
+  return {fma(a.re, b.re, fma(-a.im, b.im, acc.re)), fma(a.re, b.im, fma(a.im, b.re, acc.im))};
+}
+// acc + a*r, r real
+__device__ __forceinline__ cd cfma_r(cd acc, cd a, double r) {
+  return {fma(a.re, r, acc.re), fma(a.im, r, acc.im)};
 }
 // acc - a*b
 __device__ __forceinline__ cd cfms(cd acc, cd a, cd b) {

@@ -25,6 +25,7 @@
 
 #include "homotopy.h"
 #include "hp_internal.hpp"
+#include "hp_jit.hpp"
 
 using hp::DevSys;
 using hp::DevTerm;
@@ -333,14 +334,17 @@ int nmax_for(int n) {
   return -1;
 }
 
-// Kernel variant codes: n_max (4, 8, 12) for the group kernels (n lanes per
-// path), 100 + n_max for the lane kernels with 64 paths per wavefront and
-// 200 + n_max for those with 32.
+// Kernel variant codes: n_max (4, 8, 10, 12) for the group kernels (n lanes
+// per path), 100 + n_max for the lane kernels with 64 paths per wavefront,
+// 200 + n_max for those with 32, and 300 + n for the kernel specialised to
+// the plan's system (one path per lane, compiled at run time).
 struct Kv {
   int code = 0;
   bool lanes = false;
+  bool spec = false;  // specialised to the plan's system (compiled at run time)
   int nmax = 0;
   int pw = 0;  // lane kernels: paths per wavefront
+  const hp::SpecModule *sm = nullptr;  // spec: the loaded module
 };
 
 bool kv_decode(int code, Kv &k) {
@@ -358,6 +362,12 @@ bool kv_decode(int code, Kv &k) {
       k.pw = v.pw;
       return true;
     }
+  if (code > 300 && code <= 300 + hp::kSpecMaxN) {
+    k.spec = true;
+    k.nmax = code - 300;  // one path per lane, one exact system
+    k.pw = hp::kLanes;
+    return true;
+  }
   return false;
 }
 
@@ -442,6 +452,7 @@ struct hp_plan {
   hp_tolerances tol{};
   hp_c64 gamma{};
   Kv kv;  // kernel variant
+  bool spec_default = false;  // default variant: the specialised kernel where it applies
   DevBuf start_dev;  // explicit start points [n_start][n] (general plans)
   // plain-mode state
   DevBuf px0, pt, ph, piv, pactive;
@@ -525,6 +536,7 @@ int check_lds(hp_context *ctx, size_t lds) {
 
 // LDS bytes per workgroup of variant k for the systems of P.
 size_t kv_lds(const Kv &k, const Packed &P) {
+  if (k.spec) return 0;
   return k.lanes ? hp::lanes_lds_bytes(k.nmax, k.pw, P.emax) : P.lds(k.nmax, false);
 }
 
@@ -534,7 +546,10 @@ size_t kv_lds(const Kv &k, const Packed &P) {
 int kv_occupancy(hp_context *ctx, const Kv &k, const Packed &P, size_t *lds, int *per_cu,
                  int *stage) {
   *stage = 0;
-  if (k.lanes) {
+  if (k.spec) {
+    *lds = 0;
+    HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k.sm->persistent, hp::kLanes, 0));
+  } else if (k.lanes) {
     *lds = kv_lds(k, P);
     int rc = check_lds(ctx, *lds);
     if (rc) return rc;
@@ -569,14 +584,15 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   if (!e0) e0 = ctx->ev0;
   if (!e1) e1 = ctx->ev1;
-  if (P.nl > k.nmax || (k.lanes && P.nmin != k.nmax))
+  if (P.nl > k.nmax || (k.lanes && P.nmin != k.nmax) ||
+      (k.spec && (P.sys.size() != 1 || P.nl != k.nmax || !k.sm)))
     return fail(HP_E_INVALID_ARG, "kernel variant does not match the systems' n");
   size_t lds = 0;
   int per_cu = 0, stage = 0;
   int rc = kv_occupancy(ctx, k, P, &lds, &per_cu, &stage);
   if (rc) return rc;
   // enough wavefronts to hold every path once, at most a full device
-  const int64_t per_wave = k.lanes ? k.pw : hp::kLanes / std::max(1, P.nl);
+  const int64_t per_wave = (k.lanes || k.spec) ? k.pw : hp::kLanes / std::max(1, P.nl);
   const int64_t want = (total_paths + per_wave - 1) / per_wave;
   const int64_t groups = std::min<int64_t>((int64_t)ctx->cus * per_cu, std::max<int64_t>(1, want));
   KArgs a;
@@ -595,21 +611,59 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
   a.stage = stage;
   HIP_TRY(hipMemsetAsync(dev.qhead.p, 0, P.sys.size() * sizeof(unsigned long long), s));
   HIP_TRY(hipEventRecord(e0, s));
-  if (k.lanes) HIP_TRY((hipError_t)hp_launch_lanes(k.nmax, k.pw, a, (int)groups, lds, s));
-  else HIP_TRY((hipError_t)hp_launch_persistent(k.nmax, P.general, a, (int)groups, lds, s));
+  if (k.spec) {
+    void *params[] = {&a};
+    HIP_TRY(hipModuleLaunchKernel(k.sm->persistent, (unsigned)groups, 1, 1, hp::kLanes, 1, 1, 0, s,
+                                  params, nullptr));
+  } else if (k.lanes) {
+    HIP_TRY((hipError_t)hp_launch_lanes(k.nmax, k.pw, a, (int)groups, lds, s));
+  } else {
+    HIP_TRY((hipError_t)hp_launch_persistent(k.nmax, P.general, a, (int)groups, lds, s));
+  }
   HIP_TRY(hipEventRecord(e1, s));
   if (groups_out) *groups_out = (int)groups;
   return HP_OK;
 }
 
+// The plan's system can have a kernel specialised to it.
+bool plan_spec_eligible(const hp_plan *plan) {
+  const Packed &P = plan->P;
+  return !P.general && P.sys.size() == 1 &&
+         hp::spec_eligible(plan->info.n, P.terms.data() + P.sys[0].term_base, P.sys[0].n_terms);
+}
+
+// Generates, compiles (hiprtc; cached per process) and loads the kernel
+// specialised to the plan's system.
+int spec_prepare(hp_plan *plan, Kv &k) {
+  const Packed &P = plan->P;
+  const DevSys &d = P.sys[0];
+  const std::string src = hp::spec_source(plan->info.n, d.deg, P.terms.data() + d.term_base, d.n_terms);
+  std::string log;
+  const int rc = hp::spec_get(plan->ctx->device, src, &k.sm, log);
+  if (rc) return fail(HP_E_DEVICE, "specialised kernel: " + std::string(hipGetErrorString((hipError_t)rc)) +
+                                       (log.empty() ? "" : "\n" + log));
+  return HP_OK;
+}
+
 int plan_variant(hp_plan *plan, int code) {
-  if (code == 0) code = kv_default(plan->info.n, plan->info.emax, plan->ctx->max_lds);
+  if (code == 0) {
+    code = (plan->spec_default && plan_spec_eligible(plan))
+               ? 300 + plan->info.n
+               : kv_default(plan->info.n, plan->info.emax, plan->ctx->max_lds);
+  }
   Kv k;
-  if (!kv_decode(code, k) || k.nmax < plan->info.n || (k.lanes && k.nmax != plan->info.n))
+  if (!kv_decode(code, k) || k.nmax < plan->info.n ||
+      ((k.lanes || k.spec) && k.nmax != plan->info.n))
     return fail(HP_E_INVALID_ARG, "no compiled kernel variant " + std::to_string(code) +
                                       " for n = " + std::to_string(plan->info.n));
-  if (k.lanes && plan->P.general)
+  if ((k.lanes || k.spec) && plan->P.general)
     return fail(HP_E_INVALID_ARG, "lane kernels track the total-degree start system only");
+  if (k.spec) {
+    if (!plan_spec_eligible(plan))
+      return fail(HP_E_INVALID_ARG, "system too large for a specialised kernel");
+    int rc = spec_prepare(plan, k);
+    if (rc) return rc;
+  }
   int rc = check_lds(plan->ctx, kv_lds(k, plan->P));
   if (rc) return rc;
   plan->kv = k;
@@ -656,7 +710,7 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
   a.stage = stage;
   HIP_TRY(hipEventRecord(ctx->ev0, s));
   HIP_TRY((hipError_t)hp_launch_plain_init(a, s));
-  const int64_t per_wave = k.lanes ? k.pw : hp::kLanes / n;
+  const int64_t per_wave = (k.lanes || k.spec) ? k.pw : hp::kLanes / n;
   const int wgs = (int)((n_paths + per_wave - 1) / per_wave);
   // every path ends within max_steps + 1 attempts plus the final Newton
   const int64_t max_launches = (int64_t)plan->tol.max_steps + 4;
@@ -664,8 +718,15 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
   unsigned int active = 1;
   while (active > 0 && launches < max_launches) {
     HIP_TRY(hipMemsetAsync(plan->pactive.p, 0, sizeof(unsigned int), s));
-    if (k.lanes) HIP_TRY((hipError_t)hp_launch_lanes_plain(k.nmax, k.pw, a, wgs, lds, s));
-    else HIP_TRY((hipError_t)hp_launch_plain_step(k.nmax, plan->P.general, a, wgs, lds, s));
+    if (k.spec) {
+      void *params[] = {&a};
+      HIP_TRY(hipModuleLaunchKernel(k.sm->plain, (unsigned)wgs, 1, 1, hp::kLanes, 1, 1, 0, s,
+                                    params, nullptr));
+    } else if (k.lanes) {
+      HIP_TRY((hipError_t)hp_launch_lanes_plain(k.nmax, k.pw, a, wgs, lds, s));
+    } else {
+      HIP_TRY((hipError_t)hp_launch_plain_step(k.nmax, plan->P.general, a, wgs, lds, s));
+    }
     HIP_TRY(hipMemcpyAsync(&active, plan->pactive.p, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     ++launches;
@@ -680,13 +741,7 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
 int autotune(hp_plan *plan) {
   const std::string key = tune_key(plan->info, plan->n_terms);
   const int cached = tune_lookup(key);
-  Kv ck;
-  if (cached && kv_decode(cached, ck) && ck.nmax >= plan->info.n &&
-      (!ck.lanes || (ck.nmax == plan->info.n && !plan->P.general)) &&
-      check_lds(plan->ctx, kv_lds(ck, plan->P)) == HP_OK) {
-    plan->kv = ck;
-    return HP_OK;
-  }
+  if (cached && plan_variant(plan, cached) == HP_OK) return HP_OK;
   hp_context *ctx = plan->ctx;
   // sample: a few resident rounds of the widest variant
   const int64_t sample = std::min<int64_t>(plan->info.paths, (int64_t)ctx->cus * 4 * 64 * 2);
@@ -696,10 +751,13 @@ int autotune(hp_plan *plan) {
   if ((rc = st.alloc((size_t)sample * sizeof(int32_t)))) return rc;
   double best = 1e300;
   Kv best_k = plan->kv;
-  for (int code : kv_candidates(plan->info.n, plan->P.emax, ctx->max_lds)) {
+  std::vector<int> cands = kv_candidates(plan->info.n, plan->P.emax, ctx->max_lds);
+  if (plan_spec_eligible(plan)) cands.insert(cands.begin(), 300 + plan->info.n);
+  for (int code : cands) {
     Kv k;
     if (!kv_decode(code, k) || check_lds(ctx, kv_lds(k, plan->P)) != HP_OK) continue;
     if (k.lanes && plan->P.general) continue;
+    if (k.spec && (rc = spec_prepare(plan, k))) return rc;
     double tms = 0.0;
     for (int rep = 0; rep < 2; ++rep) {  // the second repetition counts
       DevSys d = plan->P.sys[0];
@@ -736,7 +794,7 @@ namespace {
 // explicit start points (n_start of them, host memory, [n_start][n]).
 int plan_create(hp_context *ctx, const hp_system *f, const hp_system *g, const hp_c64 *start,
                 int64_t n_start, hp_c64 gamma, const hp_tolerances *tol, int32_t tune,
-                hp_plan **out) {
+                bool spec_default, hp_plan **out) {
   if (!ctx || !out) return fail(HP_E_INVALID_ARG, "NULL argument");
   *out = nullptr;
   int rc = check_tol(tol);
@@ -745,6 +803,7 @@ int plan_create(hp_context *ctx, const hp_system *f, const hp_system *g, const h
     return fail(HP_E_INVALID_ARG, "gamma must be finite and nonzero");
   std::unique_ptr<hp_plan> p(new hp_plan());
   p->ctx = ctx;
+  p->spec_default = spec_default;
   if ((rc = check_system(f, p->info))) return rc;
   SysInfo ginfo;
   if (g) {
@@ -788,7 +847,7 @@ extern "C" {
 
 int hp_plan_create(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
                    int32_t tune, hp_plan **out) {
-  return plan_create(ctx, f, nullptr, nullptr, 0, gamma, tol, tune, out);
+  return plan_create(ctx, f, nullptr, nullptr, 0, gamma, tol, tune, true, out);
 }
 
 void hp_plan_destroy(hp_plan *plan) {
@@ -796,6 +855,25 @@ void hp_plan_destroy(hp_plan *plan) {
   (void)hipSetDevice(plan->ctx->device);
   (void)hipStreamSynchronize(plan->ctx->stream);
   delete plan;
+}
+
+int hp_spec_compile(const hp_system *f, int64_t *code_bytes) {
+  if (!code_bytes) return fail(HP_E_INVALID_ARG, "NULL argument");
+  *code_bytes = 0;
+  SysInfo info;
+  int rc = check_system(f, info);
+  if (rc) return rc;
+  Packed P;
+  pack_append(P, f, info, hp_c64{1.0, 0.0}, info.paths, 0, 0, nullptr);
+  const DevSys &d = P.sys[0];
+  if (!hp::spec_eligible(f->n, P.terms.data(), d.n_terms))
+    return fail(HP_E_UNSUPPORTED_N, "system too large for a specialised kernel");
+  std::vector<char> code;
+  std::string log;
+  rc = hp::spec_compile(hp::spec_source(f->n, d.deg, P.terms.data(), d.n_terms), code, log);
+  if (rc) return fail(HP_E_DEVICE, "specialised kernel: " + log);
+  *code_bytes = (int64_t)code.size();
+  return HP_OK;
 }
 
 int hp_plan_set_variant(hp_plan *plan, int32_t variant) {
@@ -816,7 +894,7 @@ int hp_plan_track_device(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_
   hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
   const double t0 = now_ms();
   ctx->last = hp_timing{};
-  ctx->last.paths_per_wave = plan->kv.lanes ? plan->kv.pw : hp::kLanes / plan->info.n;
+  ctx->last.paths_per_wave = (plan->kv.lanes || plan->kv.spec) ? plan->kv.pw : hp::kLanes / plan->info.n;
   ctx->last.max_n = plan->kv.nmax;
   ctx->last.variant = plan->kv.code;
   if (n_paths == 0) return HP_OK;
@@ -852,7 +930,7 @@ int hp_track_paths(hp_context *ctx, const hp_system *f, const hp_system *g, cons
     return fail(HP_E_INVALID_ARG, "bad outputs");
   const double t0 = now_ms();
   hp_plan *plan = nullptr;
-  int rc = plan_create(ctx, f, g, start, n_paths, gamma, tol, 0, &plan);
+  int rc = plan_create(ctx, f, g, start, n_paths, gamma, tol, 0, false, &plan);
   if (rc) return rc;
   std::unique_ptr<hp_plan, void (*)(hp_plan *)> guard(plan, hp_plan_destroy);
   if (n_paths > plan->info.paths)

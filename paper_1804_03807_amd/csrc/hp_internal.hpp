@@ -4,7 +4,9 @@
 
 #include <stdint.h>
 
+#ifndef __HIPCC_RTC__  // hiprtc declares the HIP device API itself
 #include <hip/hip_runtime.h>
+#endif
 
 #include "homotopy.h"
 

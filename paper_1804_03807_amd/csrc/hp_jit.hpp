@@ -1,0 +1,44 @@
+// Kernels specialised at run time to one polynomial system (host side):
+// source generation, hiprtc compilation and a per-process module cache.
+// Not part of the C ABI.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "hp_internal.hpp"
+
+namespace hp {
+
+// Largest n of a specialised kernel: its [J | rhs] lives in registers.
+constexpr int kSpecMaxN = 8;
+// Largest total factor count (sum over terms of the factors) of a system
+// with a specialised kernel; bounds its code size and compile time.
+constexpr int kSpecMaxFactors = 1024;
+
+// True when a system of n unknowns with these packed terms (the total-degree
+// start system) can have a specialised kernel.
+bool spec_eligible(int n, const DevTerm *terms, int n_terms);
+
+// HIP source of the specialised kernels hp_spec_persistent and hp_spec_plain
+// for a system of n unknowns, start-system degrees deg[0..n-1] and terms in
+// packed order (sorted by factor count; the coefficients stay run-time data).
+std::string spec_source(int n, const int32_t *deg, const DevTerm *terms, int n_terms);
+
+// Compiles spec source for gfx950 through hiprtc (no device needed): the
+// code object in `code`, the compiler log in `log`.  hipSuccess or an error.
+int spec_compile(const std::string &src, std::vector<char> &code, std::string &log);
+
+// Loaded specialised kernels of one system on one device.
+struct SpecModule {
+  hipModule_t mod = nullptr;
+  hipFunction_t persistent = nullptr;
+  hipFunction_t plain = nullptr;
+};
+
+// Module for `src` on the current device, compiled and loaded at its first
+// request and kept until the process ends.  hipSuccess or an error (log in
+// `log`).
+int spec_get(int device, const std::string &src, const SpecModule **out, std::string &log);
+
+}  // namespace hp

@@ -15,79 +15,48 @@
 //                                    the right-hand side in column NMAX;
 //   entries after that:              powers x_v^e, v < n, e = 1 .. emax.
 //
-// Method (paper: Section 1 and the end of Section 2.1 for independent
-// paths and dynamic load balancing).  H(x,t) = gamma (1-t) g(x) + t f(x),
-// g_i = x_i^{d_i} - 1.  Each term c x^a is differentiated in reverse mode:
-// prefix products from the coefficient, then a backward sweep of suffix
-// products that starts from t, so that the partial derivatives arrive
-// already scaled by t while the term value stays unscaled (H_t = f - gamma
-// g needs f itself).  They are added into the lane's own entries (ds_add_f64:
-// no other lane touches them).  The linear systems are solved by LU with
+// Terms.  Each term c x^a is differentiated in reverse mode: prefix
+// products from the coefficient, then a backward sweep of suffix products
+// that starts from t, so that the partial derivatives arrive already scaled
+// by t while the term value stays unscaled (H_t = f - gamma g needs f
+// itself).  They are added into the lane's own entries (ds_add_f64: no
+// other lane touches them).  The linear systems are solved by LU with
 // partial pivoting (largest |re|+|im|, ties to the lowest row) on the LDS
 // rows of the lane; row exchanges only swap the row addresses each lane
-// keeps in registers.  Step control and the end game are those of the
-// library's documented reading (RK4 predictor, Newton corrector, halving /
-// doubling step size, final Newton and residual test at t = 1).
-//
-// Scheduling.  The persistent kernel refills idle lanes from one device
-// queue head per system (one atomicAdd per wavefront: ballot, popcount,
-// mbcnt), in place of the work crew's guarded next-job pointer (Section 1).
-// The plain kernel performs one step per launch for a fixed path -> lane
-// map with the path state in HBM.
+// keeps in registers.  Path state, step control and scheduling are shared
+// with the other lane kernels (lane_track.hpp).
 #include <hip/hip_runtime.h>
 
-#include "hp_device.hpp"
-#include "hp_internal.hpp"
+#include "lane_track.hpp"
 
 namespace hp {
 
-// Scalar-loadable (constant address space) views of read-only tables.
-template <class T>
-using cptr = const __attribute__((address_space(4))) T *;
-template <class T>
-__device__ __forceinline__ cptr<T> as_const(const T *p) {
-  return (cptr<T>)p;
-}
-
-// N: the number of unknowns, exact (a system of another n runs on another
-// instantiation), so every loop over unknowns is unrolled without guards.
+// PW: lanes that hold paths (lanes PW..63 stay idle).
 template <int N, int PW>
-struct Lanes {
+struct Lanes : LaneTrack<Lanes<N, PW>, N> {
+  using Base = LaneTrack<Lanes<N, PW>, N>;
+  using Base::a;
+  using Base::lane;
+  using Base::slot;
+  using Base::sp;
+  using Base::deg;
+  using Base::gamma;
+  using Base::xc;
   static constexpr int NMAX = N;
   static constexpr int n = N;
   static constexpr int kCols = NMAX + 1;     // J columns + right-hand side
   static constexpr int kEntry = PW * 16;     // bytes of one entry
   static constexpr int kJ = NMAX * kCols;    // entries of [J | rhs]
 
-  const KArgs &a;
-  const int lane;
-  const bool slot;  // lane holds paths (lane < PW)
   lds_char *base;   // this lane's double2 in entry 0
   // ---- current system (wave-uniform) ----
-  cptr<DevSys> sp;
   int emax;
-  int deg[NMAX];
   const double2 *tcoef;  // this system's terms (vector loads: their wait
   const uint4 *tmeta;    // counter is not shared with the LDS atomics)
   int kpv[N + 2];  // terms with k factors are this system's terms kpv[k] .. kpv[k+1]-1
-  cd gamma;
-  long long npaths, out_path_base, out_x_base, id_base;
-  const long long *ids;
-  // ---- path state ----
-  int mode, accepts, steps, rejections, newton_its, evals, solves;
-  long long qidx;
-  double t, h;
-  cd x0[NMAX], xc[NMAX], ks[NMAX];
 
-  __device__ Lanes(const KArgs &args, char *smem)
-      : a(args), lane(threadIdx.x & 63), slot((threadIdx.x & 63) < PW) {
+  __device__ Lanes(const KArgs &args, char *smem) : Base(args, (threadIdx.x & 63) < PW) {
     base = (lds_char *)smem + (slot ? lane : 0) * 16;
-    mode = M_IDLE;
-    t = h = 0.0;
-    qidx = 0;
-    accepts = steps = rejections = newton_its = evals = solves = 0;
-#pragma unroll
-    for (int i = 0; i < NMAX; ++i) x0[i] = xc[i] = ks[i] = {0.0, 0.0};
   }
 
   // ---- LDS entries of this lane ----
@@ -96,10 +65,8 @@ struct Lanes {
   __device__ __forceinline__ lds_char *xpent(int v, int e1) const { return ent(kJ + v * emax + e1); }
 
   __device__ __forceinline__ void load_system(int s) {
-    sp = as_const(a.sys) + s;
+    this->load_common(s);
     emax = sp->emax;
-#pragma unroll
-    for (int i = 0; i < NMAX; ++i) deg[i] = (i < n) ? sp->deg[i] : 1;
     tcoef = a.tcoef + sp->term_base;
     tmeta = a.tmeta + sp->term_base;
     {
@@ -107,12 +74,6 @@ struct Lanes {
 #pragma unroll
       for (int k = 0; k <= N + 1; ++k) kpv[k] = kp[k < N + 1 ? k : HP_MAX_N + 1];
     }
-    gamma = {sp->gre, sp->gim};
-    npaths = sp->n_paths;
-    out_path_base = sp->out_path_base;
-    out_x_base = sp->out_x_base;
-    ids = (const long long *)sp->ids;
-    id_base = sp->id_base;
   }
 
   // ------------------------------------------------------------------ eval
@@ -368,300 +329,29 @@ struct Lanes {
     }
   }
 
-  // ------------------------------------------------------------ start path
-  __device__ __forceinline__ void start_path(long long q) {
-    qidx = q;
-    const long long pid = ids ? ids[q] : id_base + q;
-    cptr<double> roots = as_const((const double *)a.roots) + 2 * sp->root_base;
+  // max_i |rhs_i| (after an EV_F evaluation: the residual ||f(x)||_inf)
+  __device__ __forceinline__ double residual() const {
+    double r = 0.0;
 #pragma unroll
-    for (int i = 0; i < NMAX; ++i) {
-      if (i < n) {
-        const long long kk = (pid / sp->radix[i]) % deg[i];
-        const int ri = sp->root_off[i] + (int)kk;
-        x0[i] = {roots[2 * ri], roots[2 * ri + 1]};
-      }
-    }
-    mode = M_TRACK;
-    t = 0.0;
-    h = a.tol.h_init;
-    accepts = steps = rejections = newton_its = evals = solves = 0;
-  }
-
-  __device__ __forceinline__ double vmax_mod(const cd v[NMAX]) const {
-    double m = 0.0;
-#pragma unroll
-    for (int i = 0; i < NMAX; ++i)
-      if (i < n) m = nmax(m, cmod(v[i]));
-    return m;
-  }
-
-  // ------------------------------------------------------------- one step
-  // One predictor-corrector attempt for TRACK paths, the final Newton for
-  // FINAL paths; fin_status >= 0 for paths that end here (endpoint x0).
-  // Phases, each one evaluation and (except 5) one solve:
-  //   0..3  RK4 stages (J k = -H_t), 4  Newton iterations (J dx = H),
-  //   5     residual f(x0) of paths that end in this step.
-  __device__ __forceinline__ void step(int &fin_status, double &fin_res) {
-    const DevTol &tol = a.tol;
-    const bool trk = (mode == M_TRACK);
-    const bool fnl = (mode == M_FINAL);
-    double hs = 0.0, tn = 1.0;
-    if (trk) {
-      if (h >= 1.0 - t) {
-        hs = 1.0 - t;
-        tn = 1.0;
-      } else {
-        hs = h;
-        tn = t + h;
-      }
-    }
-    const double th = t + 0.5 * hs;
-    const int maxit = trk ? tol.max_newton : tol.max_newton_final;
-    const double ntol = trk ? tol.tol_corr : tol.tol_final;
-    bool ok = trk, iter = false, conv = false;
-    int it = 0, fs = -1;
-    double prev = 0.0, nx = 0.0, res = 0.0;
-#pragma unroll
-    for (int i = 0; i < NMAX; ++i) xc[i] = x0[i];
-    int phase = ballot(trk) ? 0 : 4;
-    if (phase == 4) iter = fnl;
-    for (;;) {
-      if (phase == 4 && ballot(iter) == 0) {
-        // ---- step control ----
-        if (trk) {
-          ++steps;
-          if (ok && conv) {
-            t = tn;
-#pragma unroll
-            for (int i = 0; i < NMAX; ++i) x0[i] = xc[i];
-            if (++accepts == 3) {
-              h = (2.0 * h < tol.h_max) ? 2.0 * h : tol.h_max;
-              accepts = 0;
-            }
-          } else {
-            ++rejections;
-            h = 0.5 * h;
-            accepts = 0;
-          }
-        }
-        if (fnl) {
-#pragma unroll
-          for (int i = 0; i < NMAX; ++i) x0[i] = xc[i];
-        }
-        nx = vmax_mod(x0);
-        if (trk) {
-          if (nx > tol.div_radius) fs = HP_DIVERGED;
-          else if (t >= 1.0) mode = M_FINAL;
-          else if (h < tol.h_min) fs = HP_FAILED_MINSTEP;
-          else if (steps > tol.max_steps) fs = HP_FAILED_MAXSTEPS;
-        }
-        if (ballot(fs >= 0 || fnl) == 0) break;
-        phase = 5;
-#pragma unroll
-        for (int i = 0; i < NMAX; ++i) xc[i] = x0[i];
-      }
-      const double te = (phase == 0) ? (trk ? t : 1.0)
-                      : (phase == 1 || phase == 2) ? (trk ? th : 1.0)
-                      : (phase == 3 || phase == 4) ? tn : 1.0;
-      eval(phase < 4 ? EV_NEG_HT : (phase == 4 ? EV_H : EV_F), te);
-      if (phase == 5) {
-        // ---- residual ||f(x0)||_inf of ending paths, classification ----
-        double r = 0.0;
-#pragma unroll
-        for (int i = 0; i < NMAX; ++i)
-          if (i < n) r = nmax(r, cmod(ldl(jent(i, NMAX))));
-        res = r;
-        if (fnl) {
-          if (res <= tol.tol_residual && nx <= tol.div_radius) fs = HP_CONVERGED;
-          else if (nx > tol.div_radius) fs = HP_DIVERGED;
-          else fs = HP_FAILED_NEWTON_T1;
-        }
-        break;
-      }
-      bool sing;
-      cd dsl[NMAX];
-      solve(dsl, sing);
-      if (phase < 4) {
-        // ---- RK4 stage ----
-        ok = ok && !sing;
-        const double cnext = (phase == 2) ? hs : 0.5 * hs;
-        const double wk = (phase == 0 || phase == 3) ? 1.0 : 2.0;
-#pragma unroll
-        for (int i = 0; i < NMAX; ++i) {
-          ks[i] = csel(phase == 0, dsl[i], cadd(ks[i], cscale(dsl[i], wk)));
-          xc[i] = csel(phase == 3, cadd(x0[i], cscale(ks[i], hs / 6.0)),
-                       cadd(x0[i], cscale(dsl[i], cnext)));
-        }
-        if (phase == 3) {
-          if (trk) {
-            evals += 4;
-            solves += 4;
-          }
-          if (fnl) {
-#pragma unroll
-            for (int i = 0; i < NMAX; ++i) xc[i] = x0[i];
-          }
-          iter = (trk && ok) || fnl;
-        }
-        ++phase;
-        continue;
-      }
-      // ---- Newton iteration: x -= dx ----
-      if (iter && !sing) {
-#pragma unroll
-        for (int i = 0; i < NMAX; ++i) xc[i] = csub(xc[i], dsl[i]);
-      }
-      const double md = vmax_mod(dsl), mx = vmax_mod(xc);
-      if (iter) {
-        ++it;
-        ++newton_its;
-        ++evals;
-        ++solves;
-        const bool finite = (md < INFINITY) && (mx < INFINITY);
-        if (sing || !finite) {
-          iter = false;
-        } else if (md <= ntol * (mx > 1.0 ? mx : 1.0)) {
-          conv = true;
-          iter = false;
-        } else if (trk && it >= 2 && md > 0.5 * prev) {
-          iter = false;
-        } else {
-          prev = md;
-          if (it >= maxit) iter = false;
-        }
-      }
-    }
-    fin_status = fs;
-    fin_res = res;
-  }
-
-  __device__ __forceinline__ void write_out(int fs, double res) {
-    double2 *e = a.endpoints + out_x_base + qidx * n;
-#pragma unroll
-    for (int i = 0; i < NMAX; ++i)
-      if (i < n) e[i] = make_double2(x0[i].re, x0[i].im);
-    const long long o = out_path_base + qidx;
-    a.status[o] = fs;
-    if (a.stats) {
-      hp_path_stats *s = a.stats + o;
-      s->steps = steps;
-      s->rejections = rejections;
-      s->newton_iters = newton_its;
-      s->evals = evals;
-      s->solves = solves;
-      s->pad = 0;
-      s->t_final = t;
-      s->residual = res;
-    }
+    for (int i = 0; i < NMAX; ++i) r = nmax(r, cmod(ldl(jent(i, NMAX))));
+    return r;
   }
 };
 
-// ------------------------------------------------------------------------
-// Persistent kernel: resident wavefronts loop until every system's queue is
-// drained; a wavefront moves to the next system once its queue is empty and
-// its own lanes are idle.
-// ------------------------------------------------------------------------
+// Persistent kernel (refilled from the device queue) and plain kernel (one
+// step per launch); see lane_persistent and lane_plain.
 template <int N, int PW>
 __global__ void __launch_bounds__(64) k_lanes(KArgs a) {
   extern __shared__ __align__(16) char smem[];
   Lanes<N, PW> tr(a, smem);
-  const int first_sys = blockIdx.x % a.n_systems;
-  for (int v = 0; v < a.n_systems; ++v) {
-    const int s = (first_sys + v) % a.n_systems;
-    tr.load_system(s);
-    bool exhausted = false;
-    for (;;) {
-      // ---- refill idle lanes: one atomic per wavefront ----
-      const bool idle = tr.slot && tr.mode == M_IDLE;
-      const uint64_t m = ballot(idle);
-      if (m != 0 && !exhausted) {
-        const unsigned cnt = __popcll(m);
-        const int first = __builtin_ctzll(m);
-        unsigned long long qb = 0;
-        if (tr.lane == first) qb = atomicAdd(&a.qhead[s], (unsigned long long)cnt);
-        qb = __shfl(qb, first);
-        const unsigned rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-        if (idle) {
-          const long long q = (long long)qb + rank;
-          if (q < tr.npaths) tr.start_path(q);
-        }
-        if ((long long)(qb + cnt) >= tr.npaths) exhausted = true;
-      }
-      if (ballot(tr.mode != M_IDLE) == 0) {
-        if (exhausted) break;  // this system is drained for this wavefront
-        continue;
-      }
-      // lanes past PW hold no LDS column: they sit out the step
-      if (tr.slot) {
-        int fs;
-        double res;
-        tr.step(fs, res);
-        if (fs >= 0) {
-          tr.write_out(fs, res);
-          tr.mode = M_IDLE;
-        }
-      }
-    }
-  }
+  lane_persistent(a, tr);
 }
 
-// ------------------------------------------------------------------------
-// Plain tracker: one step per launch.  Wavefront b owns queue indices
-// [PW b, PW b + PW) of system 0; path state lives in HBM between launches
-// (initialised by k_plain_init).
-// ------------------------------------------------------------------------
 template <int N, int PW>
 __global__ void __launch_bounds__(64) k_lanes_plain(KArgs a) {
   extern __shared__ __align__(16) char smem[];
   Lanes<N, PW> tr(a, smem);
-  tr.load_system(0);
-  const long long P = a.ps.P;
-  const long long q = (long long)blockIdx.x * PW + tr.lane;
-  const bool valid = tr.slot && q < tr.npaths;
-  const int md = valid ? a.ps.iv[q] : (int)M_IDLE;
-  if (ballot(md != M_IDLE) == 0) return;
-  tr.mode = md;
-  tr.qidx = q;
-  if (md != M_IDLE) {
-    tr.t = a.ps.t[q];
-    tr.h = a.ps.h[q];
-    tr.accepts = a.ps.iv[1 * P + q];
-    tr.steps = a.ps.iv[2 * P + q];
-    tr.rejections = a.ps.iv[3 * P + q];
-    tr.newton_its = a.ps.iv[4 * P + q];
-    tr.evals = a.ps.iv[5 * P + q];
-    tr.solves = a.ps.iv[6 * P + q];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      const double2 z = a.ps.x0[i * P + q];
-      tr.x0[i] = {z.x, z.y};
-    }
-  }
-  if (tr.slot) {
-    int fs;
-    double res;
-    tr.step(fs, res);
-    if (fs >= 0) {
-      tr.write_out(fs, res);
-      tr.mode = M_IDLE;
-    }
-  }
-  if (md != M_IDLE) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) a.ps.x0[i * P + q] = make_double2(tr.x0[i].re, tr.x0[i].im);
-    a.ps.t[q] = tr.t;
-    a.ps.h[q] = tr.h;
-    a.ps.iv[q] = tr.mode;
-    a.ps.iv[1 * P + q] = tr.accepts;
-    a.ps.iv[2 * P + q] = tr.steps;
-    a.ps.iv[3 * P + q] = tr.rejections;
-    a.ps.iv[4 * P + q] = tr.newton_its;
-    a.ps.iv[5 * P + q] = tr.evals;
-    a.ps.iv[6 * P + q] = tr.solves;
-  }
-  const uint64_t m = ballot(tr.mode != M_IDLE && valid);
-  if (tr.lane == 0 && m) atomicAdd(a.ps.active, (unsigned)__popcll(m));
+  lane_plain<Lanes<N, PW>, PW>(a, tr);
 }
 
 }  // namespace hp

@@ -1,0 +1,117 @@
+// One-path-per-lane tracker specialised to one polynomial system.  The
+// library writes the system's evaluator S at run time (straight-line code
+// with the support, exponents and start-system degrees compiled in; only the
+// coefficients are read from memory, through scalar loads) and compiles it
+// with this header through hiprtc.  Every index is then a compile-time
+// constant, so the Jacobian [J | rhs] of a lane's path lives in registers:
+// no LDS, no atomics, and the term loop is plain FP64 arithmetic.
+//
+// S provides
+//   static constexpr int N;
+//   static void eval(cptr<double2> cf, const cd (&x)[N], double te, cd s,
+//                    cd gamma, int emode, cd (&J)[N][N], cd (&b)[N]);
+// which writes J = t J_f + s J_g at (x, te) with s = gamma (1 - te), and
+// b = -H_t (EV_NEG_HT), H (EV_H) or f (EV_F), as the other kernels do.
+#pragma once
+
+#include "lane_track.hpp"
+
+namespace hp {
+
+// x0 and ks sit in the lane's LDS slots (RkLds: 2N x 1 KB per wavefront),
+// leaving the registers to [J | rhs].
+template <class S>
+struct Spec : LaneTrack<Spec<S>, S::N, RkLds<S::N>> {
+  static constexpr int N = S::N;
+  using Base = LaneTrack<Spec<S>, N, RkLds<N>>;
+  using Base::a;
+  using Base::sp;
+  using Base::gamma;
+  using Base::xc;
+
+  cptr<double2> coef;  // this system's term coefficients, in packed order
+  cd J[N][N];
+  cd b[N];
+
+  // lds: the wavefront's RkLds<N>::kBytes
+  __device__ Spec(const KArgs &args, lds_char *lds)
+      : Base(args, true, lds + (threadIdx.x & 63) * 16) {}
+
+  __device__ __forceinline__ void load_system(int s) {
+    this->load_common(s);
+    coef = as_const(a.tcoef) + sp->term_base;
+  }
+
+  __device__ __forceinline__ void eval(int emode, double te) {
+    S::eval(coef, xc, te, cscale(gamma, 1.0 - te), gamma, emode, J, b);
+    // Hand [J | rhs] over to the solve as opaque register values: otherwise
+    // the compiler interleaves the evaluation with the elimination and needs
+    // far more registers than either (scratch spills from n = 7 on).
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) asm volatile("" : "+v"(J[i][j].re), "+v"(J[i][j].im));
+      asm volatile("" : "+v"(b[i].re), "+v"(b[i].im));
+    }
+  }
+
+  // LU with partial pivoting (largest |re|+|im| in the column, ties to the
+  // lowest row) on the registers, then back substitution into dx.  A row
+  // exchange is a select per entry: the pivot row is data dependent and
+  // registers cannot be indexed by a lane-varying value.  sing: an exactly
+  // zero (or NaN) pivot.
+  __device__ __forceinline__ void solve(cd dx[N], bool &sing) {
+    sing = false;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double best = -1.0;
+      int p = k;
+#pragma unroll
+      for (int i = k; i < N; ++i) {
+        const double c = cabs1(J[i][k]);
+        const bool take = c > best;
+        best = take ? c : best;
+        p = take ? i : p;
+      }
+      if (!(best > 0.0)) sing = true;
+#pragma unroll
+      for (int i = k + 1; i < N; ++i) {
+        const bool sw = (i == p);
+#pragma unroll
+        for (int j = k; j < N; ++j) {
+          const cd u = J[k][j], v = J[i][j];
+          J[k][j] = csel(sw, v, u);
+          J[i][j] = csel(sw, u, v);
+        }
+        const cd u = b[k], v = b[i];
+        b[k] = csel(sw, v, u);
+        b[i] = csel(sw, u, v);
+      }
+      const cd inv = crecip_nr(J[k][k]);
+      J[k][k] = inv;  // kept for the back substitution
+#pragma unroll
+      for (int i = k + 1; i < N; ++i) {
+        const cd l = cmul(J[i][k], inv);
+#pragma unroll
+        for (int j = k + 1; j < N; ++j) J[i][j] = cfms(J[i][j], l, J[k][j]);
+        b[i] = cfms(b[i], l, b[k]);
+      }
+    }
+#pragma unroll
+    for (int k = N - 1; k >= 0; --k) {
+      cd y = b[k];
+#pragma unroll
+      for (int j = k + 1; j < N; ++j) y = cfms(y, J[k][j], dx[j]);
+      dx[k] = cmul(y, J[k][k]);
+    }
+  }
+
+  __device__ __forceinline__ double residual() const {
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r = nmax(r, cmod(b[i]));
+    return r;
+  }
+};
+
+}  // namespace hp

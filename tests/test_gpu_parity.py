@@ -153,15 +153,18 @@ def test_ids_list_matches_direct(ctx):
     import paper_1804_03807_amd as hp
     wl = W.cyclic_workload(6, 9)
     s = wl.systems[0]
-    e1, s1, _ = ctx.track_paths(s, wl.gammas[0])
     ids = np.array([5, 700, 3, 3, 100, 719, 0], np.int64)
     plan = ctx.plan(s, wl.gammas[0])
+    ea, sa, _ = plan.outputs(s.bezout())
+    plan.track_device(ea, sa)  # every path, in id order
     e, st, sts = plan.outputs(len(ids))
     dids = torch.from_numpy(ids).cuda()
     plan.track_device(e, st, sts, ids=dids)
     torch.cuda.synchronize()
+    e1, s1 = hp.Plan.endpoints_to_numpy(ea), sa.cpu().numpy()
     assert np.array_equal(st.cpu().numpy(), s1[ids])
     assert np.array_equal(hp.Plan.endpoints_to_numpy(e), e1[ids])
+    plan.close()
 
 
 def test_forced_failure_statuses(ctx):

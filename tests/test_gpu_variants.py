@@ -1,6 +1,7 @@
-"""Every compiled kernel variant (group kernels: n lanes per path; lane
-kernels: one path per lane, Jacobian in LDS) against the CPU oracle on the
-same seeded inputs, in batched and plain mode."""
+"""Every kernel variant (group kernels: n lanes per path; lane kernels: one
+path per lane, Jacobian in LDS; kernels specialised to the system at run
+time: one path per lane, Jacobian in registers) against the CPU oracle on
+the same seeded inputs, in batched and plain mode."""
 import os
 import sys
 
@@ -16,6 +17,7 @@ pytestmark = pytest.mark.gpu
 NTHREADS = min(16, os.cpu_count() or 1)
 GROUP = [4, 8, 10, 12]
 LANES = [100 + n for n in range(1, 9)] + [207, 208]
+SPEC = [300 + n for n in range(1, 9)]
 
 
 def log(*a):
@@ -64,7 +66,7 @@ def run_variant(ctx, s, g, code, mode):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("code", GROUP + LANES)
+@pytest.mark.parametrize("code", GROUP + LANES + SPEC)
 def test_variant_matches_oracle(ctx, name, code):
     s, g = CASES[name]()
     if (code >= 100 and code % 100 != s.n) or code % 100 < s.n:
@@ -79,7 +81,8 @@ def test_variant_matches_oracle(ctx, name, code):
     assert (sts["residual"][st == 0] <= 1e-10).all()
 
 
-@pytest.mark.parametrize("name,code", [("cyclic4", 104), ("cyclic6", 106), ("dense8_d2", 208)])
+@pytest.mark.parametrize("name,code", [("cyclic4", 104), ("cyclic6", 106), ("dense8_d2", 208),
+                                       ("cyclic6", 306), ("dense8_d2", 308)])
 def test_lane_plain_equals_batched(ctx, name, code):
     s, g = CASES[name]()
     (e1, s1, t1), _ = run_variant(ctx, s, g, code, "batched")
@@ -94,7 +97,7 @@ def test_unknown_variant_rejected(ctx):
     import paper_1804_03807_amd as hp
     s, g = CASES["cyclic6"]()
     plan = ctx.plan(s, g)
-    for bad in (5, 104, 108, 207, 300, -1):
+    for bad in (5, 104, 108, 207, 300, 305, 309, -1):
         with pytest.raises(hp.HomotopyError):
             plan.set_variant(bad)
     plan.close()
@@ -116,7 +119,7 @@ def test_autotune_chooses_a_valid_variant(ctx, tmp_path, monkeypatch):
     torch.cuda.synchronize()
     code = ctx.last_timing()["variant"]
     log(f"autotuned variant {code}")
-    assert code in GROUP + LANES
+    assert code in GROUP + LANES + SPEC
     assert code < 100 or code % 100 == s.n
     text = cache.read_text().split()
     assert len(text) == 2 and int(text[1]) == code
@@ -130,3 +133,19 @@ def test_autotune_chooses_a_valid_variant(ctx, tmp_path, monkeypatch):
     torch.cuda.synchronize()
     assert ctx.last_timing()["variant"] == code
     plan2.close()
+
+
+@pytest.mark.parametrize("name", ["cyclic6", "dense8_d2"])
+def test_plan_default_is_specialised(ctx, name):
+    """Without tuning, a plan for n <= 8 runs on the kernel specialised to
+    its system (variant 300 + n), 64 paths per wavefront."""
+    import torch
+    s, g = CASES[name]()
+    plan = ctx.plan(s, g)
+    e, st, sts = plan.outputs(s.bezout())
+    plan.track_device(e, st, sts)
+    torch.cuda.synchronize()
+    t = ctx.last_timing()
+    assert t["variant"] == 300 + s.n
+    assert t["paths_per_wave"] == 64
+    plan.close()

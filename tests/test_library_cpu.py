@@ -79,3 +79,24 @@ def test_find_duplicates_matches_oracle(hp, oracle_lib):
     got = {tuple(p) for p in hp.find_duplicates(x, st)}
     ref = {tuple(p) for p in oracle.find_duplicates(x, st)}
     assert got == ref and len(ref) > 3
+
+
+@pytest.mark.parametrize("n", [3, 5, 8])
+def test_specialised_kernel_compiles(hp, n):
+    """The kernel specialised to a system's support is written and compiled
+    for gfx950 by the library itself (hiprtc), without a device."""
+    s = W.cyclic_system(n, np.random.default_rng(n))
+    assert hp.spec_compile(s) > 1000
+    d = W.dense_system(3, [3, 2, 2], np.random.default_rng(5))  # exponents above 1
+    assert hp.spec_compile(d) > 1000
+
+
+def test_specialised_kernel_limits(hp):
+    """n above 8 and systems with more than 1024 factors in all have none."""
+    with pytest.raises(hp.HomotopyError) as e:
+        hp.spec_compile(W.cyclic_system(9, np.random.default_rng(0)))
+    assert e.value.code == hp._lib.HP_E_UNSUPPORTED_N
+    big = W.dense_system(8, [3] * 8, np.random.default_rng(0))  # 8 x 165 terms
+    with pytest.raises(hp.HomotopyError) as e:
+        hp.spec_compile(big)
+    assert e.value.code == hp._lib.HP_E_UNSUPPORTED_N
