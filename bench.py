@@ -24,20 +24,24 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 
-# HBM bytes per k_persistent launch on the cyclic-8 workload from two
+# HBM bytes per launch of the kernel the bench times (the plan's default:
+# the kernel specialised to the cyclic-8 support, variant 308) from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each
 # scaled by what the counter reads for a 256 MiB device copy (FETCH_SIZE
 # reads half the copied bytes, WRITE_SIZE all of them).  Valid only for the
 # kernel sources they were taken on; reported as null once those change.
 TRAFFIC_PROFILE = {
     "workload": "cyclic8",
+    "variant": 308,
     "sources_sha256": {
-        "tracker.hip": "6492a16b9465eaee80ca23c26ede10731dbbbde3c4d79b6614a639f3aed8c089",
-        "hp_internal.hpp": "c7f8cece0fea903bcf92b428c942c27b08d75e01276364113c38025c3bd5db70",
-        "hp_device.hpp": "f174e9baadd11815ab244a02b2dd3a227cd609097421486823a63c8ca0c37d6d",
+        "spec_track.hpp": "631195aad601ec68dec03ec7c5f935ab06450d629319c25b4645962199a3bb6d",
+        "lane_track.hpp": "aed01d67c6847aef3b8f0f99d499d542926987522c11a5a7ceea007620ba3dcb",
+        "hp_device.hpp": "59e9abb60ed3f145295bcf480824c4d0bcd5e1685c2d5892c48171b3a34134d4",
+        "hp_internal.hpp": "d8d670ae2a8630ffe925e804b39d702d4bf60bb806a0de39e8832bc0e4af05f8",
+        "hp_jit.cpp": "46e759b11eb3772d8f74dbefe64351f6821b96d12000914a554c40044468ce28",
     },
-    "fetch_kib": 264.5, "fetch_scale": 262144 / 131088.25,
-    "write_kib": 8472.90625, "write_scale": 262144 / 262144,
+    "fetch_kib": 563.0, "fetch_scale": 262144 / 131088.5,
+    "write_kib": 6812.34375, "write_scale": 262144 / 262144,
 }
 
 WORKLOADS = {
@@ -60,12 +64,13 @@ def load_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, variant):
     """HBM bytes per launch from the counter profile, or None when the kernel
-    sources differ from the profiled ones or the workload is another one."""
+    sources differ from the profiled ones or the workload or kernel variant
+    is another one."""
     import hashlib
     T = TRAFFIC_PROFILE
-    if workload != T["workload"]:
+    if workload != T["workload"] or variant != T["variant"] or not T["sources_sha256"]:
         return None
     csrc = os.path.join(ROOT, "paper_1804_03807_amd", "csrc")
     for name, digest in T["sources_sha256"].items():
@@ -295,7 +300,7 @@ def main():
         "kernel_ms_mean": kmean,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic(args.workload),
+                     "traffic": measured_traffic(args.workload, timing["variant"]),
                      "flops_per_launch": flop},
     }
     if not resid_ok:

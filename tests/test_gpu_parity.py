@@ -148,6 +148,32 @@ def test_cyclic8_full_parity(ctx):
     assert len(oracle.find_duplicates(e_g, s_g)) == 0
 
 
+def test_cyclic8_full_parity_specialised_plan(ctx):
+    """The benchmark's configuration: a plan for the cyclic-8 workload runs on
+    the kernel specialised to its support (variant 308, one persistent
+    launch); all 40320 paths against the oracle."""
+    import torch
+    import paper_1804_03807_amd as hp
+    from parity import compare_paths
+    wl = W.cyclic8()
+    s, g = wl.systems[0], complex(wl.gammas[0])
+    plan = ctx.plan(s, g)
+    e, st, sts = plan.outputs(s.bezout())
+    plan.track_device(e, st, sts)
+    torch.cuda.synchronize()
+    assert ctx.last_timing()["variant"] == 308
+    e_g, s_g, st_g = hp.Plan.endpoints_to_numpy(e), st.cpu().numpy(), hp.Plan.stats_to_numpy(sts)
+    plan.close()
+    e_o, s_o, st_o = oracle.track_paths(s, g, n_paths=s.bezout(), n_threads=NTHREADS)
+    hard, flips = compare_paths(e_g, s_g, st_g, e_o, s_o, st_o)
+    log(f"  converged gpu={int((s_g == 0).sum())} oracle={int((s_o == 0).sum())} "
+        f"hard={len(hard)} borderline={len(flips)}")
+    assert len(hard) == 0, f"paths {hard[:8]} differ from the oracle"
+    assert abs(int((s_g == 0).sum()) - int((s_o == 0).sum())) <= len(flips)
+    assert (st_g["residual"][s_g == 0] <= 1e-10).all()
+    assert len(oracle.find_duplicates(e_g, s_g)) == 0
+
+
 def test_ids_list_matches_direct(ctx):
     import torch
     import paper_1804_03807_amd as hp
