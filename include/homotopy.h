@@ -159,11 +159,12 @@ int hp_track_paths(hp_context *ctx, const hp_system *f, const hp_system *g, cons
 
 /* A plan: f packed and resident on the device, with a kernel variant chosen
  * (autotuned when tune != 0 and no cached choice exists).  Without tuning,
- * a plan for n <= 8 whose terms have at most 1024 factors in all runs on a
+ * a plan for n <= 10 whose terms have at most 1024 factors in all runs on a
  * kernel specialised to f's support (variant 300 + n): its source is written
- * and compiled (hiprtc) at plan creation, which takes up to a few seconds
- * the first time a support is seen in the process; plans for systems of the
- * same support share the compiled module.  Errors of that compilation are
+ * and compiled (hiprtc) at plan creation, which takes seconds (n = 8: 5-7 s,
+ * n = 10: 13-17 s on one host core) the first time a support is seen; plans
+ * for systems of the same support share the compiled module, and
+ * $HP_JIT_CACHE (a directory) keeps code objects across processes.  Errors of that compilation are
  * HP_E_DEVICE with the compiler log in hp_last_error. */
 int hp_plan_create(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
                    int32_t tune, hp_plan **out);
@@ -177,7 +178,7 @@ void hp_plan_destroy(hp_plan *plan);
  *                          this n;
  *   200 + n (n = 7, 8)     lane kernels with 32 paths per wavefront (half the
  *                          LDS, for systems whose power table is large);
- *   300 + n (n = 1..8)     the kernel specialised to the plan's system (one
+ *   300 + n (n = 1..10)    the kernel specialised to the plan's system (one
  *                          path per lane, [J | rhs] in registers, compiled at
  *                          run time; total-degree start system only).
  * The variant must fit the system's n and its LDS must fit the device; 0
@@ -190,7 +191,10 @@ int hp_plan_set_variant(hp_plan *plan, int32_t variant);
 
 /* Writes and compiles the kernel specialised to f (variant 300 + n) for
  * gfx950 without loading it, so it needs no device; *code_bytes = size of
- * the code object.  HP_E_UNSUPPORTED_N when f cannot have one (n > 8, or more
+ * the code object.  The code object is kept for the process (and written to
+ * the directory $HP_JIT_CACHE names, when set, where later processes find
+ * it), so plans for systems with f's support skip the compilation: a caller
+ * can compile ahead of the first solve.  HP_E_UNSUPPORTED_N when f cannot have one (n > 10, or more
  * than 1024 factors in all), HP_E_DEVICE when compilation fails (compiler log
  * in hp_last_error), HP_E_INVALID_ARG for a malformed system. */
 int hp_spec_compile(const hp_system *f, int64_t *code_bytes);

@@ -10,8 +10,15 @@
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <unistd.h>
+
 #include <algorithm>
+#include <atomic>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -177,7 +184,80 @@ std::string spec_source(int n, const int32_t *deg, const DevTerm *terms, int n_t
   return o.str();
 }
 
-int spec_compile(const std::string &src, std::vector<char> &code, std::string &log) {
+namespace {
+
+// Code objects already built in this process, by source.
+std::mutex g_code_mu;
+std::map<std::string, std::vector<char>> g_code;
+
+// hiprtc options of every specialised kernel (no packed FP32 instructions in
+// device code, as for the compiled kernels).
+const char *const kRtcOpts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang",
+                                "-target-feature", "-Xclang", "-packed-fp32-ops"};
+
+// What a cached code object depends on besides its source: the compiler
+// version and options.
+std::string build_tag() {
+  int major = 0, minor = 0;
+  hiprtcVersion(&major, &minor);
+  std::string t = "hiprtc " + std::to_string(major) + "." + std::to_string(minor);
+  for (const char *o : kRtcOpts) t += std::string(" ") + o;
+  return t + "\n";
+}
+
+// File of the on-disk code cache ($HP_JIT_CACHE, when set): named by a hash
+// of the key (build tag + source); the file starts with the key itself, so
+// that a hash collision or another compiler reads as a miss.
+std::string disk_path(const std::string &key) {
+  const char *dir = std::getenv("HP_JIT_CACHE");
+  if (!dir || !*dir) return std::string();
+  char name[40];
+  std::snprintf(name, sizeof(name), "/hp_spec_%016zx.bin", std::hash<std::string>()(key));
+  return std::string(dir) + name;
+}
+
+bool disk_load(const std::string &src, std::vector<char> &code) {
+  const std::string key = build_tag() + src;
+  const std::string path = disk_path(key);
+  if (path.empty()) return false;
+  std::ifstream in(path, std::ios::binary);
+  if (!in) return false;
+  uint64_t ls = 0, lc = 0;
+  in.read((char *)&ls, sizeof(ls));
+  if (!in || ls != key.size()) return false;
+  std::string s2(ls, '\0');
+  in.read(&s2[0], (std::streamsize)ls);
+  in.read((char *)&lc, sizeof(lc));
+  if (!in || s2 != key || lc == 0 || lc > (1ull << 30)) return false;
+  code.resize(lc);
+  in.read(code.data(), (std::streamsize)lc);
+  return (bool)in;
+}
+
+void disk_store(const std::string &src, const std::vector<char> &code) {
+  static std::atomic<unsigned> seq{0};
+  const std::string key = build_tag() + src;
+  const std::string path = disk_path(key);
+  if (path.empty()) return;
+  const std::string tmp =
+      path + ".tmp" + std::to_string((long)getpid()) + "_" + std::to_string(seq++);
+  {
+    std::ofstream out(tmp, std::ios::binary);
+    if (!out) return;
+    const uint64_t ls = key.size(), lc = code.size();
+    out.write((const char *)&ls, sizeof(ls));
+    out.write(key.data(), (std::streamsize)ls);
+    out.write((const char *)&lc, sizeof(lc));
+    out.write(code.data(), (std::streamsize)lc);
+    if (!out) {
+      std::remove(tmp.c_str());
+      return;
+    }
+  }
+  std::rename(tmp.c_str(), path.c_str());  // readers see a whole file or none
+}
+
+int rtc_compile(const std::string &src, std::vector<char> &code, std::string &log) {
   std::vector<const char *> names, texts;
   for (size_t i = 0; i < sizeof(kJitHeaderNames) / sizeof(kJitHeaderNames[0]); ++i) {
     names.push_back(kJitHeaderNames[i]);
@@ -194,10 +274,7 @@ int spec_compile(const std::string &src, std::vector<char> &code, std::string &l
     log = hiprtcGetErrorString(r);
     return (int)hipErrorInvalidValue;
   }
-  // no packed FP32 instructions in device code, as for the compiled kernels
-  const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang",
-                        "-target-feature", "-Xclang", "-packed-fp32-ops"};
-  r = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+  r = hiprtcCompileProgram(prog, (int)(sizeof(kRtcOpts) / sizeof(kRtcOpts[0])), kRtcOpts);
   size_t ls = 0;
   hiprtcGetProgramLogSize(prog, &ls);
   log.assign(ls, '\0');
@@ -213,6 +290,27 @@ int spec_compile(const std::string &src, std::vector<char> &code, std::string &l
   }
   hiprtcDestroyProgram(&prog);
   return rc;
+}
+
+}  // namespace
+
+int spec_compile(const std::string &src, std::vector<char> &code, std::string &log) {
+  {
+    std::lock_guard<std::mutex> g(g_code_mu);
+    auto it = g_code.find(src);
+    if (it != g_code.end()) {
+      code = it->second;
+      return (int)hipSuccess;
+    }
+  }
+  if (!disk_load(src, code)) {
+    const int rc = rtc_compile(src, code, log);
+    if (rc) return rc;
+    disk_store(src, code);
+  }
+  std::lock_guard<std::mutex> g(g_code_mu);
+  g_code.emplace(src, code);
+  return (int)hipSuccess;
 }
 
 int spec_get(int device, const std::string &src, const SpecModule **out, std::string &log) {

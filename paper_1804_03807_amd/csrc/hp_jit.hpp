@@ -10,8 +10,10 @@
 
 namespace hp {
 
-// Largest n of a specialised kernel: its [J | rhs] lives in registers.
-constexpr int kSpecMaxN = 8;
+// Largest n of a specialised kernel: its [J | rhs] lives in registers
+// (n = 9, 10 spill part of it to scratch and still run several times faster
+// than the group kernels; from n = 11 on the spills make them slower).
+constexpr int kSpecMaxN = 10;
 // Largest total factor count (sum over terms of the factors) of a system
 // with a specialised kernel; bounds its code size and compile time.
 constexpr int kSpecMaxFactors = 1024;
@@ -25,8 +27,10 @@ bool spec_eligible(int n, const DevTerm *terms, int n_terms);
 // packed order (sorted by factor count; the coefficients stay run-time data).
 std::string spec_source(int n, const int32_t *deg, const DevTerm *terms, int n_terms);
 
-// Compiles spec source for gfx950 through hiprtc (no device needed): the
-// code object in `code`, the compiler log in `log`.  hipSuccess or an error.
+// Code object of spec source for gfx950 (no device needed): from this
+// process's cache, else from the directory $HP_JIT_CACHE names (when set),
+// else compiled through hiprtc and stored in both.  The compiler log goes to
+// `log`.  hipSuccess or an error.
 int spec_compile(const std::string &src, std::vector<char> &code, std::string &log);
 
 // Loaded specialised kernels of one system on one device.

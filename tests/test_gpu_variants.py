@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 NTHREADS = min(16, os.cpu_count() or 1)
 GROUP = [4, 8, 10, 12]
 LANES = [100 + n for n in range(1, 9)] + [207, 208]
-SPEC = [300 + n for n in range(1, 9)]
+SPEC = [300 + n for n in range(1, 11)]
 
 
 def log(*a):
@@ -97,7 +97,7 @@ def test_unknown_variant_rejected(ctx):
     import paper_1804_03807_amd as hp
     s, g = CASES["cyclic6"]()
     plan = ctx.plan(s, g)
-    for bad in (5, 104, 108, 207, 300, 305, 309, -1):
+    for bad in (5, 104, 108, 207, 300, 305, 309, 311, -1):
         with pytest.raises(hp.HomotopyError):
             plan.set_variant(bad)
     plan.close()
@@ -137,7 +137,7 @@ def test_autotune_chooses_a_valid_variant(ctx, tmp_path, monkeypatch):
 
 @pytest.mark.parametrize("name", ["cyclic6", "dense8_d2"])
 def test_plan_default_is_specialised(ctx, name):
-    """Without tuning, a plan for n <= 8 runs on the kernel specialised to
+    """Without tuning, a plan for n <= 10 runs on the kernel specialised to
     its system (variant 300 + n), 64 paths per wavefront."""
     import torch
     s, g = CASES[name]()

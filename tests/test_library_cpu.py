@@ -92,11 +92,36 @@ def test_specialised_kernel_compiles(hp, n):
 
 
 def test_specialised_kernel_limits(hp):
-    """n above 8 and systems with more than 1024 factors in all have none."""
+    """n above 10 and systems with more than 1024 factors in all have none."""
     with pytest.raises(hp.HomotopyError) as e:
-        hp.spec_compile(W.cyclic_system(9, np.random.default_rng(0)))
+        hp.spec_compile(W.cyclic_system(11, np.random.default_rng(0)))
     assert e.value.code == hp._lib.HP_E_UNSUPPORTED_N
     big = W.dense_system(8, [3] * 8, np.random.default_rng(0))  # 8 x 165 terms
     with pytest.raises(hp.HomotopyError) as e:
         hp.spec_compile(big)
     assert e.value.code == hp._lib.HP_E_UNSUPPORTED_N
+
+
+def test_specialised_kernel_disk_cache(hp, tmp_path):
+    """With $HP_JIT_CACHE set, a compiled code object is written there and a
+    fresh process loads it instead of compiling (same code size)."""
+    import subprocess
+    import sys
+    s = W.dense_system(2, [2, 3], np.random.default_rng(77))  # a support no other test uses
+    env = dict(os.environ, HP_JIT_CACHE=str(tmp_path))
+    code = ("import sys, time; sys.path.insert(0, %r); import numpy as np; import workloads as W; "
+            "import paper_1804_03807_amd as hp; "
+            "s = W.dense_system(2, [2, 3], np.random.default_rng(77)); "
+            "t = time.perf_counter(); b = hp.spec_compile(s); "
+            "print(b, time.perf_counter() - t)" % ROOT)
+    out1 = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                          timeout=300, check=True).stdout.split()
+    files = list(tmp_path.glob("hp_spec_*.bin"))
+    assert len(files) == 1 and files[0].stat().st_size > int(out1[0])
+    ino = files[0].stat().st_ino
+    out2 = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                          timeout=300, check=True).stdout.split()
+    assert out2[0] == out1[0]
+    # loaded, not compiled: a compilation would have replaced the file
+    assert list(tmp_path.glob("hp_spec_*.bin")) == files and files[0].stat().st_ino == ino
+    assert hp.spec_compile(s) == int(out1[0])
