@@ -10,13 +10,14 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libhomotopy.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["tracker.hip", "lanes.hip", "hp_host.cpp", "hp_jit.cpp"]
+SOURCES = ["tracker.hip", "lanes.hip", "dense.hip", "hp_host.cpp", "hp_jit.cpp"]
 # headers the run-time specialised kernels are compiled with (hiprtc)
 JIT_HEADERS = [("homotopy.h", os.path.join(ROOT, "include", "homotopy.h")),
                ("hp_internal.hpp", os.path.join(CSRC, "hp_internal.hpp")),
                ("hp_device.hpp", os.path.join(CSRC, "hp_device.hpp")),
                ("lane_track.hpp", os.path.join(CSRC, "lane_track.hpp")),
-               ("spec_track.hpp", os.path.join(CSRC, "spec_track.hpp"))]
+               ("spec_track.hpp", os.path.join(CSRC, "spec_track.hpp")),
+               ("reg_lu.hpp", os.path.join(CSRC, "reg_lu.hpp"))]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # no packed FP32 instructions anywhere in device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -1,0 +1,183 @@
+// Dense one-path-per-lane tracker kernel for gfx950 (CDNA4), complex FP64:
+// systems of n <= kDenseMaxN unknowns whose equations have total degree at
+// most 3, stored as full coefficient tables (every monomial of the degree,
+// zero where absent; layout in hp_internal.hpp).
+//
+// Evaluation.  With the loops over variables unrolled for the compile-time
+// n, an equation is evaluated in nested (Horner) form,
+//   f = c + sum_a x_a T_a,   T_a = l_a + sum_{b>=a} x_b S_ab,
+//   S_ab = q_ab + sum_{c>=b} k_abc x_c,
+// and its gradient in reverse mode over the same form: df/dx_a += T_a,
+// df/dx_b += x_a S_ab, df/dx_c += x_a x_b k_abc (repeated indices give the
+// multiplicities of squares and cubes by themselves).  Two complex
+// multiply-adds per cubic monomial, every index a compile-time constant, so
+// the Jacobian row is a register array and the whole [J | rhs] stays in
+// registers for the register LU, as in the kernels specialised at run time.
+// The partial derivatives are scaled by t and the start system
+// g_i = x_i^{d_i} - 1 is added as in the other kernels (paper: Section 1;
+// the end of Section 2.1 for independent paths).
+//
+// One launch tracks every system of a batch (mixed n): a wavefront drains
+// the systems' refill queues one after another and runs the tracker
+// instantiated for each system's n.
+#include <hip/hip_runtime.h>
+
+#include "lane_track.hpp"
+#include "reg_lu.hpp"
+
+namespace hp {
+
+template <int N>
+struct Dense : LaneTrack<Dense<N>, N, RkLds<N>> {
+  using Base = LaneTrack<Dense<N>, N, RkLds<N>>;
+  using Base::a;
+  using Base::sp;
+  using Base::gamma;
+  using Base::xc;
+  using Base::deg;
+
+  cptr<double> dc;  // this system's dense table, (re, im) pairs
+  int off[N];       // first coefficient of equation i
+  cd J[N][N];
+  cd b[N];
+
+  // lds: at least RkLds<N>::kBytes
+  __device__ Dense(const KArgs &args, lds_char *lds)
+      : Base(args, true, lds + (threadIdx.x & 63) * 16) {}
+
+  __device__ __forceinline__ void load_system(int s) {
+    this->load_common(s);
+    dc = as_const((const double *)a.dcoef) + 2 * (long long)sp->dense_base;
+#pragma unroll
+    for (int i = 0; i < N; ++i) off[i] = sp->dense_off[i];
+  }
+
+  __device__ __forceinline__ static cd coef(cptr<double> c, int k) { return {c[2 * k], c[2 * k + 1]}; }
+
+  // Equation of total degree D whose table starts at c: returns its value
+  // and writes its gradient to g.
+  template <int D>
+  __device__ __forceinline__ cd equation(cptr<double> c, cd (&g)[N]) const {
+    constexpr int kQuad = 1 + N;                     // first quadratic coefficient
+    constexpr int kCubic = kQuad + N * (N + 1) / 2;  // first cubic coefficient
+#pragma unroll
+    for (int v = 0; v < N; ++v) g[v] = {0.0, 0.0};
+    cd f = coef(c, 0);
+    int qi = kQuad, ci = kCubic;  // compile-time after unrolling
+#pragma unroll
+    for (int va = 0; va < N; ++va) {
+      // T_a, complete once its b loop is done: folded into f and df/dx_a
+      cd T = coef(c, 1 + va);
+      if constexpr (D >= 2) {
+#pragma unroll
+        for (int vb = va; vb < N; ++vb) {
+          cd S = coef(c, qi++);
+          if constexpr (D >= 3) {
+            // two partial sums shorten the dependent chain
+            const cd P = cmul(xc[va], xc[vb]);
+            cd S1 = {0.0, 0.0};
+#pragma unroll
+            for (int vc = vb; vc < N; ++vc) {
+              const cd k = coef(c, ci++);
+              if ((vc - vb) & 1) S1 = cfma(S1, k, xc[vc]);
+              else S = cfma(S, k, xc[vc]);
+              g[vc] = cfma(g[vc], P, k);
+            }
+            S = cadd(S, S1);
+          }
+          T = cfma(T, xc[vb], S);
+          g[vb] = cfma(g[vb], xc[va], S);
+        }
+      }
+      f = cfma(f, xc[va], T);
+      g[va] = cadd(g[va], T);
+    }
+    return f;
+  }
+
+  // [J_x(xc, te) | rhs]: J = t J_f + s J_g, rhs = -H_t, H or f (EvalMode).
+  __device__ __forceinline__ void eval(int emode, double te) {
+    const cd s = cscale(gamma, 1.0 - te);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      cd g[N];
+      const cptr<double> c = dc + 2 * off[i];
+      const int d = deg[i];
+      cd f;
+      if (d >= 3) f = equation<3>(c, g);
+      else if (d == 2) f = equation<2>(c, g);
+      else f = equation<1>(c, g);
+#pragma unroll
+      for (int j = 0; j < N; ++j) J[i][j] = cscale(g[j], te);
+      // start system x_i^{d_i} - 1 (d_i <= 3)
+      cd xq = (d >= 2) ? xc[i] : cd{1.0, 0.0};
+      if (d >= 3) xq = cmul(xq, xc[i]);
+      cd gs = cmul(xq, xc[i]);
+      gs.re -= 1.0;
+      J[i][i] = cadd(J[i][i], cmul(s, cscale(xq, (double)d)));
+      const cd hv = cadd(cmul(s, gs), cscale(f, te));
+      const cd mht = csub(cmul(gamma, gs), f);
+      b[i] = csel(emode == EV_F, f, csel(emode == EV_H, hv, mht));
+    }
+    // [J | rhs] reaches the solve as opaque register values (keeps the
+    // compiler from interleaving evaluation and elimination)
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) asm volatile("" : "+v"(J[i][j].re), "+v"(J[i][j].im));
+      asm volatile("" : "+v"(b[i].re), "+v"(b[i].im));
+    }
+  }
+
+  __device__ __forceinline__ void solve(cd dx[N], bool &sing) { reg_lu_solve<N>(J, b, dx, sing); }
+
+  __device__ __forceinline__ double residual() const {
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r = nmax(r, cmod(b[i]));
+    return r;
+  }
+};
+
+template <int N>
+__device__ __forceinline__ void dense_drain(const KArgs &a, int s, lds_char *rk) {
+  Dense<N> tr(a, rk);
+  lane_drain(a, tr, s);
+}
+
+// Persistent kernel over every system of the launch; the system's n picks
+// the instantiation (wave-uniform).
+__global__ void __launch_bounds__(64) k_dense(KArgs a) {
+  __shared__ __align__(16) char rk[RkLds<kDenseMaxN>::kBytes];
+  lds_char *lds = (lds_char *)rk;
+  const int first_sys = blockIdx.x % a.n_systems;
+  for (int v = 0; v < a.n_systems; ++v) {
+    const int s = (first_sys + v) % a.n_systems;
+    switch (as_const(a.sys)[s].n) {
+      case 1: dense_drain<1>(a, s, lds); break;
+      case 2: dense_drain<2>(a, s, lds); break;
+      case 3: dense_drain<3>(a, s, lds); break;
+      case 4: dense_drain<4>(a, s, lds); break;
+      case 5: dense_drain<5>(a, s, lds); break;
+      case 6: dense_drain<6>(a, s, lds); break;
+      case 7: dense_drain<7>(a, s, lds); break;
+      case 8: dense_drain<8>(a, s, lds); break;
+      case 9: dense_drain<9>(a, s, lds); break;
+      case 10: dense_drain<10>(a, s, lds); break;
+      default: break;  // the host admits n <= kDenseMaxN only
+    }
+  }
+}
+
+}  // namespace hp
+
+using namespace hp;
+
+int hp_launch_dense(const KArgs &a, int groups, void *stream) {
+  hipLaunchKernelGGL(k_dense, dim3(groups), dim3(64), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int hp_dense_per_cu(int *out) {
+  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_dense, 64, 0);
+}

@@ -173,8 +173,11 @@ struct Packed {
   std::vector<int32_t> kp;
   std::vector<double2> roots;
   std::vector<DevSys> sys;
+  std::vector<double2> dense;  // dense coefficient tables (dense kernel)
   int nl = 1, nmin = HP_MAX_N, emax = 1, kmax = 0;
   bool general = false;  // a general start system or explicit start points
+  bool dense_ok = true;  // every system has a dense table
+  double dense_fill = 1.0;  // smallest terms / table entries over the systems
   // workgroup LDS bytes of the n_max group variant: largest over the
   // systems, with or without the term tables staged in LDS
   size_t lds(int nmax, bool stage = true) const {
@@ -241,6 +244,49 @@ int32_t pack_terms(Packed &P, const hp_system *f, int32_t term_base) {
   return block;
 }
 
+// Dense table of f for the dense kernel (n <= kDenseMaxN, every equation of
+// total degree <= kDenseMaxDeg), appended to P.dense with its offsets in d;
+// false when f does not qualify.  Entry order: the kernel's loops (constant;
+// x_a; x_a x_b, a <= b; x_a x_b x_c, a <= b <= c; a outermost).
+bool pack_dense(Packed &P, const hp_system *f, const SysInfo &info, DevSys &d) {
+  const int n = f->n;
+  if (n > hp::kDenseMaxN) return false;
+  for (int i = 0; i < n; ++i)
+    if (info.deg[i] > hp::kDenseMaxDeg) return false;
+  const int nq = n * (n + 1) / 2, nc = n * (n + 1) * (n + 2) / 6;
+  std::vector<int> qidx((size_t)n * n, -1), cidx((size_t)n * n * n, -1);
+  int qi = 1 + n, ci = 1 + n + nq;
+  for (int a = 0; a < n; ++a)
+    for (int b = a; b < n; ++b) {
+      qidx[(size_t)a * n + b] = qi++;
+      for (int c = b; c < n; ++c) cidx[((size_t)a * n + b) * n + c] = ci++;
+    }
+  const size_t base = P.dense.size();
+  d.dense_base = (int32_t)base;
+  size_t entries = 0;
+  for (int i = 0; i < n; ++i) {
+    const int di = info.deg[i];
+    const size_t size = 1 + n + (di >= 2 ? nq : 0) + (di >= 3 ? nc : 0);
+    const size_t eq0 = P.dense.size();
+    d.dense_off[i] = (int32_t)(eq0 - base);
+    P.dense.resize(eq0 + size, make_double2(0.0, 0.0));
+    entries += size;
+    for (int t = f->eq_ptr[i]; t < f->eq_ptr[i + 1]; ++t) {
+      int v[hp::kDenseMaxDeg], td = 0;  // variables of the monomial, ascending
+      for (int j = 0; j < n; ++j)
+        for (int e = 0; e < f->exps[(size_t)t * n + j]; ++e) v[td++] = j;
+      const int pos = td == 0 ? 0
+                    : td == 1 ? 1 + v[0]
+                    : td == 2 ? qidx[(size_t)v[0] * n + v[1]]
+                              : cidx[((size_t)v[0] * n + v[1]) * n + v[2]];
+      P.dense[eq0 + pos].x += f->coeff[t].re;
+      P.dense[eq0 + pos].y += f->coeff[t].im;
+    }
+  }
+  P.dense_fill = std::min(P.dense_fill, (double)f->n_terms / (double)entries);
+  return true;
+}
+
 void pack_append(Packed &P, const hp_system *f, const SysInfo &info, hp_c64 gamma,
                  int64_t queue_len, int64_t out_path_base, int64_t out_x_base,
                  const int64_t *dev_ids, const hp_system *g = nullptr, int g_emax = 0,
@@ -283,6 +329,7 @@ void pack_append(Packed &P, const hp_system *f, const SysInfo &info, hp_c64 gamm
     d.emax = std::max(d.emax, g_emax);
   }
   d.start = dev_start;
+  if (g || dev_start || !pack_dense(P, f, info, d)) P.dense_ok = false;
   P.sys.push_back(d);
   P.nl = std::max(P.nl, n);
   P.nmin = std::min(P.nmin, n);
@@ -293,10 +340,14 @@ void pack_append(Packed &P, const hp_system *f, const SysInfo &info, hp_c64 gamm
 
 // Device copy of a Packed image.
 struct DevTables {
-  DevBuf tcoef, tmeta, kp, roots, sys, qhead;
+  DevBuf tcoef, tmeta, kp, roots, sys, qhead, dcoef;
   int upload(const Packed &P, hipStream_t s) {
     int rc;
     const size_t nt = std::max<size_t>(1, P.terms.size());
+    if ((rc = dcoef.alloc(std::max<size_t>(1, P.dense.size()) * sizeof(double2)))) return rc;
+    if (!P.dense.empty())
+      HIP_TRY(hipMemcpyAsync(dcoef.p, P.dense.data(), P.dense.size() * sizeof(double2),
+                             hipMemcpyHostToDevice, s));
     if ((rc = tcoef.alloc(nt * sizeof(double2)))) return rc;
     if ((rc = tmeta.alloc(nt * sizeof(uint4)))) return rc;
     if ((rc = kp.alloc(std::max<size_t>(1, P.kp.size()) * sizeof(int32_t)))) return rc;
@@ -336,16 +387,20 @@ int nmax_for(int n) {
 
 // Kernel variant codes: n_max (4, 8, 10, 12) for the group kernels (n lanes
 // per path), 100 + n_max for the lane kernels with 64 paths per wavefront,
-// 200 + n_max for those with 32, and 300 + n for the kernel specialised to
-// the plan's system (one path per lane, compiled at run time).
+// 200 + n_max for those with 32, 300 + n for the kernel specialised to
+// the plan's system (one path per lane, compiled at run time), and 400 for
+// the dense kernel (one path per lane, systems of total degree <= 3).
 struct Kv {
   int code = 0;
   bool lanes = false;
   bool spec = false;  // specialised to the plan's system (compiled at run time)
+  bool dense = false;  // the dense kernel (any n <= kDenseMaxN, degree <= 3)
   int nmax = 0;
   int pw = 0;  // lane kernels: paths per wavefront
   const hp::SpecModule *sm = nullptr;  // spec: the loaded module
 };
+
+constexpr int kDenseCode = 400;
 
 bool kv_decode(int code, Kv &k) {
   k = Kv{};
@@ -368,8 +423,19 @@ bool kv_decode(int code, Kv &k) {
     k.pw = hp::kLanes;
     return true;
   }
+  if (code == kDenseCode) {
+    k.dense = true;
+    k.nmax = hp::kDenseMaxN;
+    k.pw = hp::kLanes;
+    return true;
+  }
   return false;
 }
+
+// The dense kernel is the default for launches whose systems all have dense
+// tables filled to at least a quarter (sparser systems evaluate faster term
+// by term).
+bool dense_preferred(const Packed &P) { return P.dense_ok && P.dense_fill >= 0.25; }
 
 // Variants that can run systems of up to n unknowns and exponents up to
 // emax within max_lds bytes of LDS (group kernels: checked per system).
@@ -536,7 +602,7 @@ int check_lds(hp_context *ctx, size_t lds) {
 
 // LDS bytes per workgroup of variant k for the systems of P.
 size_t kv_lds(const Kv &k, const Packed &P) {
-  if (k.spec) return 0;
+  if (k.spec || k.dense) return 0;
   return k.lanes ? hp::lanes_lds_bytes(k.nmax, k.pw, P.emax) : P.lds(k.nmax, false);
 }
 
@@ -549,6 +615,9 @@ int kv_occupancy(hp_context *ctx, const Kv &k, const Packed &P, size_t *lds, int
   if (k.spec) {
     *lds = 0;
     HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k.sm->persistent, hp::kLanes, 0));
+  } else if (k.dense) {
+    *lds = 0;
+    HIP_TRY((hipError_t)hp_dense_per_cu(per_cu));
   } else if (k.lanes) {
     *lds = kv_lds(k, P);
     int rc = check_lds(ctx, *lds);
@@ -573,7 +642,8 @@ int kv_occupancy(hp_context *ctx, const Kv &k, const Packed &P, size_t *lds, int
 // all systems.
 Kv kv_pick(const Packed &P, const hp_context *ctx) {
   Kv k;
-  kv_decode(P.nmin == P.nl ? kv_default(P.nl, P.emax, ctx->max_lds) : nmax_for(P.nl), k);
+  if (dense_preferred(P)) kv_decode(kDenseCode, k);
+  else kv_decode(P.nmin == P.nl ? kv_default(P.nl, P.emax, ctx->max_lds) : nmax_for(P.nl), k);
   return k;
 }
 
@@ -585,14 +655,14 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
   if (!e0) e0 = ctx->ev0;
   if (!e1) e1 = ctx->ev1;
   if (P.nl > k.nmax || (k.lanes && P.nmin != k.nmax) ||
-      (k.spec && (P.sys.size() != 1 || P.nl != k.nmax || !k.sm)))
+      (k.spec && (P.sys.size() != 1 || P.nl != k.nmax || !k.sm)) || (k.dense && !P.dense_ok))
     return fail(HP_E_INVALID_ARG, "kernel variant does not match the systems' n");
   size_t lds = 0;
   int per_cu = 0, stage = 0;
   int rc = kv_occupancy(ctx, k, P, &lds, &per_cu, &stage);
   if (rc) return rc;
   // enough wavefronts to hold every path once, at most a full device
-  const int64_t per_wave = (k.lanes || k.spec) ? k.pw : hp::kLanes / std::max(1, P.nl);
+  const int64_t per_wave = (k.lanes || k.spec || k.dense) ? k.pw : hp::kLanes / std::max(1, P.nl);
   const int64_t want = (total_paths + per_wave - 1) / per_wave;
   const int64_t groups = std::min<int64_t>((int64_t)ctx->cus * per_cu, std::max<int64_t>(1, want));
   KArgs a;
@@ -609,12 +679,15 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
   a.stats = stats;
   a.tol = dev_tol(tol);
   a.stage = stage;
+  a.dcoef = dev.dcoef.as<double2>();
   HIP_TRY(hipMemsetAsync(dev.qhead.p, 0, P.sys.size() * sizeof(unsigned long long), s));
   HIP_TRY(hipEventRecord(e0, s));
   if (k.spec) {
     void *params[] = {&a};
     HIP_TRY(hipModuleLaunchKernel(k.sm->persistent, (unsigned)groups, 1, 1, hp::kLanes, 1, 1, 0, s,
                                   params, nullptr));
+  } else if (k.dense) {
+    HIP_TRY((hipError_t)hp_launch_dense(a, (int)groups, s));
   } else if (k.lanes) {
     HIP_TRY((hipError_t)hp_launch_lanes(k.nmax, k.pw, a, (int)groups, lds, s));
   } else {
@@ -647,17 +720,21 @@ int spec_prepare(hp_plan *plan, Kv &k) {
 
 int plan_variant(hp_plan *plan, int code) {
   if (code == 0) {
-    code = (plan->spec_default && plan_spec_eligible(plan))
-               ? 300 + plan->info.n
-               : kv_default(plan->info.n, plan->info.emax, plan->ctx->max_lds);
+    code = (plan->spec_default && plan_spec_eligible(plan)) ? 300 + plan->info.n
+           : dense_preferred(plan->P) ? kDenseCode
+                                      : kv_default(plan->info.n, plan->info.emax, plan->ctx->max_lds);
   }
   Kv k;
   if (!kv_decode(code, k) || k.nmax < plan->info.n ||
       ((k.lanes || k.spec) && k.nmax != plan->info.n))
     return fail(HP_E_INVALID_ARG, "no compiled kernel variant " + std::to_string(code) +
                                       " for n = " + std::to_string(plan->info.n));
-  if ((k.lanes || k.spec) && plan->P.general)
+  if ((k.lanes || k.spec || k.dense) && plan->P.general)
     return fail(HP_E_INVALID_ARG, "lane kernels track the total-degree start system only");
+  if (k.dense && !plan->P.dense_ok)
+    return fail(HP_E_INVALID_ARG, "the dense kernel takes n <= " + std::to_string(hp::kDenseMaxN) +
+                                      " and equations of total degree <= " +
+                                      std::to_string(hp::kDenseMaxDeg));
   if (k.spec) {
     if (!plan_spec_eligible(plan))
       return fail(HP_E_INVALID_ARG, "system too large for a specialised kernel");
@@ -680,7 +757,10 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
   if ((rc = plan->ph.alloc((size_t)n_paths * sizeof(double)))) return rc;
   if ((rc = plan->piv.alloc((size_t)8 * n_paths * sizeof(int32_t)))) return rc;
   if ((rc = plan->pactive.alloc(sizeof(unsigned int)))) return rc;
-  const Kv &k = plan->kv;
+  // the dense kernel has no plain form: plain calls of a dense plan run the
+  // group kernel
+  Kv k = plan->kv;
+  if (k.dense) kv_decode(nmax_for(n), k);
   size_t lds = 0;
   int per_cu = 0, stage = 0;
   if ((rc = kv_occupancy(ctx, k, plan->P, &lds, &per_cu, &stage))) return rc;
@@ -753,6 +833,7 @@ int autotune(hp_plan *plan) {
   Kv best_k = plan->kv;
   std::vector<int> cands = kv_candidates(plan->info.n, plan->P.emax, ctx->max_lds);
   if (plan_spec_eligible(plan)) cands.insert(cands.begin(), 300 + plan->info.n);
+  if (plan->P.dense_ok && !plan->P.general) cands.push_back(kDenseCode);
   for (int code : cands) {
     Kv k;
     if (!kv_decode(code, k) || check_lds(ctx, kv_lds(k, plan->P)) != HP_OK) continue;
@@ -894,7 +975,8 @@ int hp_plan_track_device(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_
   hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
   const double t0 = now_ms();
   ctx->last = hp_timing{};
-  ctx->last.paths_per_wave = (plan->kv.lanes || plan->kv.spec) ? plan->kv.pw : hp::kLanes / plan->info.n;
+  ctx->last.paths_per_wave = (plan->kv.lanes || plan->kv.spec || plan->kv.dense) ? plan->kv.pw
+                                                                                 : hp::kLanes / plan->info.n;
   ctx->last.max_n = plan->kv.nmax;
   ctx->last.variant = plan->kv.code;
   if (n_paths == 0) return HP_OK;
@@ -1015,7 +1097,7 @@ int hp_track_batch(hp_context *ctx, const hp_system *fs, int32_t n_systems, cons
   ctx->last.kernel_ms = ms;
   ctx->last.launches = 1;
   ctx->last.groups = groups;
-  ctx->last.paths_per_wave = kv.lanes ? kv.pw : hp::kLanes / P.nl;
+  ctx->last.paths_per_wave = (kv.lanes || kv.dense) ? kv.pw : hp::kLanes / P.nl;
   ctx->last.max_n = kv.nmax;
   ctx->last.variant = kv.code;
   ctx->last.total_ms = now_ms() - t0;
@@ -1187,6 +1269,7 @@ struct Request {
   int64_t region_paths = 0;  // capacity in paths
   int64_t region_off = -1;   // offset in paths into the arena
   bool admitted = false, done = false, failed = false;
+  bool dense = false;  // runs on the dense kernel (as it would alone)
 };
 
 }  // namespace
@@ -1279,28 +1362,35 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
   size_t same = 0;
   for (auto &R : batch) same += std::memcmp(&R->tol, &tol, sizeof(tol)) == 0;
   const int64_t share = std::max<int64_t>(kMinChunk, kEpochPaths / (int64_t)same);
-  Packed P;
+  // one launch per kernel family, each request on the family it runs on
+  // alone (dense kernel or group kernels), so that its result does not
+  // depend on the other requests of the mix
+  Packed P[2];
+  int64_t total[2] = {0, 0};
   std::vector<int64_t> chunk(batch.size(), 0);
-  int64_t total = 0;
   for (size_t i = 0; i < batch.size(); ++i) {
     Request &R = *batch[i];
     if (std::memcmp(&R.tol, &tol, sizeof(tol)) != 0) continue;
     chunk[i] = std::min(std::min(R.info.paths - R.next_path, R.region_paths), share);
     // chunk outputs go to the request's arena region; slots are HP_MAX_N wide
-    pack_append(P, &R.sys, R.info, R.gamma, chunk[i], R.region_off,
-                R.region_off * HP_MAX_N, nullptr);
-    P.sys.back().id_base = R.next_path;
+    Packed &Q = P[R.dense ? 1 : 0];
+    pack_append(Q, &R.sys, R.info, R.gamma, chunk[i], R.region_off, R.region_off * HP_MAX_N,
+                nullptr);
+    Q.sys.back().id_base = R.next_path;
     // endpoints of a chunk are packed with stride n inside its region
-    total += chunk[i];
+    total[R.dense ? 1 : 0] += chunk[i];
   }
-  const Kv kv = kv_pick(P, ctx);
-  DevTables dev;
-  int rc = dev.upload(P, S->stream);
-  if (rc) return rc;
-  rc = launch_persistent(ctx, dev, P, kv, tol, total, S->a_ends.as<hp_c64>(),
-                         S->a_status.as<int32_t>(), S->a_stats.as<hp_path_stats>(), S->stream,
-                         nullptr, S->ev0, S->ev1);
-  if (rc) return rc;
+  DevTables dev[2];
+  for (int f = 0; f < 2; ++f) {
+    if (P[f].sys.empty()) continue;
+    const Kv kv = kv_pick(P[f], ctx);  // P[1]: the dense kernel; P[0]: group kernels
+    int rc = dev[f].upload(P[f], S->stream);
+    if (rc) return rc;
+    rc = launch_persistent(ctx, dev[f], P[f], kv, tol, total[f], S->a_ends.as<hp_c64>(),
+                           S->a_status.as<int32_t>(), S->a_stats.as<hp_path_stats>(), S->stream,
+                           nullptr, S->ev0, S->ev1);
+    if (rc) return rc;
+  }
   HIP_TRY(hipStreamSynchronize(S->stream));
   // copy finished chunks to the requests' host results
   for (size_t i = 0; i < batch.size(); ++i) {
@@ -1411,6 +1501,7 @@ int hp_server_submit(hp_server *S, const hp_system *f, hp_c64 gamma, const hp_to
     const Kv kv = kv_pick(one, S->ctx);
     if (kv.nmax < n) return fail(HP_E_UNSUPPORTED_N, "no kernel variant for n");
     if ((rc = check_lds(S->ctx, kv_lds(kv, one)))) return rc;
+    R->dense = kv.dense;
   }
   R->eq_ptr.assign(f->eq_ptr, f->eq_ptr + n + 1);
   R->coeff.assign(f->coeff, f->coeff + f->n_terms);

@@ -55,7 +55,21 @@ struct alignas(16) DevSys {
   int32_t g_eq_base;           // g's kKSlots block in the kp array
   int32_t g_pad;
   const double2 *start;        // [path id][n] start points (nullptr: roots of unity)
+  // dense table (systems of total degree <= 3 on the dense kernel): the
+  // coefficients of equation i start at dense_base + dense_off[i], see
+  // kDenseMaxN
+  int32_t dense_base;
+  int32_t dense_off[HP_MAX_N];
+  int32_t dense_pad[3];
 };
+
+// Dense kernel: systems of n <= kDenseMaxN unknowns whose equations have
+// total degree <= 3, every equation's coefficients as a full table in the
+// fixed order constant; x_a (a < n); x_a x_b (a <= b); x_a x_b x_c
+// (a <= b <= c), each block present up to the equation's degree, loops with
+// a outermost (missing monomials hold zero).
+constexpr int kDenseMaxN = 10;
+constexpr int kDenseMaxDeg = 3;
 
 struct DevTol {
   double tol_residual, tol_corr, tol_final, div_radius, h_init, h_min, h_max;
@@ -87,6 +101,7 @@ struct KArgs {
   DevTol tol;
   int32_t stage;         // group kernels: copy term tables of <= kMaxStagedTerms into LDS
   PlainState ps;         // plain mode only
+  const double2 *dcoef;  // dense coefficient tables (dense kernel)
 };
 
 enum Mode : int32_t { M_IDLE = 0, M_TRACK = 1, M_FINAL = 2 };
@@ -154,7 +169,8 @@ inline size_t lanes_lds_bytes(int n, int pw, int emax) {
 
 }  // namespace hp
 
-// Kernel launchers (tracker.hip, lanes.hip).  Return a hipError_t value.
+// Kernel launchers (tracker.hip, lanes.hip, dense.hip).  Return a hipError_t
+// value.
 extern "C++" {
 // general: the systems use a general start system or explicit start points
 int hp_launch_persistent(int nmax, bool general, const hp::KArgs &a, int groups, size_t lds,
@@ -167,4 +183,6 @@ int hp_launch_lanes(int n, int pw, const hp::KArgs &a, int groups, size_t lds, v
 int hp_launch_lanes_plain(int n, int pw, const hp::KArgs &a, int groups, size_t lds,
                           void *stream);
 int hp_lanes_per_cu(int n, int pw, size_t lds, int *out);
+int hp_launch_dense(const hp::KArgs &a, int groups, void *stream);
+int hp_dense_per_cu(int *out);
 }

@@ -312,47 +312,51 @@ struct LaneTrack {
 // head per system with one atomicAdd per wavefront (ballot, popcount,
 // mbcnt), in place of the work crew's guarded next-job pointer (Section 1).
 // ------------------------------------------------------------------------
+// Drains system s's queue: tracks its paths until the queue is empty and
+// this wavefront's lanes are idle.
 template <class T>
-__device__ __forceinline__ void lane_persistent(const KArgs &a, T &tr) {
-  const int first_sys = blockIdx.x % a.n_systems;
-  for (int v = 0; v < a.n_systems; ++v) {
-    const int s = (first_sys + v) % a.n_systems;
-    tr.load_system(s);
-    bool exhausted = false;
-    for (;;) {
-      // ---- refill idle lanes: one atomic per wavefront ----
-      const bool idle = tr.slot && tr.mode == M_IDLE;
-      const uint64_t m = ballot(idle);
-      if (m != 0 && !exhausted) {
-        const unsigned cnt = __popcll(m);
-        const int first = __builtin_ctzll(m);
-        unsigned long long qb = 0;
-        if (tr.lane == first) qb = atomicAdd(&a.qhead[s], (unsigned long long)cnt);
-        qb = __shfl(qb, first);
-        const unsigned rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-        if (idle) {
-          const long long q = (long long)qb + rank;
-          if (q < tr.npaths) tr.start_path(q);
-        }
-        if ((long long)(qb + cnt) >= tr.npaths) exhausted = true;
+__device__ __forceinline__ void lane_drain(const KArgs &a, T &tr, int s) {
+  tr.load_system(s);
+  bool exhausted = false;
+  for (;;) {
+    // ---- refill idle lanes: one atomic per wavefront ----
+    const bool idle = tr.slot && tr.mode == M_IDLE;
+    const uint64_t m = ballot(idle);
+    if (m != 0 && !exhausted) {
+      const unsigned cnt = __popcll(m);
+      const int first = __builtin_ctzll(m);
+      unsigned long long qb = 0;
+      if (tr.lane == first) qb = atomicAdd(&a.qhead[s], (unsigned long long)cnt);
+      qb = __shfl(qb, first);
+      const unsigned rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+      if (idle) {
+        const long long q = (long long)qb + rank;
+        if (q < tr.npaths) tr.start_path(q);
       }
-      if (ballot(tr.mode != M_IDLE) == 0) {
-        if (exhausted) break;  // this system is drained for this wavefront
-        continue;
-      }
-      // lanes that hold no path slot sit out the step
-      if (tr.slot) {
-        int fs;
-        double res;
-        tr.step(fs, res);
-        if (fs >= 0) {
-          tr.write_out(fs, res);
-          tr.mode = M_IDLE;
-        }
+      if ((long long)(qb + cnt) >= tr.npaths) exhausted = true;
+    }
+    if (ballot(tr.mode != M_IDLE) == 0) {
+      if (exhausted) break;  // this system is drained for this wavefront
+      continue;
+    }
+    // lanes that hold no path slot sit out the step
+    if (tr.slot) {
+      int fs;
+      double res;
+      tr.step(fs, res);
+      if (fs >= 0) {
+        tr.write_out(fs, res);
+        tr.mode = M_IDLE;
       }
     }
   }
+}
+
+template <class T>
+__device__ __forceinline__ void lane_persistent(const KArgs &a, T &tr) {
+  const int first_sys = blockIdx.x % a.n_systems;
+  for (int v = 0; v < a.n_systems; ++v) lane_drain(a, tr, (first_sys + v) % a.n_systems);
 }
 
 // ------------------------------------------------------------------------

@@ -1,0 +1,62 @@
+// Solve of a small complex system held entirely in registers, for the
+// one-path-per-lane kernels whose Jacobian is a register array (the
+// specialised and the dense kernels).
+#pragma once
+
+#include "hp_device.hpp"
+
+namespace hp {
+
+// LU with partial pivoting (largest |re|+|im| in the column, ties to the
+// lowest row) on the registers, then back substitution into dx.  A row
+// exchange is a select per entry: the pivot row is data dependent and
+// registers cannot be indexed by a lane-varying value.  sing: an exactly
+// zero (or NaN) pivot.
+template <int N>
+__device__ __forceinline__ void reg_lu_solve(cd (&J)[N][N], cd (&b)[N], cd dx[N], bool &sing) {
+  sing = false;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    double best = -1.0;
+    int p = k;
+#pragma unroll
+    for (int i = k; i < N; ++i) {
+      const double c = cabs1(J[i][k]);
+      const bool take = c > best;
+      best = take ? c : best;
+      p = take ? i : p;
+    }
+    if (!(best > 0.0)) sing = true;
+#pragma unroll
+    for (int i = k + 1; i < N; ++i) {
+      const bool sw = (i == p);
+#pragma unroll
+      for (int j = k; j < N; ++j) {
+        const cd u = J[k][j], v = J[i][j];
+        J[k][j] = csel(sw, v, u);
+        J[i][j] = csel(sw, u, v);
+      }
+      const cd u = b[k], v = b[i];
+      b[k] = csel(sw, v, u);
+      b[i] = csel(sw, u, v);
+    }
+    const cd inv = crecip_nr(J[k][k]);
+    J[k][k] = inv;  // kept for the back substitution
+#pragma unroll
+    for (int i = k + 1; i < N; ++i) {
+      const cd l = cmul(J[i][k], inv);
+#pragma unroll
+      for (int j = k + 1; j < N; ++j) J[i][j] = cfms(J[i][j], l, J[k][j]);
+      b[i] = cfms(b[i], l, b[k]);
+    }
+  }
+#pragma unroll
+  for (int k = N - 1; k >= 0; --k) {
+    cd y = b[k];
+#pragma unroll
+    for (int j = k + 1; j < N; ++j) y = cfms(y, J[k][j], dx[j]);
+    dx[k] = cmul(y, J[k][k]);
+  }
+}
+
+}  // namespace hp

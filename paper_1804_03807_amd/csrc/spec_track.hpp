@@ -15,6 +15,7 @@
 #pragma once
 
 #include "lane_track.hpp"
+#include "reg_lu.hpp"
 
 namespace hp {
 
@@ -55,56 +56,7 @@ struct Spec : LaneTrack<Spec<S>, S::N, RkLds<S::N>> {
     }
   }
 
-  // LU with partial pivoting (largest |re|+|im| in the column, ties to the
-  // lowest row) on the registers, then back substitution into dx.  A row
-  // exchange is a select per entry: the pivot row is data dependent and
-  // registers cannot be indexed by a lane-varying value.  sing: an exactly
-  // zero (or NaN) pivot.
-  __device__ __forceinline__ void solve(cd dx[N], bool &sing) {
-    sing = false;
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-      double best = -1.0;
-      int p = k;
-#pragma unroll
-      for (int i = k; i < N; ++i) {
-        const double c = cabs1(J[i][k]);
-        const bool take = c > best;
-        best = take ? c : best;
-        p = take ? i : p;
-      }
-      if (!(best > 0.0)) sing = true;
-#pragma unroll
-      for (int i = k + 1; i < N; ++i) {
-        const bool sw = (i == p);
-#pragma unroll
-        for (int j = k; j < N; ++j) {
-          const cd u = J[k][j], v = J[i][j];
-          J[k][j] = csel(sw, v, u);
-          J[i][j] = csel(sw, u, v);
-        }
-        const cd u = b[k], v = b[i];
-        b[k] = csel(sw, v, u);
-        b[i] = csel(sw, u, v);
-      }
-      const cd inv = crecip_nr(J[k][k]);
-      J[k][k] = inv;  // kept for the back substitution
-#pragma unroll
-      for (int i = k + 1; i < N; ++i) {
-        const cd l = cmul(J[i][k], inv);
-#pragma unroll
-        for (int j = k + 1; j < N; ++j) J[i][j] = cfms(J[i][j], l, J[k][j]);
-        b[i] = cfms(b[i], l, b[k]);
-      }
-    }
-#pragma unroll
-    for (int k = N - 1; k >= 0; --k) {
-      cd y = b[k];
-#pragma unroll
-      for (int j = k + 1; j < N; ++j) y = cfms(y, J[k][j], dx[j]);
-      dx[k] = cmul(y, J[k][k]);
-    }
-  }
+  __device__ __forceinline__ void solve(cd dx[N], bool &sing) { reg_lu_solve<N>(J, b, dx, sing); }
 
   __device__ __forceinline__ double residual() const {
     double r = 0.0;

@@ -18,6 +18,7 @@ NTHREADS = min(16, os.cpu_count() or 1)
 GROUP = [4, 8, 10, 12]
 LANES = [100 + n for n in range(1, 9)] + [207, 208]
 SPEC = [300 + n for n in range(1, 11)]
+DENSE = [400]
 
 
 def log(*a):
@@ -66,10 +67,13 @@ def run_variant(ctx, s, g, code, mode):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("code", GROUP + LANES + SPEC)
+@pytest.mark.parametrize("code", GROUP + LANES + SPEC + DENSE)
 def test_variant_matches_oracle(ctx, name, code):
     s, g = CASES[name]()
-    if (code >= 100 and code % 100 != s.n) or code % 100 < s.n:
+    if code in DENSE:
+        if s.n > 10 or max(s.degrees()) > 3:
+            pytest.skip("the dense kernel takes n <= 10, total degree <= 3")
+    elif (code >= 100 and code % 100 != s.n) or code % 100 < s.n:
         pytest.skip("variant not compiled for this n")
     log(f"case {name} n={s.n} paths={s.bezout()} variant={code}")
     (e, st, sts), t = run_variant(ctx, s, g, code, "batched")
@@ -97,7 +101,7 @@ def test_unknown_variant_rejected(ctx):
     import paper_1804_03807_amd as hp
     s, g = CASES["cyclic6"]()
     plan = ctx.plan(s, g)
-    for bad in (5, 104, 108, 207, 300, 305, 309, 311, -1):
+    for bad in (5, 104, 108, 207, 300, 305, 309, 311, 400, -1):
         with pytest.raises(hp.HomotopyError):
             plan.set_variant(bad)
     plan.close()
@@ -119,7 +123,7 @@ def test_autotune_chooses_a_valid_variant(ctx, tmp_path, monkeypatch):
     torch.cuda.synchronize()
     code = ctx.last_timing()["variant"]
     log(f"autotuned variant {code}")
-    assert code in GROUP + LANES + SPEC
+    assert code in GROUP + LANES + SPEC + DENSE
     assert code < 100 or code % 100 == s.n
     text = cache.read_text().split()
     assert len(text) == 2 and int(text[1]) == code
