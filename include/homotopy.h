@@ -242,10 +242,17 @@ int hp_solve(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_toleran
  * request larger than the free room gets a region of at least 4096 slots
  * and runs chunk by chunk.  Each round of work packs the next chunk of every
  * admitted request (same tolerances) into one multi-system persistent
- * launch, so requests that arrive while others run share the following
- * launches.  HP_E_BUDGET if the budget holds fewer than 4096 slots. */
+ * launch per kernel family (the kernel specialised to a support, shared by
+ * the requests of that support; the dense kernel; the group kernels), so
+ * that requests that arrive while others run share the following launches
+ * and each request runs on the kernel it would get alone.  HP_E_BUDGET if
+ * the budget holds fewer than 4096 slots. */
 int hp_server_create(hp_context *ctx, size_t hbm_budget_bytes, hp_server **out);
-/* Queues a request; the system is copied.  *req_id receives its id. */
+/* Queues a request; the system is copied.  *req_id receives its id.  A
+ * sparse system with n <= 10 runs on the kernel specialised to its support,
+ * which this call compiles (seconds) the first time that support is seen in
+ * the process unless hp_spec_compile did so ahead; the calling thread's
+ * current HIP device becomes the server's. */
 int hp_server_submit(hp_server *srv, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
                      int64_t *req_id);
 /* *done = 1 once every path of the request has finished (non-blocking). */

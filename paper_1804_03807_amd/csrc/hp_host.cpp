@@ -655,7 +655,7 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
   if (!e0) e0 = ctx->ev0;
   if (!e1) e1 = ctx->ev1;
   if (P.nl > k.nmax || (k.lanes && P.nmin != k.nmax) ||
-      (k.spec && (P.sys.size() != 1 || P.nl != k.nmax || !k.sm)) || (k.dense && !P.dense_ok))
+      (k.spec && (P.nl != k.nmax || P.nmin != k.nmax || !k.sm)) || (k.dense && !P.dense_ok))
     return fail(HP_E_INVALID_ARG, "kernel variant does not match the systems' n");
   size_t lds = 0;
   int per_cu = 0, stage = 0;
@@ -1270,6 +1270,7 @@ struct Request {
   int64_t region_off = -1;   // offset in paths into the arena
   bool admitted = false, done = false, failed = false;
   bool dense = false;  // runs on the dense kernel (as it would alone)
+  const hp::SpecModule *sm = nullptr;  // runs on the kernel specialised to its support
 };
 
 }  // namespace
@@ -1363,27 +1364,43 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
   for (auto &R : batch) same += std::memcmp(&R->tol, &tol, sizeof(tol)) == 0;
   const int64_t share = std::max<int64_t>(kMinChunk, kEpochPaths / (int64_t)same);
   // one launch per kernel family, each request on the family it runs on
-  // alone (dense kernel or group kernels), so that its result does not
-  // depend on the other requests of the mix
-  Packed P[2];
-  int64_t total[2] = {0, 0};
+  // alone (its specialised kernel, the dense kernel or the group kernels),
+  // so that its result does not depend on the other requests of the mix
+  std::map<const hp::SpecModule *, size_t> fam_of;  // specialised: one family per module
+  std::vector<Packed> P(2);                          // 0: group kernels, 1: dense kernel
+  std::vector<int64_t> total(2, 0);
+  std::vector<const hp::SpecModule *> fam_sm(2, nullptr);
   std::vector<int64_t> chunk(batch.size(), 0);
   for (size_t i = 0; i < batch.size(); ++i) {
     Request &R = *batch[i];
     if (std::memcmp(&R.tol, &tol, sizeof(tol)) != 0) continue;
     chunk[i] = std::min(std::min(R.info.paths - R.next_path, R.region_paths), share);
+    size_t f = R.dense ? 1 : 0;
+    if (R.sm) {
+      auto it = fam_of.find(R.sm);
+      if (it == fam_of.end()) {
+        it = fam_of.emplace(R.sm, P.size()).first;
+        P.emplace_back();
+        total.push_back(0);
+        fam_sm.push_back(R.sm);
+      }
+      f = it->second;
+    }
     // chunk outputs go to the request's arena region; slots are HP_MAX_N wide
-    Packed &Q = P[R.dense ? 1 : 0];
-    pack_append(Q, &R.sys, R.info, R.gamma, chunk[i], R.region_off, R.region_off * HP_MAX_N,
+    pack_append(P[f], &R.sys, R.info, R.gamma, chunk[i], R.region_off, R.region_off * HP_MAX_N,
                 nullptr);
-    Q.sys.back().id_base = R.next_path;
+    P[f].sys.back().id_base = R.next_path;
     // endpoints of a chunk are packed with stride n inside its region
-    total[R.dense ? 1 : 0] += chunk[i];
+    total[f] += chunk[i];
   }
-  DevTables dev[2];
-  for (int f = 0; f < 2; ++f) {
+  std::vector<DevTables> dev(P.size());
+  for (size_t f = 0; f < P.size(); ++f) {
     if (P[f].sys.empty()) continue;
-    const Kv kv = kv_pick(P[f], ctx);  // P[1]: the dense kernel; P[0]: group kernels
+    Kv kv = kv_pick(P[f], ctx);  // P[1]: the dense kernel; P[0]: group kernels
+    if (fam_sm[f]) {
+      kv_decode(300 + P[f].nl, kv);
+      kv.sm = fam_sm[f];
+    }
     int rc = dev[f].upload(P[f], S->stream);
     if (rc) return rc;
     rc = launch_persistent(ctx, dev[f], P[f], kv, tol, total[f], S->a_ends.as<hp_c64>(),
@@ -1502,6 +1519,17 @@ int hp_server_submit(hp_server *S, const hp_system *f, hp_c64 gamma, const hp_to
     if (kv.nmax < n) return fail(HP_E_UNSUPPORTED_N, "no kernel variant for n");
     if ((rc = check_lds(S->ctx, kv_lds(kv, one)))) return rc;
     R->dense = kv.dense;
+    // systems a specialised kernel serves run on it (compiled here the
+    // first time their support is seen, then shared by every request of
+    // that support)
+    const DevSys &d = one.sys[0];
+    if (!R->dense && hp::spec_eligible(n, one.terms.data(), d.n_terms)) {
+      std::string log;
+      HIP_TRY(hipSetDevice(S->ctx->device));
+      rc = hp::spec_get(S->ctx->device, hp::spec_source(n, d.deg, one.terms.data(), d.n_terms),
+                        &R->sm, log);
+      if (rc) return fail(HP_E_DEVICE, "specialised kernel: " + log);
+    }
   }
   R->eq_ptr.assign(f->eq_ptr, f->eq_ptr + n + 1);
   R->coeff.assign(f->coeff, f->coeff + f->n_terms);

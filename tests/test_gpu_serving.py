@@ -1,9 +1,10 @@
 """GPU tests of the serving loop (hp_server_*): continuous batching of solve
 requests of different sizes, admitted by HBM budget.
 
-* every request's result in the mix equals its result alone (the same
-  batched tracker on its own), endpoint by endpoint within 1e-8 relative and
-  with identical statuses;
+* every request's result in the mix equals its result alone (the request
+  served by itself), endpoint by endpoint within 1e-8 relative and with
+  identical statuses; each request runs on the kernel family it gets alone
+  (its specialised kernel, the dense kernel or a group kernel);
 * a request whose outputs exceed the budget is tracked chunk by chunk and
   still equals the whole-system result; the arena never exceeds the budget;
 * sampled paths of mixed requests match the CPU oracle."""
@@ -48,6 +49,17 @@ def small_requests(count, max_paths):
     return out
 
 
+def served_alone(ctx, s, g):
+    """The request's result from a server that holds nothing else."""
+    import paper_1804_03807_amd as hp
+    srv = hp.Server(ctx, 1 << 30)
+    try:
+        e, st, sts, _ = srv.wait(srv.submit(s, g), stats=True)
+        return e, st, sts
+    finally:
+        srv.close()
+
+
 def assert_same(res, ref, what):
     """res, ref: (endpoints, status, stats) of the same request."""
     hard, flips = compare_paths(*res, *ref)
@@ -58,7 +70,7 @@ def test_alone_equals_mix(ctx):
     import paper_1804_03807_amd as hp
     reqs = small_requests(12, 6000)
     log("requests", [(r, s.name, s.bezout()) for r, s, _ in reqs])
-    alone = {r: ctx.track_paths(s, g) for r, s, g in reqs}
+    alone = {r: served_alone(ctx, s, g) for r, s, g in reqs}
     srv = hp.Server(ctx, 1 << 30)
     try:
         ids = [(r, srv.submit(s, g)) for r, s, g in reqs]
@@ -79,7 +91,7 @@ def test_arrivals_during_work_overlap(ctx):
     complete with the alone result."""
     import paper_1804_03807_amd as hp
     reqs = small_requests(24, 6000)
-    alone = {r: ctx.track_paths(s, g) for r, s, g in reqs}
+    alone = {r: served_alone(ctx, s, g) for r, s, g in reqs}
     arr = W.poisson_arrivals(len(reqs), rate=200.0)
     srv = hp.Server(ctx, 1 << 30)
     ids = {}
@@ -110,9 +122,9 @@ def test_over_budget_request_is_chunked(ctx):
     import paper_1804_03807_amd as hp
     wl = W.cyclic8()
     sys8, g8 = wl.systems[0], complex(wl.gammas[0])
-    ref8 = ctx.track_paths(sys8, g8)
+    ref8 = served_alone(ctx, sys8, g8)
     (r1, s1, g1), = small_requests(1, 1000)
-    ref1 = ctx.track_paths(s1, g1)
+    ref1 = served_alone(ctx, s1, g1)
     budget = 2 * 1000 * 1000
     srv = hp.Server(ctx, budget)
     try:
