@@ -56,50 +56,60 @@ struct Dense : LaneTrack<Dense<N>, N, RkLds<N>> {
 
   // Equation of total degree D whose table starts at c: returns its value
   // and writes its gradient to g.
+  // Table positions (the host fills the table in the same order).
+  static constexpr int kQuad = 1 + N;                     // first x_a x_b
+  static constexpr int kCubic = kQuad + N * (N + 1) / 2;  // first x_a x_b x_c
+  __device__ static constexpr int quad_at(int va, int vb) {
+    return kQuad + va * N - va * (va - 1) / 2 + (vb - va);
+  }
+  __device__ static constexpr int cubic_at(int va, int vb, int vc) {
+    int k = kCubic;
+    for (int u = 0; u < va; ++u) k += (N - u) * (N - u + 1) / 2;
+    for (int u = va; u < vb; ++u) k += N - u;
+    return k + (vc - vb);
+  }
+
   template <int D>
   __device__ __forceinline__ cd equation(cptr<double> c, cd (&g)[N]) const {
-    constexpr int kQuad = 1 + N;                     // first quadratic coefficient
-    constexpr int kCubic = kQuad + N * (N + 1) / 2;  // first cubic coefficient
 #pragma unroll
     for (int v = 0; v < N; ++v) g[v] = {0.0, 0.0};
     cd f = coef(c, 0);
-    int qi = kQuad, ci = kCubic;  // compile-time after unrolling
-#pragma unroll
-    for (int va = 0; va < N; ++va) {
+    sfor<0, N>([&](auto ia) {
+      constexpr int va = decltype(ia)::value;
       // T_a, complete once its b loop is done: folded into f and df/dx_a
       cd T = coef(c, 1 + va);
       if constexpr (D >= 2) {
-#pragma unroll
-        for (int vb = va; vb < N; ++vb) {
-          cd S = coef(c, qi++);
+        sfor<va, N>([&](auto ib) {
+          constexpr int vb = decltype(ib)::value;
+          cd S = coef(c, quad_at(va, vb));
           if constexpr (D >= 3) {
             // two partial sums shorten the dependent chain
             const cd P = cmul(xc[va], xc[vb]);
             cd S1 = {0.0, 0.0};
-#pragma unroll
-            for (int vc = vb; vc < N; ++vc) {
-              const cd k = coef(c, ci++);
-              if ((vc - vb) & 1) S1 = cfma(S1, k, xc[vc]);
+            sfor<vb, N>([&](auto ic) {
+              constexpr int vc = decltype(ic)::value;
+              const cd k = coef(c, cubic_at(va, vb, vc));
+              if constexpr (((vc - vb) & 1) != 0) S1 = cfma(S1, k, xc[vc]);
               else S = cfma(S, k, xc[vc]);
               g[vc] = cfma(g[vc], P, k);
-            }
+            });
             S = cadd(S, S1);
           }
           T = cfma(T, xc[vb], S);
           g[vb] = cfma(g[vb], xc[va], S);
-        }
+        });
       }
       f = cfma(f, xc[va], T);
       g[va] = cadd(g[va], T);
-    }
+    });
     return f;
   }
 
   // [J_x(xc, te) | rhs]: J = t J_f + s J_g, rhs = -H_t, H or f (EvalMode).
   __device__ __forceinline__ void eval(int emode, double te) {
     const cd s = cscale(gamma, 1.0 - te);
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
+    sfor<0, N>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
       cd g[N];
       const cptr<double> c = dc + 2 * off[i];
       const int d = deg[i];
@@ -118,7 +128,11 @@ struct Dense : LaneTrack<Dense<N>, N, RkLds<N>> {
       const cd hv = cadd(cmul(s, gs), cscale(f, te));
       const cd mht = csub(cmul(gamma, gs), f);
       b[i] = csel(emode == EV_F, f, csel(emode == EV_H, hv, mht));
-    }
+      // the finished row as opaque values: equations are not interleaved
+#pragma unroll
+      for (int j = 0; j < N; ++j) asm volatile("" : "+v"(J[i][j].re), "+v"(J[i][j].im));
+      asm volatile("" : "+v"(b[i].re), "+v"(b[i].im));
+    });
     // [J | rhs] reaches the solve as opaque register values (keeps the
     // compiler from interleaving evaluation and elimination)
 #pragma unroll
@@ -129,7 +143,12 @@ struct Dense : LaneTrack<Dense<N>, N, RkLds<N>> {
     }
   }
 
-  __device__ __forceinline__ void solve(cd dx[N], bool &sing) { reg_lu_solve<N>(J, b, dx, sing); }
+  // the current point waits in LDS during the elimination
+  __device__ __forceinline__ void solve(cd dx[N], bool &sing) {
+    this->rk.park(xc);
+    reg_lu_solve<N>(J, b, dx, sing);
+    this->rk.unpark(xc);
+  }
 
   __device__ __forceinline__ double residual() const {
     double r = 0.0;

@@ -112,6 +112,22 @@ __device__ __forceinline__ void addl(lds_char *p, cd c) {
   __hip_atomic_fetch_add(q + 1, c.im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Compile-time loop: f(Int<I>{}) for I = B .. E-1.  Unlike an unrolled
+// runtime loop this cannot be left rolled, so register arrays indexed by I
+// stay in registers (a loop whose bounds depend on an outer loop's index is
+// not always fully unrolled, and its array accesses then go to scratch).
+template <int V>
+struct Int {
+  static constexpr int value = V;
+};
+template <int B, int E, class F>
+__device__ __forceinline__ void sfor(F &&f) {
+  if constexpr (B < E) {
+    f(Int<B>{});
+    sfor<B + 1, E>(f);
+  }
+}
+
 // Right-hand side an evaluation assembles: -H_t (RK4 stages), H (Newton
 // corrector) or f (end game at t = 1).
 enum EvalMode { EV_NEG_HT = 0, EV_H = 1, EV_F = 2 };

@@ -39,10 +39,11 @@ struct RkRegs {
 };
 // Lane-major: slot e of the wavefront is 64 x 16 bytes, lane l's value at
 // byte e * 1024 + l * 16 (every access is one contiguous block); x0 in slots
-// 0..N-1, ks in slots N..2N-1.
+// 0..N-1, ks in slots N..2N-1, and slots 2N..3N-1 park the current point
+// while the elimination needs the registers (park / unpark).
 template <int N>
 struct RkLds {
-  static constexpr int kBytes = 2 * N * 64 * 16;  // per wavefront
+  static constexpr int kBytes = 3 * N * 64 * 16;  // per wavefront
   lds_char *p;  // this lane's value in slot 0
   __device__ __forceinline__ void init() {
 #pragma unroll
@@ -52,6 +53,18 @@ struct RkLds {
   __device__ __forceinline__ void set_x0(int i, cd v) { stl(p + i * 1024, v); }
   __device__ __forceinline__ cd ks(int i) const { return ldl(p + (N + i) * 1024); }
   __device__ __forceinline__ void set_ks(int i, cd v) { stl(p + (N + i) * 1024, v); }
+  // x to LDS and back; the memory barriers keep the compiler from carrying
+  // the values in registers across (it must reload them)
+  __device__ __forceinline__ void park(const cd (&x)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) stl(p + (2 * N + i) * 1024, x[i]);
+    asm volatile("" ::: "memory");
+  }
+  __device__ __forceinline__ void unpark(cd (&x)[N]) {
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = ldl(p + (2 * N + i) * 1024);
+  }
 };
 
 // N: the number of unknowns, exact (a system of another n runs on another

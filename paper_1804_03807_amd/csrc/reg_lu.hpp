@@ -14,49 +14,56 @@ namespace hp {
 // zero (or NaN) pivot.
 template <int N>
 __device__ __forceinline__ void reg_lu_solve(cd (&J)[N][N], cd (&b)[N], cd dx[N], bool &sing) {
+  // compile-time loops throughout: with bounds that depend on the column k,
+  // unrolled runtime loops are not always unrolled fully, and J would then
+  // be indexed at run time and live in scratch memory
   sing = false;
-#pragma unroll
-  for (int k = 0; k < N; ++k) {
+  sfor<0, N>([&](auto ik) {
+    constexpr int k = decltype(ik)::value;
     double best = -1.0;
     int p = k;
-#pragma unroll
-    for (int i = k; i < N; ++i) {
+    sfor<k, N>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
       const double c = cabs1(J[i][k]);
       const bool take = c > best;
       best = take ? c : best;
       p = take ? i : p;
-    }
+    });
     if (!(best > 0.0)) sing = true;
-#pragma unroll
-    for (int i = k + 1; i < N; ++i) {
+    sfor<k + 1, N>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
       const bool sw = (i == p);
-#pragma unroll
-      for (int j = k; j < N; ++j) {
+      sfor<k, N>([&](auto ij) {
+        constexpr int j = decltype(ij)::value;
         const cd u = J[k][j], v = J[i][j];
         J[k][j] = csel(sw, v, u);
         J[i][j] = csel(sw, u, v);
-      }
+      });
       const cd u = b[k], v = b[i];
       b[k] = csel(sw, v, u);
       b[i] = csel(sw, u, v);
-    }
+    });
     const cd inv = crecip_nr(J[k][k]);
     J[k][k] = inv;  // kept for the back substitution
-#pragma unroll
-    for (int i = k + 1; i < N; ++i) {
+    sfor<k + 1, N>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
       const cd l = cmul(J[i][k], inv);
-#pragma unroll
-      for (int j = k + 1; j < N; ++j) J[i][j] = cfms(J[i][j], l, J[k][j]);
+      sfor<k + 1, N>([&](auto ij) {
+        constexpr int j = decltype(ij)::value;
+        J[i][j] = cfms(J[i][j], l, J[k][j]);
+      });
       b[i] = cfms(b[i], l, b[k]);
-    }
-  }
-#pragma unroll
-  for (int k = N - 1; k >= 0; --k) {
+    });
+  });
+  sfor<0, N>([&](auto ir) {
+    constexpr int k = N - 1 - decltype(ir)::value;
     cd y = b[k];
-#pragma unroll
-    for (int j = k + 1; j < N; ++j) y = cfms(y, J[k][j], dx[j]);
+    sfor<k + 1, N>([&](auto ij) {
+      constexpr int j = decltype(ij)::value;
+      y = cfms(y, J[k][j], dx[j]);
+    });
     dx[k] = cmul(y, J[k][k]);
-  }
+  });
 }
 
 }  // namespace hp

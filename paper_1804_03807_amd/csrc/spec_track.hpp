@@ -56,7 +56,12 @@ struct Spec : LaneTrack<Spec<S>, S::N, RkLds<S::N>> {
     }
   }
 
-  __device__ __forceinline__ void solve(cd dx[N], bool &sing) { reg_lu_solve<N>(J, b, dx, sing); }
+  // the current point waits in LDS during the elimination
+  __device__ __forceinline__ void solve(cd dx[N], bool &sing) {
+    this->rk.park(xc);
+    reg_lu_solve<N>(J, b, dx, sing);
+    this->rk.unpark(xc);
+  }
 
   __device__ __forceinline__ double residual() const {
     double r = 0.0;
