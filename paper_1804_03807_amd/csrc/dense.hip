@@ -127,24 +127,21 @@ struct Dense : LaneTrack<Dense<N>, N, RkLds<N>> {
       J[i][i] = cadd(J[i][i], cmul(s, cscale(xq, (double)d)));
       const cd hv = cadd(cmul(s, gs), cscale(f, te));
       const cd mht = csub(cmul(gamma, gs), f);
-      b[i] = csel(emode == EV_F, f, csel(emode == EV_H, hv, mht));
+      // the right-hand side waits in the lane's spare LDS slots until the
+      // solve, leaving the registers to the Jacobian rows
+      this->rk.set_spare(i, csel(emode == EV_F, f, csel(emode == EV_H, hv, mht)));
       // the finished row as opaque values: equations are not interleaved
 #pragma unroll
       for (int j = 0; j < N; ++j) asm volatile("" : "+v"(J[i][j].re), "+v"(J[i][j].im));
-      asm volatile("" : "+v"(b[i].re), "+v"(b[i].im));
     });
-    // [J | rhs] reaches the solve as opaque register values (keeps the
-    // compiler from interleaving evaluation and elimination)
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-#pragma unroll
-      for (int j = 0; j < N; ++j) asm volatile("" : "+v"(J[i][j].re), "+v"(J[i][j].im));
-      asm volatile("" : "+v"(b[i].re), "+v"(b[i].im));
-    }
+    asm volatile("" ::: "memory");
   }
 
-  // the current point waits in LDS during the elimination
+  // right-hand side from LDS; the current point waits in LDS during the
+  // elimination
   __device__ __forceinline__ void solve(cd dx[N], bool &sing) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) b[i] = this->rk.spare(i);
     this->rk.park(xc);
     reg_lu_solve<N>(J, b, dx, sing);
     this->rk.unpark(xc);
@@ -153,7 +150,7 @@ struct Dense : LaneTrack<Dense<N>, N, RkLds<N>> {
   __device__ __forceinline__ double residual() const {
     double r = 0.0;
 #pragma unroll
-    for (int i = 0; i < N; ++i) r = nmax(r, cmod(b[i]));
+    for (int i = 0; i < N; ++i) r = nmax(r, cmod(this->rk.spare(i)));
     return r;
   }
 };

@@ -53,6 +53,9 @@ struct RkLds {
   __device__ __forceinline__ void set_x0(int i, cd v) { stl(p + i * 1024, v); }
   __device__ __forceinline__ cd ks(int i) const { return ldl(p + (N + i) * 1024); }
   __device__ __forceinline__ void set_ks(int i, cd v) { stl(p + (N + i) * 1024, v); }
+  // slot 2N + i (the parking slots) one value at a time
+  __device__ __forceinline__ cd spare(int i) const { return ldl(p + (2 * N + i) * 1024); }
+  __device__ __forceinline__ void set_spare(int i, cd v) { stl(p + (2 * N + i) * 1024, v); }
   // x to LDS and back; the memory barriers keep the compiler from carrying
   // the values in registers across (it must reload them)
   __device__ __forceinline__ void park(const cd (&x)[N]) {
