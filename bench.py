@@ -34,14 +34,15 @@ TRAFFIC_PROFILE = {
     "workload": "cyclic8",
     "variant": 308,
     "sources_sha256": {
-        "spec_track.hpp": "631195aad601ec68dec03ec7c5f935ab06450d629319c25b4645962199a3bb6d",
-        "lane_track.hpp": "aed01d67c6847aef3b8f0f99d499d542926987522c11a5a7ceea007620ba3dcb",
-        "hp_device.hpp": "59e9abb60ed3f145295bcf480824c4d0bcd5e1685c2d5892c48171b3a34134d4",
-        "hp_internal.hpp": "d8d670ae2a8630ffe925e804b39d702d4bf60bb806a0de39e8832bc0e4af05f8",
-        "hp_jit.cpp": "46e759b11eb3772d8f74dbefe64351f6821b96d12000914a554c40044468ce28",
+        "spec_track.hpp": "d4e493b4c891742f16210b763f1fb7f52de1881cd8858fd50e3afb5126c3b9d6",
+        "lane_track.hpp": "0e9327b3608a565f542e4baa4bb08383ed115b936fdd1fea46357a474006ac28",
+        "hp_device.hpp": "f785014ca74114e45d5b32364f08af0b41660996c35cbf08085ef6fbc53b0a3e",
+        "hp_internal.hpp": "cd88d14afd5e4f63601afe4c22505eac7f4dc8c3359e73ffac36511be2f626e2",
+        "hp_jit.cpp": "e5e4f33bc6bfe8887e2fed04ea619062690429de2c117062dc2e46a44640f3a7",
+        "reg_lu.hpp": "ad427109a098bb4ecee85321685be37648315ec356c45e1478d2bed7824eda6e",
     },
-    "fetch_kib": 563.0, "fetch_scale": 262144 / 131088.5,
-    "write_kib": 6812.34375, "write_scale": 262144 / 262144,
+    "fetch_kib": 570.5, "fetch_scale": 262144 / 131092.6875,
+    "write_kib": 6812.40625, "write_scale": 262144 / 262144,
 }
 
 WORKLOADS = {
