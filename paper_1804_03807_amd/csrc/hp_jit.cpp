@@ -93,7 +93,7 @@ std::string spec_source(int n, const int32_t *deg, const DevTerm *terms, int n_t
     << "  static constexpr int N = " << n << ";\n"
     << "  __device__ __forceinline__ static void eval(cptr<double2> cf, const cd (&x)[N], double te,\n"
     << "                                              cd s, cd gamma, int emode, cd (&J)[N][N],\n"
-    << "                                              cd (&b)[N]) {\n";
+    << "                                              lds_char *spare) {\n";
   for (int v = 0; v < n; ++v) {
     o << "    const cd " << pw(v, 1) << " = x[" << v << "];\n";
     for (int e = 2; e <= emax[v]; ++e)
@@ -101,6 +101,12 @@ std::string spec_source(int n, const int32_t *deg, const DevTerm *terms, int n_t
   }
   o << "    cd F[N];\n";
   std::vector<char> jt((size_t)n * n, 0), ft(n, 0);
+  // an equation's value goes to the lane's spare LDS slot after its last
+  // term (out of the registers the Jacobian needs), its right-hand side
+  // replaces it there at the end
+  std::vector<int> last(n, -1);
+  for (int t = 0; t < n_terms; ++t) last[T[t].eq] = t;
+  auto slot = [](int i) { return "spare + " + std::to_string(i * 1024); };
   auto add_f = [&](int eq, const std::string &val) {
     const std::string fe = "F[" + std::to_string(eq) + "]";
     if (ft[eq]) o << "      " << fe << " = cadd(" << fe << ", " << val << ");\n";
@@ -114,6 +120,7 @@ std::string spec_source(int n, const int32_t *deg, const DevTerm *terms, int n_t
     if (K == 0) {
       add_f(g.eq, "c");
       o << "    }\n";
+      if (last[g.eq] == t) o << "    stl(" << slot(g.eq) << ", F[" << g.eq << "]);\n";
       continue;
     }
     for (int m = 0; m < K; ++m)
@@ -144,12 +151,14 @@ std::string spec_source(int n, const int32_t *deg, const DevTerm *terms, int n_t
       }
     }
     o << "    }\n";
+    if (last[g.eq] == t) o << "    stl(" << slot(g.eq) << ", F[" << g.eq << "]);\n";
   }
   for (int i = 0; i < n; ++i) {
-    if (!ft[i]) o << "    F[" << i << "] = {0.0, 0.0};\n";
+    if (!ft[i]) o << "    stl(" << slot(i) << ", cd{0.0, 0.0});\n";
     for (int j = 0; j < n; ++j)
       if (!jt[(size_t)i * n + j]) o << "    " << jn(i, j) << " = {0.0, 0.0};\n";
   }
+  o << "    asm volatile(\"\" ::: \"memory\");  // values are reloaded, not kept in registers\n";
   // start system x_i^{d_i} - 1 and the right-hand side; the powers x_i^e,
   // e < d_i, are formed here (live only in this block) by the same chain of
   // products as the term powers
@@ -166,10 +175,10 @@ std::string spec_source(int n, const int32_t *deg, const DevTerm *terms, int n_t
     o << "      cd g = cmul(xq, " << xi << ");\n"
       << "      g.re -= 1.0;\n"
       << "      " << jn(i, i) << " = cadd(" << jn(i, i) << ", cmul(s, cscale(xq, " << d << ".0)));\n"
-      << "      const cd f = F[" << i << "];\n"
+      << "      const cd f = ldl(" << slot(i) << ");\n"
       << "      const cd hv = cadd(cmul(s, g), cscale(f, te));\n"
       << "      const cd mht = csub(cmul(gamma, g), f);\n"
-      << "      b[" << i << "] = csel(emode == EV_F, f, csel(emode == EV_H, hv, mht));\n"
+      << "      stl(" << slot(i) << ", csel(emode == EV_F, f, csel(emode == EV_H, hv, mht)));\n"
       << "    }\n";
   }
   o << "  }\n};\n\n}  // namespace gen\n}  // namespace hp\n\n"

@@ -54,6 +54,7 @@ struct RkLds {
   __device__ __forceinline__ cd ks(int i) const { return ldl(p + (N + i) * 1024); }
   __device__ __forceinline__ void set_ks(int i, cd v) { stl(p + (N + i) * 1024, v); }
   // slot 2N + i (the parking slots) one value at a time
+  __device__ __forceinline__ lds_char *spare_base() const { return p + 2 * N * 1024; }
   __device__ __forceinline__ cd spare(int i) const { return ldl(p + (2 * N + i) * 1024); }
   __device__ __forceinline__ void set_spare(int i, cd v) { stl(p + (2 * N + i) * 1024, v); }
   // x to LDS and back; the memory barriers keep the compiler from carrying

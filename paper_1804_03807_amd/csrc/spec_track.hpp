@@ -9,9 +9,10 @@
 // S provides
 //   static constexpr int N;
 //   static void eval(cptr<double2> cf, const cd (&x)[N], double te, cd s,
-//                    cd gamma, int emode, cd (&J)[N][N], cd (&b)[N]);
+//                    cd gamma, int emode, cd (&J)[N][N], lds_char *spare);
 // which writes J = t J_f + s J_g at (x, te) with s = gamma (1 - te), and
-// b = -H_t (EV_NEG_HT), H (EV_H) or f (EV_F), as the other kernels do.
+// the right-hand side -H_t (EV_NEG_HT), H (EV_H) or f (EV_F), as the other
+// kernels do, to the lane's LDS slots spare + i * 1024.
 #pragma once
 
 #include "lane_track.hpp"
@@ -43,21 +44,27 @@ struct Spec : LaneTrack<Spec<S>, S::N, RkLds<S::N>> {
     coef = as_const(a.tcoef) + sp->term_base;
   }
 
+  // [J | rhs]: J in registers, the right-hand side in the lane's spare LDS
+  // slots (the evaluator leaves each equation's value there after its last
+  // term, then its right-hand side)
   __device__ __forceinline__ void eval(int emode, double te) {
-    S::eval(coef, xc, te, cscale(gamma, 1.0 - te), gamma, emode, J, b);
-    // Hand [J | rhs] over to the solve as opaque register values: otherwise
-    // the compiler interleaves the evaluation with the elimination and needs
+    S::eval(coef, xc, te, cscale(gamma, 1.0 - te), gamma, emode, J, this->rk.spare_base());
+    // Hand J over to the solve as opaque register values: otherwise the
+    // compiler interleaves the evaluation with the elimination and needs
     // far more registers than either (scratch spills from n = 7 on).
 #pragma unroll
     for (int i = 0; i < N; ++i) {
 #pragma unroll
       for (int j = 0; j < N; ++j) asm volatile("" : "+v"(J[i][j].re), "+v"(J[i][j].im));
-      asm volatile("" : "+v"(b[i].re), "+v"(b[i].im));
     }
+    asm volatile("" ::: "memory");
   }
 
-  // the current point waits in LDS during the elimination
+  // right-hand side from LDS; the current point waits in LDS during the
+  // elimination
   __device__ __forceinline__ void solve(cd dx[N], bool &sing) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) b[i] = this->rk.spare(i);
     this->rk.park(xc);
     reg_lu_solve<N>(J, b, dx, sing);
     this->rk.unpark(xc);
@@ -66,7 +73,7 @@ struct Spec : LaneTrack<Spec<S>, S::N, RkLds<S::N>> {
   __device__ __forceinline__ double residual() const {
     double r = 0.0;
 #pragma unroll
-    for (int i = 0; i < N; ++i) r = nmax(r, cmod(b[i]));
+    for (int i = 0; i < N; ++i) r = nmax(r, cmod(this->rk.spare(i)));
     return r;
   }
 };
