@@ -34,15 +34,15 @@ TRAFFIC_PROFILE = {
     "workload": "cyclic8",
     "variant": 308,
     "sources_sha256": {
-        "spec_track.hpp": "d4e493b4c891742f16210b763f1fb7f52de1881cd8858fd50e3afb5126c3b9d6",
-        "lane_track.hpp": "0e9327b3608a565f542e4baa4bb08383ed115b936fdd1fea46357a474006ac28",
+        "spec_track.hpp": "3b1160d5bcf9e1f1ce43ac17352c3a0c74c593841c712ee6957c4a5d1719be9e",
+        "lane_track.hpp": "799f28d0cf38588c4c3355cb03561a850a4df11bda9a4af936ecaeb790c008cf",
         "hp_device.hpp": "f785014ca74114e45d5b32364f08af0b41660996c35cbf08085ef6fbc53b0a3e",
         "hp_internal.hpp": "cd88d14afd5e4f63601afe4c22505eac7f4dc8c3359e73ffac36511be2f626e2",
-        "hp_jit.cpp": "e5e4f33bc6bfe8887e2fed04ea619062690429de2c117062dc2e46a44640f3a7",
+        "hp_jit.cpp": "68ea891f83569c2ac813abe655cbad7017d071dd90b2a6914bb17cad6a746e10",
         "reg_lu.hpp": "ad427109a098bb4ecee85321685be37648315ec356c45e1478d2bed7824eda6e",
     },
-    "fetch_kib": 570.5, "fetch_scale": 262144 / 131092.6875,
-    "write_kib": 6812.40625, "write_scale": 262144 / 262144,
+    "fetch_kib": 562.5, "fetch_scale": 262144 / 131092.25,
+    "write_kib": 6812.71875, "write_scale": 262144 / 262144,
 }
 
 WORKLOADS = {

@@ -40,6 +40,8 @@ CASES = {
     "cyclic7": lambda: (W.cyclic_workload(7, 7).systems[0], complex(W.cyclic_workload(7, 7).gammas[0])),
     "dense3_d3": lambda: (W.dense_system(3, [3, 3, 2], np.random.default_rng(33)), 0.6 + 0.8j),
     "dense8_d2": lambda: (W.dense_system(8, [2] * 8, np.random.default_rng(34)), np.exp(0.3j)),
+    # a linear, a quadratic and a cubic equation (every block of the dense table)
+    "dense3_d123": lambda: (W.dense_system(3, [1, 2, 3], np.random.default_rng(35)), np.exp(1.1j)),
 }
 _oracle_cache = {}
 
