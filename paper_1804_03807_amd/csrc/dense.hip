@@ -11,8 +11,10 @@
 // df/dx_b += x_a S_ab, df/dx_c += x_a x_b k_abc (repeated indices give the
 // multiplicities of squares and cubes by themselves).  Two complex
 // multiply-adds per cubic monomial, every index a compile-time constant, so
-// the Jacobian row is a register array and the whole [J | rhs] stays in
-// registers for the register LU, as in the kernels specialised at run time.
+// the Jacobian row is a register array and the whole Jacobian stays in
+// registers for the register LU, as in the kernels specialised at run time;
+// the right-hand side, the RK4 state and (during the solve) the current
+// point sit in the lane's own LDS slots.
 // The partial derivatives are scaled by t and the start system
 // g_i = x_i^{d_i} - 1 is added as in the other kernels (paper: Section 1;
 // the end of Section 2.1 for independent paths).

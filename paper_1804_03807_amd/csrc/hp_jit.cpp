@@ -339,7 +339,10 @@ int spec_get(int device, const std::string &src, const SpecModule **out, std::st
   hipError_t e = hipModuleLoadData(&m->mod, code.data());
   if (e == hipSuccess) e = hipModuleGetFunction(&m->persistent, m->mod, "hp_spec_persistent");
   if (e == hipSuccess) e = hipModuleGetFunction(&m->plain, m->mod, "hp_spec_plain");
-  if (e != hipSuccess) return (int)e;
+  if (e != hipSuccess) {
+    if (m->mod) (void)hipModuleUnload(m->mod);
+    return (int)e;
+  }
   *out = m.get();
   cache.emplace(std::move(key), std::move(m));
   return (int)hipSuccess;

@@ -3,8 +3,10 @@
 // with the support, exponents and start-system degrees compiled in; only the
 // coefficients are read from memory, through scalar loads) and compiles it
 // with this header through hiprtc.  Every index is then a compile-time
-// constant, so the Jacobian [J | rhs] of a lane's path lives in registers:
-// no LDS, no atomics, and the term loop is plain FP64 arithmetic.
+// constant, so the Jacobian of a lane's path lives in registers: no atomics,
+// and the term loop is plain FP64 arithmetic.  What the registers cannot
+// also hold sits in the lane's own LDS slots: its RK4 state, its equation
+// values and right-hand side, and its current point during the solve.
 //
 // S provides
 //   static constexpr int N;
@@ -20,8 +22,7 @@
 
 namespace hp {
 
-// x0 and ks sit in the lane's LDS slots (RkLds: 2N x 1 KB per wavefront),
-// leaving the registers to [J | rhs].
+// LDS slots per wavefront: RkLds<N> (3N x 1 KB).
 template <class S>
 struct Spec : LaneTrack<Spec<S>, S::N, RkLds<S::N>> {
   static constexpr int N = S::N;
