@@ -34,11 +34,11 @@ TRAFFIC_PROFILE = {
     "workload": "cyclic8",
     "variant": 308,
     "sources_sha256": {
-        "spec_track.hpp": "3b1160d5bcf9e1f1ce43ac17352c3a0c74c593841c712ee6957c4a5d1719be9e",
+        "spec_track.hpp": "6508c4afd886b2feb9f3ffdadc085ad985944583a96351c047ac7d53d614c871",
         "lane_track.hpp": "799f28d0cf38588c4c3355cb03561a850a4df11bda9a4af936ecaeb790c008cf",
         "hp_device.hpp": "f785014ca74114e45d5b32364f08af0b41660996c35cbf08085ef6fbc53b0a3e",
         "hp_internal.hpp": "cd88d14afd5e4f63601afe4c22505eac7f4dc8c3359e73ffac36511be2f626e2",
-        "hp_jit.cpp": "68ea891f83569c2ac813abe655cbad7017d071dd90b2a6914bb17cad6a746e10",
+        "hp_jit.cpp": "4b489fc1add9e7d03fd1830751f73ac383abb2a75cece9fb32d4fb79ffe9a8f0",
         "reg_lu.hpp": "ad427109a098bb4ecee85321685be37648315ec356c45e1478d2bed7824eda6e",
     },
     "fetch_kib": 562.5, "fetch_scale": 262144 / 131092.25,
