@@ -1275,11 +1275,17 @@ struct Request {
 
 }  // namespace
 
+// Streams on which the kernel families of an epoch run side by side (with
+// the server's own stream the process holds four hardware queues).
+constexpr int kFamilyStreams = 3;
+
 struct hp_server {
   hp_context *ctx = nullptr;
   size_t budget = 0, resident = 0, peak = 0;
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipStream_t fam_stream[kFamilyStreams] = {};
+  hipEvent_t fam_ev[kFamilyStreams][2] = {};
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<std::shared_ptr<Request>> pending;
@@ -1393,22 +1399,27 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
     // endpoints of a chunk are packed with stride n inside its region
     total[f] += chunk[i];
   }
+  // the families run side by side (their requests' arena regions are
+  // disjoint), each on one of the family streams
   std::vector<DevTables> dev(P.size());
-  for (size_t f = 0; f < P.size(); ++f) {
+  int rc = HP_OK;
+  for (size_t f = 0, used = 0; f < P.size() && rc == HP_OK; ++f) {
     if (P[f].sys.empty()) continue;
+    const int q = (int)(used++ % kFamilyStreams);
     Kv kv = kv_pick(P[f], ctx);  // P[1]: the dense kernel; P[0]: group kernels
     if (fam_sm[f]) {
       kv_decode(300 + P[f].nl, kv);
       kv.sm = fam_sm[f];
     }
-    int rc = dev[f].upload(P[f], S->stream);
-    if (rc) return rc;
-    rc = launch_persistent(ctx, dev[f], P[f], kv, tol, total[f], S->a_ends.as<hp_c64>(),
-                           S->a_status.as<int32_t>(), S->a_stats.as<hp_path_stats>(), S->stream,
-                           nullptr, S->ev0, S->ev1);
-    if (rc) return rc;
+    rc = dev[f].upload(P[f], S->fam_stream[q]);
+    if (rc == HP_OK)
+      rc = launch_persistent(ctx, dev[f], P[f], kv, tol, total[f], S->a_ends.as<hp_c64>(),
+                             S->a_status.as<int32_t>(), S->a_stats.as<hp_path_stats>(),
+                             S->fam_stream[q], nullptr, S->fam_ev[q][0], S->fam_ev[q][1]);
   }
-  HIP_TRY(hipStreamSynchronize(S->stream));
+  // every launched family ends before its tables are freed or read back
+  for (int q = 0; q < kFamilyStreams; ++q) HIP_TRY(hipStreamSynchronize(S->fam_stream[q]));
+  if (rc) return rc;
   // copy finished chunks to the requests' host results
   for (size_t i = 0; i < batch.size(); ++i) {
     Request &R = *batch[i];
@@ -1494,6 +1505,11 @@ int hp_server_create(hp_context *ctx, size_t hbm_budget_bytes, hp_server **out) 
   HIP_TRY(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
   HIP_TRY(hipEventCreate(&S->ev0));
   HIP_TRY(hipEventCreate(&S->ev1));
+  for (int f = 0; f < kFamilyStreams; ++f) {
+    HIP_TRY(hipStreamCreateWithFlags(&S->fam_stream[f], hipStreamNonBlocking));
+    HIP_TRY(hipEventCreate(&S->fam_ev[f][0]));
+    HIP_TRY(hipEventCreate(&S->fam_ev[f][1]));
+  }
   hp_server *raw = S.get();
   S->worker = std::thread(worker_main, raw);
   *out = S.release();
@@ -1597,6 +1613,12 @@ void hp_server_destroy(hp_server *S) {
   if (S->worker.joinable()) S->worker.join();
   (void)hipSetDevice(S->ctx->device);
   if (S->stream) (void)hipStreamSynchronize(S->stream);
+  for (int f = 0; f < kFamilyStreams; ++f) {
+    if (S->fam_stream[f]) (void)hipStreamSynchronize(S->fam_stream[f]);
+    for (int e = 0; e < 2; ++e)
+      if (S->fam_ev[f][e]) (void)hipEventDestroy(S->fam_ev[f][e]);
+    if (S->fam_stream[f]) (void)hipStreamDestroy(S->fam_stream[f]);
+  }
   if (S->ev0) (void)hipEventDestroy(S->ev0);
   if (S->ev1) (void)hipEventDestroy(S->ev1);
   if (S->stream) (void)hipStreamDestroy(S->stream);
