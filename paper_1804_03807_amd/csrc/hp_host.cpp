@@ -250,7 +250,7 @@ int32_t pack_terms(Packed &P, const hp_system *f, int32_t term_base) {
 // x_a; x_a x_b, a <= b; x_a x_b x_c, a <= b <= c; a outermost).
 bool pack_dense(Packed &P, const hp_system *f, const SysInfo &info, DevSys &d) {
   const int n = f->n;
-  if (n > hp::kDenseMaxN) return false;
+  if (n > hp::kDenseWideMaxN) return false;
   for (int i = 0; i < n; ++i)
     if (info.deg[i] > hp::kDenseMaxDeg) return false;
   const int nq = n * (n + 1) / 2, nc = n * (n + 1) * (n + 2) / 6;
@@ -423,19 +423,35 @@ bool kv_decode(int code, Kv &k) {
     k.pw = hp::kLanes;
     return true;
   }
-  if (code == kDenseCode) {
+  if (code == kDenseCode || (code > kDenseCode + hp::kDenseMaxN &&
+                             code <= kDenseCode + hp::kDenseWideMaxN)) {
     k.dense = true;
-    k.nmax = hp::kDenseMaxN;
+    k.nmax = code == kDenseCode ? hp::kDenseMaxN : code - kDenseCode;
     k.pw = hp::kLanes;
     return true;
   }
   return false;
 }
 
+// Dense kernel for the systems of P: 400 (k_dense) when every n <= kDenseMaxN,
+// 400 + n (k_dense11, k_dense12) when they all have that one larger n, else 0.
+int dense_code_for(const Packed &P) {
+  if (!P.dense_ok) return 0;
+  if (P.nl <= hp::kDenseMaxN) return kDenseCode;
+  if (P.nmin == P.nl && P.nl <= hp::kDenseWideMaxN) return kDenseCode + P.nl;
+  return 0;
+}
+
+// True when kernel k runs the systems of P.
+bool dense_fits(const Kv &k, const Packed &P) {
+  return k.dense && P.dense_ok &&
+         (k.code == kDenseCode ? P.nl <= hp::kDenseMaxN : (P.nmin == k.nmax && P.nl == k.nmax));
+}
+
 // The dense kernel is the default for launches whose systems all have dense
 // tables filled to at least a quarter (sparser systems evaluate faster term
 // by term).
-bool dense_preferred(const Packed &P) { return P.dense_ok && P.dense_fill >= 0.25; }
+int dense_preferred(const Packed &P) { return P.dense_fill >= 0.25 ? dense_code_for(P) : 0; }
 
 // Variants that can run systems of up to n unknowns and exponents up to
 // emax within max_lds bytes of LDS (group kernels: checked per system).
@@ -617,7 +633,9 @@ int kv_occupancy(hp_context *ctx, const Kv &k, const Packed &P, size_t *lds, int
     HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k.sm->persistent, hp::kLanes, 0));
   } else if (k.dense) {
     *lds = 0;
-    HIP_TRY((hipError_t)hp_dense_per_cu(per_cu));
+    if (k.code == kDenseCode) HIP_TRY((hipError_t)hp_dense_per_cu(per_cu));
+    else if (k.nmax == 11) HIP_TRY((hipError_t)hp_dense11_per_cu(per_cu));
+    else HIP_TRY((hipError_t)hp_dense12_per_cu(per_cu));
   } else if (k.lanes) {
     *lds = kv_lds(k, P);
     int rc = check_lds(ctx, *lds);
@@ -642,7 +660,7 @@ int kv_occupancy(hp_context *ctx, const Kv &k, const Packed &P, size_t *lds, int
 // all systems.
 Kv kv_pick(const Packed &P, const hp_context *ctx) {
   Kv k;
-  if (dense_preferred(P)) kv_decode(kDenseCode, k);
+  if (const int dc = dense_preferred(P)) kv_decode(dc, k);
   else kv_decode(P.nmin == P.nl ? kv_default(P.nl, P.emax, ctx->max_lds) : nmax_for(P.nl), k);
   return k;
 }
@@ -655,7 +673,7 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
   if (!e0) e0 = ctx->ev0;
   if (!e1) e1 = ctx->ev1;
   if (P.nl > k.nmax || (k.lanes && P.nmin != k.nmax) ||
-      (k.spec && (P.nl != k.nmax || P.nmin != k.nmax || !k.sm)) || (k.dense && !P.dense_ok))
+      (k.spec && (P.nl != k.nmax || P.nmin != k.nmax || !k.sm)) || (k.dense && !dense_fits(k, P)))
     return fail(HP_E_INVALID_ARG, "kernel variant does not match the systems' n");
   size_t lds = 0;
   int per_cu = 0, stage = 0;
@@ -687,7 +705,9 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
     HIP_TRY(hipModuleLaunchKernel(k.sm->persistent, (unsigned)groups, 1, 1, hp::kLanes, 1, 1, 0, s,
                                   params, nullptr));
   } else if (k.dense) {
-    HIP_TRY((hipError_t)hp_launch_dense(a, (int)groups, s));
+    if (k.code == kDenseCode) HIP_TRY((hipError_t)hp_launch_dense(a, (int)groups, s));
+    else if (k.nmax == 11) HIP_TRY((hipError_t)hp_launch_dense11(a, (int)groups, s));
+    else HIP_TRY((hipError_t)hp_launch_dense12(a, (int)groups, s));
   } else if (k.lanes) {
     HIP_TRY((hipError_t)hp_launch_lanes(k.nmax, k.pw, a, (int)groups, lds, s));
   } else {
@@ -720,19 +740,21 @@ int spec_prepare(hp_plan *plan, Kv &k) {
 
 int plan_variant(hp_plan *plan, int code) {
   if (code == 0) {
+    const int dc = dense_preferred(plan->P);
     code = (plan->spec_default && plan_spec_eligible(plan)) ? 300 + plan->info.n
-           : dense_preferred(plan->P) ? kDenseCode
-                                      : kv_default(plan->info.n, plan->info.emax, plan->ctx->max_lds);
+           : dc ? dc
+                : kv_default(plan->info.n, plan->info.emax, plan->ctx->max_lds);
   }
   Kv k;
   if (!kv_decode(code, k) || k.nmax < plan->info.n ||
-      ((k.lanes || k.spec) && k.nmax != plan->info.n))
+      ((k.lanes || k.spec || (k.dense && k.code != kDenseCode)) && k.nmax != plan->info.n))
     return fail(HP_E_INVALID_ARG, "no compiled kernel variant " + std::to_string(code) +
                                       " for n = " + std::to_string(plan->info.n));
   if ((k.lanes || k.spec || k.dense) && plan->P.general)
     return fail(HP_E_INVALID_ARG, "lane kernels track the total-degree start system only");
-  if (k.dense && !plan->P.dense_ok)
-    return fail(HP_E_INVALID_ARG, "the dense kernel takes n <= " + std::to_string(hp::kDenseMaxN) +
+  if (k.dense && !dense_fits(k, plan->P))
+    return fail(HP_E_INVALID_ARG, "the dense kernels take n <= " +
+                                      std::to_string(hp::kDenseWideMaxN) +
                                       " and equations of total degree <= " +
                                       std::to_string(hp::kDenseMaxDeg));
   if (k.spec) {
@@ -833,7 +855,8 @@ int autotune(hp_plan *plan) {
   Kv best_k = plan->kv;
   std::vector<int> cands = kv_candidates(plan->info.n, plan->P.emax, ctx->max_lds);
   if (plan_spec_eligible(plan)) cands.insert(cands.begin(), 300 + plan->info.n);
-  if (plan->P.dense_ok && !plan->P.general) cands.push_back(kDenseCode);
+  if (!plan->P.general)
+    if (const int dc = dense_code_for(plan->P)) cands.push_back(dc);
   for (int code : cands) {
     Kv k;
     if (!kv_decode(code, k) || check_lds(ctx, kv_lds(k, plan->P)) != HP_OK) continue;
@@ -1269,7 +1292,7 @@ struct Request {
   int64_t region_paths = 0;  // capacity in paths
   int64_t region_off = -1;   // offset in paths into the arena
   bool admitted = false, done = false, failed = false;
-  bool dense = false;  // runs on the dense kernel (as it would alone)
+  int dense_code = 0;  // runs on this dense kernel (as it would alone), 0: not dense
   const hp::SpecModule *sm = nullptr;  // runs on the kernel specialised to its support
 };
 
@@ -1372,26 +1395,35 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
   // one launch per kernel family, each request on the family it runs on
   // alone (its specialised kernel, the dense kernel or the group kernels),
   // so that its result does not depend on the other requests of the mix
-  std::map<const hp::SpecModule *, size_t> fam_of;  // specialised: one family per module
-  std::vector<Packed> P(2);                          // 0: group kernels, 1: dense kernel
-  std::vector<int64_t> total(2, 0);
-  std::vector<const hp::SpecModule *> fam_sm(2, nullptr);
+  // family key: (300, module) for a specialised kernel, (dense code,
+  // nullptr) for a dense kernel, (0, nullptr) for the group kernels
+  std::map<std::pair<int, const void *>, size_t> fam_of;
+  std::vector<Packed> P;
+  std::vector<int64_t> total;
+  std::vector<Kv> fam_kv;
   std::vector<int64_t> chunk(batch.size(), 0);
   for (size_t i = 0; i < batch.size(); ++i) {
     Request &R = *batch[i];
     if (std::memcmp(&R.tol, &tol, sizeof(tol)) != 0) continue;
     chunk[i] = std::min(std::min(R.info.paths - R.next_path, R.region_paths), share);
-    size_t f = R.dense ? 1 : 0;
-    if (R.sm) {
-      auto it = fam_of.find(R.sm);
-      if (it == fam_of.end()) {
-        it = fam_of.emplace(R.sm, P.size()).first;
-        P.emplace_back();
-        total.push_back(0);
-        fam_sm.push_back(R.sm);
+    const std::pair<int, const void *> key =
+        R.sm ? std::make_pair(300, (const void *)R.sm)
+             : std::make_pair(R.dense_code, (const void *)nullptr);
+    auto it = fam_of.find(key);
+    if (it == fam_of.end()) {
+      it = fam_of.emplace(key, P.size()).first;
+      P.emplace_back();
+      total.push_back(0);
+      Kv kv;
+      if (R.sm) {
+        kv_decode(300 + R.info.n, kv);
+        kv.sm = R.sm;
+      } else if (R.dense_code) {
+        kv_decode(R.dense_code, kv);
       }
-      f = it->second;
+      fam_kv.push_back(kv);  // group family: chosen from its systems below
     }
+    const size_t f = it->second;
     // chunk outputs go to the request's arena region; slots are HP_MAX_N wide
     pack_append(P[f], &R.sys, R.info, R.gamma, chunk[i], R.region_off, R.region_off * HP_MAX_N,
                 nullptr);
@@ -1406,11 +1438,8 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
   for (size_t f = 0, used = 0; f < P.size() && rc == HP_OK; ++f) {
     if (P[f].sys.empty()) continue;
     const int q = (int)(used++ % kFamilyStreams);
-    Kv kv = kv_pick(P[f], ctx);  // P[1]: the dense kernel; P[0]: group kernels
-    if (fam_sm[f]) {
-      kv_decode(300 + P[f].nl, kv);
-      kv.sm = fam_sm[f];
-    }
+    Kv kv = fam_kv[f];
+    if (!kv.spec && !kv.dense) kv_decode(nmax_for(P[f].nl), kv);  // group kernels
     rc = dev[f].upload(P[f], S->fam_stream[q]);
     if (rc == HP_OK)
       rc = launch_persistent(ctx, dev[f], P[f], kv, tol, total[f], S->a_ends.as<hp_c64>(),
@@ -1534,12 +1563,12 @@ int hp_server_submit(hp_server *S, const hp_system *f, hp_c64 gamma, const hp_to
     const Kv kv = kv_pick(one, S->ctx);
     if (kv.nmax < n) return fail(HP_E_UNSUPPORTED_N, "no kernel variant for n");
     if ((rc = check_lds(S->ctx, kv_lds(kv, one)))) return rc;
-    R->dense = kv.dense;
+    R->dense_code = kv.dense ? kv.code : 0;
     // systems a specialised kernel serves run on it (compiled here the
     // first time their support is seen, then shared by every request of
     // that support)
     const DevSys &d = one.sys[0];
-    if (!R->dense && hp::spec_eligible(n, one.terms.data(), d.n_terms)) {
+    if (!R->dense_code && hp::spec_eligible(n, one.terms.data(), d.n_terms)) {
       std::string log;
       HIP_TRY(hipSetDevice(S->ctx->device));
       rc = hp::spec_get(S->ctx->device, hp::spec_source(n, d.deg, one.terms.data(), d.n_terms),

@@ -68,7 +68,8 @@ struct alignas(16) DevSys {
 // fixed order constant; x_a (a < n); x_a x_b (a <= b); x_a x_b x_c
 // (a <= b <= c), each block present up to the equation's degree, loops with
 // a outermost (missing monomials hold zero).
-constexpr int kDenseMaxN = 10;
+constexpr int kDenseMaxN = 10;      // k_dense: any n up to this in one launch
+constexpr int kDenseWideMaxN = 12;  // k_dense11, k_dense12: one exact n per launch
 constexpr int kDenseMaxDeg = 3;
 
 struct DevTol {
@@ -169,7 +170,8 @@ inline size_t lanes_lds_bytes(int n, int pw, int emax) {
 
 }  // namespace hp
 
-// Kernel launchers (tracker.hip, lanes.hip, dense.hip).  Return a hipError_t
+// Kernel launchers (tracker.hip, lanes.hip, dense.hip, dense11.hip,
+// dense12.hip).  Return a hipError_t
 // value.
 extern "C++" {
 // general: the systems use a general start system or explicit start points
@@ -185,4 +187,8 @@ int hp_launch_lanes_plain(int n, int pw, const hp::KArgs &a, int groups, size_t 
 int hp_lanes_per_cu(int n, int pw, size_t lds, int *out);
 int hp_launch_dense(const hp::KArgs &a, int groups, void *stream);
 int hp_dense_per_cu(int *out);
+int hp_launch_dense11(const hp::KArgs &a, int groups, void *stream);
+int hp_dense11_per_cu(int *out);
+int hp_launch_dense12(const hp::KArgs &a, int groups, void *stream);
+int hp_dense12_per_cu(int *out);
 }

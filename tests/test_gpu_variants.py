@@ -18,7 +18,7 @@ NTHREADS = min(16, os.cpu_count() or 1)
 GROUP = [4, 8, 10, 12]
 LANES = [100 + n for n in range(1, 9)] + [207, 208]
 SPEC = [300 + n for n in range(1, 11)]
-DENSE = [400]
+DENSE = [400, 411, 412]
 
 
 def log(*a):
@@ -42,6 +42,7 @@ CASES = {
     "dense8_d2": lambda: (W.dense_system(8, [2] * 8, np.random.default_rng(34)), np.exp(0.3j)),
     # a linear, a quadratic and a cubic equation (every block of the dense table)
     "dense3_d123": lambda: (W.dense_system(3, [1, 2, 3], np.random.default_rng(35)), np.exp(1.1j)),
+    "dense11_d2": lambda: (W.dense_system(11, [2] * 11, np.random.default_rng(36)), np.exp(0.9j)),
 }
 _oracle_cache = {}
 
@@ -73,8 +74,8 @@ def run_variant(ctx, s, g, code, mode):
 def test_variant_matches_oracle(ctx, name, code):
     s, g = CASES[name]()
     if code in DENSE:
-        if s.n > 10 or max(s.degrees()) > 3:
-            pytest.skip("the dense kernel takes n <= 10, total degree <= 3")
+        if (s.n > 10 if code == 400 else s.n != code - 400) or max(s.degrees()) > 3:
+            pytest.skip("dense kernel 400: n <= 10; 411, 412: n = 11, 12; total degree <= 3")
     elif (code >= 100 and code % 100 != s.n) or code % 100 < s.n:
         pytest.skip("variant not compiled for this n")
     log(f"case {name} n={s.n} paths={s.bezout()} variant={code}")
@@ -103,7 +104,7 @@ def test_unknown_variant_rejected(ctx):
     import paper_1804_03807_amd as hp
     s, g = CASES["cyclic6"]()
     plan = ctx.plan(s, g)
-    for bad in (5, 104, 108, 207, 300, 305, 309, 311, 400, -1):
+    for bad in (5, 104, 108, 207, 300, 305, 309, 311, 400, 410, 411, 413, -1):
         with pytest.raises(hp.HomotopyError):
             plan.set_variant(bad)
     plan.close()
@@ -155,3 +156,28 @@ def test_plan_default_is_specialised(ctx, name):
     assert t["variant"] == 300 + s.n
     assert t["paths_per_wave"] == 64
     plan.close()
+
+
+def test_dense12_sampled(ctx):
+    """The n = 12 dense kernel (412, the default for such a system) on a
+    serving-size system of mixed degrees: a stride sample against the
+    oracle."""
+    import torch
+    import paper_1804_03807_amd as hp
+    rng = np.random.default_rng(37)
+    s = W.dense_system(12, rng.integers(2, 4, size=12), rng)
+    g = np.exp(0.4j)
+    P = s.bezout()
+    plan = ctx.plan(s, g)
+    e, st, sts = plan.outputs(P)
+    plan.track_device(e, st, sts)
+    torch.cuda.synchronize()
+    assert ctx.last_timing()["variant"] == 412
+    e, st, sts = hp.Plan.endpoints_to_numpy(e), st.cpu().numpy(), hp.Plan.stats_to_numpy(sts)
+    plan.close()
+    sample = W.stride_sample(P, 160)
+    log(f"dense12 paths={P} sample={len(sample)}")
+    ref = oracle.track_paths(s, g, path_ids=sample, n_threads=NTHREADS)
+    hard, flips = compare_paths(e[sample], st[sample], sts[sample], *ref)
+    assert len(hard) == 0, f"paths {sample[hard[:8]]} differ from the oracle"
+    assert (sts["residual"][st == 0] <= 1e-10).all()
