@@ -180,10 +180,15 @@ void hp_plan_destroy(hp_plan *plan);
  *                          LDS, for systems whose power table is large);
  *   300 + n (n = 1..10)    the kernel specialised to the plan's system (one
  *                          path per lane, [J | rhs] in registers, compiled at
- *                          run time; total-degree start system only).
+ *                          run time; total-degree start system only);
+ *   400, 411, 412          dense kernels for equations of total degree <= 3
+ *                          (400: any n <= 10; 411, 412: n = 11, 12), one path
+ *                          per lane, batched mode only (a plain call of a
+ *                          plan on a dense kernel runs a group kernel).
  * The variant must fit the system's n and its LDS must fit the device; 0
- * selects the default (the specialised kernel where it applies, else the
- * narrowest group kernel).  HP_E_INVALID_ARG for other values,
+ * selects the default (the specialised kernel where it applies, else a
+ * dense kernel for a dense system of total degree <= 3, else the narrowest
+ * group kernel).  HP_E_INVALID_ARG for other values,
  * HP_E_UNSUPPORTED_N if the LDS does not fit.  The autotuner of
  * hp_plan_create times every candidate on a sample of the plan's paths and
  * caches the choice per system shape (file named by $HP_TUNE_CACHE). */
