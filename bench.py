@@ -37,12 +37,12 @@ TRAFFIC_PROFILE = {
         "spec_track.hpp": "6508c4afd886b2feb9f3ffdadc085ad985944583a96351c047ac7d53d614c871",
         "lane_track.hpp": "799f28d0cf38588c4c3355cb03561a850a4df11bda9a4af936ecaeb790c008cf",
         "hp_device.hpp": "f785014ca74114e45d5b32364f08af0b41660996c35cbf08085ef6fbc53b0a3e",
-        "hp_internal.hpp": "cd88d14afd5e4f63601afe4c22505eac7f4dc8c3359e73ffac36511be2f626e2",
+        "hp_internal.hpp": "fcdd9f4c568f1d13ef2e0d021aee18cbcf41be765e41d7bf5a60016e6757857e",
         "hp_jit.cpp": "4b489fc1add9e7d03fd1830751f73ac383abb2a75cece9fb32d4fb79ffe9a8f0",
         "reg_lu.hpp": "ad427109a098bb4ecee85321685be37648315ec356c45e1478d2bed7824eda6e",
     },
-    "fetch_kib": 562.5, "fetch_scale": 262144 / 131092.25,
-    "write_kib": 6812.71875, "write_scale": 262144 / 262144,
+    "fetch_kib": 562.5, "fetch_scale": 262144 / 131092.1875,
+    "write_kib": 6812.21875, "write_scale": 262144 / 262144,
 }
 
 WORKLOADS = {
