@@ -34,15 +34,15 @@ TRAFFIC_PROFILE = {
     "workload": "cyclic8",
     "variant": 308,
     "sources_sha256": {
-        "spec_track.hpp": "6508c4afd886b2feb9f3ffdadc085ad985944583a96351c047ac7d53d614c871",
-        "lane_track.hpp": "799f28d0cf38588c4c3355cb03561a850a4df11bda9a4af936ecaeb790c008cf",
+        "spec_track.hpp": "fca314d9a2a7c3db422491467a19d7033d9804ea05ef2a2cb232475df5001b3c",
+        "lane_track.hpp": "d88e396d1469da3c3c901e2aaa6170c2cb2c893162686c6fafd3989921cf3ff4",
         "hp_device.hpp": "f785014ca74114e45d5b32364f08af0b41660996c35cbf08085ef6fbc53b0a3e",
         "hp_internal.hpp": "fcdd9f4c568f1d13ef2e0d021aee18cbcf41be765e41d7bf5a60016e6757857e",
-        "hp_jit.cpp": "4b489fc1add9e7d03fd1830751f73ac383abb2a75cece9fb32d4fb79ffe9a8f0",
-        "reg_lu.hpp": "ad427109a098bb4ecee85321685be37648315ec356c45e1478d2bed7824eda6e",
+        "hp_jit.cpp": "161eb0b1682f3e9c2e6298568b857aa590840c85fd0c98555fde715ce4f31b59",
+        "reg_lu.hpp": "2ee03185cebaccbe5e9e23ec56790db7fa54010becacce5ac9f79ec2dda3b585",
     },
-    "fetch_kib": 562.5, "fetch_scale": 262144 / 131092.1875,
-    "write_kib": 6812.21875, "write_scale": 262144 / 262144,
+    "fetch_kib": 571.0, "fetch_scale": 262144 / 131093.125,
+    "write_kib": 6812.9375, "write_scale": 262144 / 262144,
 }
 
 WORKLOADS = {

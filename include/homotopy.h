@@ -126,7 +126,9 @@ typedef struct hp_context hp_context;
 typedef struct hp_plan hp_plan;
 typedef struct hp_server hp_server;
 
-/* Context on HIP device `device`.  Creates a stream of default priority. */
+/* Context on HIP device `device`.  Creates a stream of default priority.
+ * A call that takes a context, a plan or a server may make the context's
+ * device the current HIP device of the calling thread, and leaves it so. */
 int hp_context_create(int device, hp_context **out);
 /* Every plan and server made from ctx must be destroyed first. */
 void hp_context_destroy(hp_context *ctx);
@@ -164,8 +166,10 @@ int hp_track_paths(hp_context *ctx, const hp_system *f, const hp_system *g, cons
  * and compiled (hiprtc) at plan creation, which takes seconds (n = 8: 5-7 s,
  * n = 10: 13-17 s on one host core) the first time a support is seen; plans
  * for systems of the same support share the compiled module, and
- * $HP_JIT_CACHE (a directory) keeps code objects across processes.  Errors of that compilation are
- * HP_E_DEVICE with the compiler log in hp_last_error. */
+ * $HP_JIT_CACHE (a directory) keeps code objects across processes (keyed by
+ * the source, the compiler version and options and the library's kernel
+ * headers, so a rebuilt library does not load stale code).  Errors of that
+ * compilation are HP_E_DEVICE with the compiler log in hp_last_error. */
 int hp_plan_create(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
                    int32_t tune, hp_plan **out);
 void hp_plan_destroy(hp_plan *plan);

@@ -143,11 +143,11 @@ struct Dense : LaneTrack<Dense<N>, N, RkLds<N>> {
 
   // right-hand side from LDS; the current point waits in LDS during the
   // elimination
-  __device__ __forceinline__ void solve(cd dx[N], bool &sing) {
+  __device__ __forceinline__ void solve(cd dx[N], bool &sing, bool live) {
 #pragma unroll
     for (int i = 0; i < N; ++i) b[i] = this->rk.spare(i);
     this->rk.park(xc);
-    reg_lu_solve<N>(J, b, dx, sing);
+    reg_lu_solve<N, true>(J, b, dx, sing, live);
     this->rk.unpark(xc);
   }
 

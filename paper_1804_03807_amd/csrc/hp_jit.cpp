@@ -205,13 +205,34 @@ const char *const kRtcOpts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-
                                 "-target-feature", "-Xclang", "-packed-fp32-ops"};
 
 // What a cached code object depends on besides its source: the compiler
-// version and options.
+// version and options, and the text of the headers the source includes (a
+// 64-bit FNV-1a digest of their names and texts).
 std::string build_tag() {
-  int major = 0, minor = 0;
-  hiprtcVersion(&major, &minor);
-  std::string t = "hiprtc " + std::to_string(major) + "." + std::to_string(minor);
-  for (const char *o : kRtcOpts) t += std::string(" ") + o;
-  return t + "\n";
+  static const std::string tag = [] {
+    int major = 0, minor = 0;
+    hiprtcVersion(&major, &minor);
+    std::string t = "hiprtc " + std::to_string(major) + "." + std::to_string(minor);
+    for (const char *o : kRtcOpts) t += std::string(" ") + o;
+    uint64_t h = 0xcbf29ce484222325ull;
+    auto mix = [&h](const char *s) {
+      // each string ends with a 0xff byte, which no header text holds
+      for (;; ++s) {
+        h ^= *s ? (unsigned char)*s : 0xffu;
+        h *= 0x100000001b3ull;
+        if (!*s) break;
+      }
+    };
+    for (size_t i = 0; i < sizeof(kJitHeaderNames) / sizeof(kJitHeaderNames[0]); ++i) {
+      mix(kJitHeaderNames[i]);
+      mix(kJitHeaderTexts[i]);
+    }
+    mix(kRtcStdint);
+    mix(kRtcStddef);
+    char d[40];
+    std::snprintf(d, sizeof(d), " headers %016llx", (unsigned long long)h);
+    return t + d + "\n";
+  }();
+  return tag;
 }
 
 // File of the on-disk code cache ($HP_JIT_CACHE, when set): named by a hash

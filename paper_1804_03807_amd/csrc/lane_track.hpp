@@ -3,7 +3,9 @@
 // control and end game, the output record, and the persistent and plain
 // kernel bodies.  A tracker D derives from LaneTrack<D, N> and supplies
 //   void eval(int emode, double te);    [J_x(xc, te) | rhs], see EvalMode
-//   void solve(cd dx[N], bool &sing);   J dx = rhs
+//   void solve(cd dx[N], bool &sing, bool live);
+//                                       J dx = rhs; lanes with live false
+//                                       discard dx and sing
 //   double residual() const;            max_i |rhs_i| after eval(EV_F, 1)
 // Compiled by hipcc into the library and by hiprtc into the kernels that
 // are specialised to one system at run time.
@@ -243,7 +245,9 @@ struct LaneTrack {
       }
       bool sing;
       cd dsl[N];
-      self().solve(dsl, sing);
+      // the RK4 stages serve the tracking lanes, a Newton iteration the
+      // lanes still iterating; the other lanes run along and discard dx
+      self().solve(dsl, sing, phase < 4 ? trk : iter);
       if (phase < 4) {
         // ---- RK4 stage ----
         ok = ok && !sing;

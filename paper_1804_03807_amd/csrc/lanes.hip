@@ -225,7 +225,7 @@ struct Lanes : LaneTrack<Lanes<N, PW>, N> {
   // pivot column is updated first and kept in registers (look-ahead), so the
   // pivot search never waits on LDS; the other columns are streamed: column
   // j + 1 is read before column j is written back.
-  __device__ __forceinline__ void solve(cd dx[NMAX], bool &sing) {
+  __device__ __forceinline__ void solve(cd dx[NMAX], bool &sing, bool /*live*/) {
     lds_char *row[NMAX];
 #pragma unroll
     for (int i = 0; i < NMAX; ++i) row[i] = base + i * kCols * kEntry;

@@ -11,9 +11,16 @@ namespace hp {
 // lowest row) on the registers, then back substitution into dx.  A row
 // exchange is a select per entry: the pivot row is data dependent and
 // registers cannot be indexed by a lane-varying value.  sing: an exactly
-// zero (or NaN) pivot.
-template <int N>
-__device__ __forceinline__ void reg_lu_solve(cd (&J)[N][N], cd (&b)[N], cd dx[N], bool &sing) {
+// zero (or NaN) pivot.  Lanes with live false discard dx and sing (lanes
+// whose paths have ended, or whose corrector has stopped, still run the
+// solve in step with the others).  With SkipRows the exchange of a row is
+// skipped for the whole wavefront when no live lane takes its pivot there.
+// In the dense kernels the branches this adds also cut the register spills;
+// in the specialised kernel of n = 10, which spills already, they cost more
+// than they save (and n = 9, which spills too, keeps the exchanges as well).
+template <int N, bool SkipRows>
+__device__ __forceinline__ void reg_lu_solve(cd (&J)[N][N], cd (&b)[N], cd dx[N], bool &sing,
+                                             bool live) {
   // compile-time loops throughout: with bounds that depend on the column k,
   // unrolled runtime loops are not always unrolled fully, and J would then
   // be indexed at run time and live in scratch memory
@@ -33,6 +40,7 @@ __device__ __forceinline__ void reg_lu_solve(cd (&J)[N][N], cd (&b)[N], cd dx[N]
     sfor<k + 1, N>([&](auto ii) {
       constexpr int i = decltype(ii)::value;
       const bool sw = (i == p);
+      if (SkipRows && ballot(live && sw) == 0) return;
       sfor<k, N>([&](auto ij) {
         constexpr int j = decltype(ij)::value;
         const cd u = J[k][j], v = J[i][j];

@@ -63,11 +63,11 @@ struct Spec : LaneTrack<Spec<S>, S::N, RkLds<S::N>> {
 
   // right-hand side from LDS; the current point waits in LDS during the
   // elimination
-  __device__ __forceinline__ void solve(cd dx[N], bool &sing) {
+  __device__ __forceinline__ void solve(cd dx[N], bool &sing, bool live) {
 #pragma unroll
     for (int i = 0; i < N; ++i) b[i] = this->rk.spare(i);
     this->rk.park(xc);
-    reg_lu_solve<N>(J, b, dx, sing);
+    reg_lu_solve<N, (N <= 8)>(J, b, dx, sing, live);
     this->rk.unpark(xc);
   }
 
