@@ -465,13 +465,10 @@ std::vector<int> kv_candidates(int n, int emax, size_t max_lds) {
   return out;
 }
 
-// Default: the group kernel of the smallest n_max >= n (the faster family
-// on the measured workloads); the lane kernels are autotuner candidates.
-int kv_default(int n, int emax, size_t max_lds) {
-  (void)emax;
-  (void)max_lds;
-  return nmax_for(n);
-}
+// Default among the compiled-ahead kernels for sparse systems: the group
+// kernel of the smallest n_max >= n (faster than the lane kernels on the
+// measured workloads, which stay autotuner candidates).
+int kv_default(int n) { return nmax_for(n); }
 
 std::mutex g_tune_mu;
 std::map<std::string, int> g_tune_mem;
@@ -656,12 +653,13 @@ int kv_occupancy(hp_context *ctx, const Kv &k, const Packed &P, size_t *lds, int
   return HP_OK;
 }
 
-// Default variant for a multi-system launch: a lane kernel needs one n for
-// all systems.
-Kv kv_pick(const Packed &P, const hp_context *ctx) {
+// Default variant of a launch over packed systems (one-shot calls, batches,
+// serving requests): the dense kernel when the systems suit it, else the
+// group kernel for their widest n.
+Kv kv_pick(const Packed &P) {
   Kv k;
   if (const int dc = dense_preferred(P)) kv_decode(dc, k);
-  else kv_decode(P.nmin == P.nl ? kv_default(P.nl, P.emax, ctx->max_lds) : nmax_for(P.nl), k);
+  else kv_decode(kv_default(P.nl), k);
   return k;
 }
 
@@ -743,7 +741,7 @@ int plan_variant(hp_plan *plan, int code) {
     const int dc = dense_preferred(plan->P);
     code = (plan->spec_default && plan_spec_eligible(plan)) ? 300 + plan->info.n
            : dc ? dc
-                : kv_default(plan->info.n, plan->info.emax, plan->ctx->max_lds);
+                : kv_default(plan->info.n);
   }
   Kv k;
   if (!kv_decode(code, k) || k.nmax < plan->info.n ||
@@ -1095,7 +1093,7 @@ int hp_track_batch(hp_context *ctx, const hp_system *fs, int32_t n_systems, cons
     check_system(&fs[s], info);
     pack_append(P, &fs[s], info, gammas[s], info.paths, po[s], xo[s], nullptr);
   }
-  const Kv kv = kv_pick(P, ctx);
+  const Kv kv = kv_pick(P);
   DevTables dev;
   if ((rc = dev.upload(P, ctx->stream))) return rc;
   DevBuf e, st, sts;
@@ -1560,7 +1558,7 @@ int hp_server_submit(hp_server *S, const hp_system *f, hp_c64 gamma, const hp_to
     // takes the widest variant of its requests, which fits as well
     Packed one;
     pack_append(one, f, R->info, gamma, 1, 0, 0, nullptr);
-    const Kv kv = kv_pick(one, S->ctx);
+    const Kv kv = kv_pick(one);
     if (kv.nmax < n) return fail(HP_E_UNSUPPORTED_N, "no kernel variant for n");
     if ((rc = check_lds(S->ctx, kv_lds(kv, one)))) return rc;
     R->dense_code = kv.dense ? kv.code : 0;
