@@ -34,12 +34,12 @@ TRAFFIC_PROFILE = {
     "workload": "cyclic8",
     "variant": 308,
     "sources_sha256": {
-        "spec_track.hpp": "fca314d9a2a7c3db422491467a19d7033d9804ea05ef2a2cb232475df5001b3c",
+        "spec_track.hpp": "bb636574221bdf00805a21bbf4a783b4222c9c83e6ae6b0d1ef22211410816f1",
         "lane_track.hpp": "d88e396d1469da3c3c901e2aaa6170c2cb2c893162686c6fafd3989921cf3ff4",
         "hp_device.hpp": "f785014ca74114e45d5b32364f08af0b41660996c35cbf08085ef6fbc53b0a3e",
         "hp_internal.hpp": "fcdd9f4c568f1d13ef2e0d021aee18cbcf41be765e41d7bf5a60016e6757857e",
         "hp_jit.cpp": "161eb0b1682f3e9c2e6298568b857aa590840c85fd0c98555fde715ce4f31b59",
-        "reg_lu.hpp": "2ee03185cebaccbe5e9e23ec56790db7fa54010becacce5ac9f79ec2dda3b585",
+        "reg_lu.hpp": "38cca378445e739dacd720c25919d7e5082e5df9c964ec3f4c1a1888602fa360",
     },
     "fetch_kib": 571.0, "fetch_scale": 262144 / 131093.125,
     "write_kib": 6812.9375, "write_scale": 262144 / 262144,

@@ -147,7 +147,7 @@ struct Dense : LaneTrack<Dense<N>, N, RkLds<N>> {
 #pragma unroll
     for (int i = 0; i < N; ++i) b[i] = this->rk.spare(i);
     this->rk.park(xc);
-    reg_lu_solve<N, true>(J, b, dx, sing, live);
+    reg_lu_solve<N, true, true>(J, b, dx, sing, live);
     this->rk.unpark(xc);
   }
 

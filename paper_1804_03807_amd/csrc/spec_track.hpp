@@ -67,7 +67,7 @@ struct Spec : LaneTrack<Spec<S>, S::N, RkLds<S::N>> {
 #pragma unroll
     for (int i = 0; i < N; ++i) b[i] = this->rk.spare(i);
     this->rk.park(xc);
-    reg_lu_solve<N, (N <= 8)>(J, b, dx, sing, live);
+    reg_lu_solve<N, (N <= 8), false>(J, b, dx, sing, live);
     this->rk.unpark(xc);
   }
 
