@@ -39,7 +39,7 @@ TRAFFIC_PROFILE = {
         "hp_device.hpp": "f785014ca74114e45d5b32364f08af0b41660996c35cbf08085ef6fbc53b0a3e",
         "hp_internal.hpp": "fcdd9f4c568f1d13ef2e0d021aee18cbcf41be765e41d7bf5a60016e6757857e",
         "hp_jit.cpp": "161eb0b1682f3e9c2e6298568b857aa590840c85fd0c98555fde715ce4f31b59",
-        "reg_lu.hpp": "38cca378445e739dacd720c25919d7e5082e5df9c964ec3f4c1a1888602fa360",
+        "reg_lu.hpp": "488a287cfdfca4d8c1b616ad7aa2ae6bd41dfae4f8f485f55d55bd2819711eb2",
     },
     "fetch_kib": 571.0, "fetch_scale": 262144 / 131093.125,
     "write_kib": 6812.9375, "write_scale": 262144 / 262144,

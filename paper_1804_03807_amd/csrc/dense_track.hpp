@@ -147,7 +147,9 @@ struct Dense : LaneTrack<Dense<N>, N, RkLds<N>> {
 #pragma unroll
     for (int i = 0; i < N; ++i) b[i] = this->rk.spare(i);
     this->rk.park(xc);
-    reg_lu_solve<N, true, true>(J, b, dx, sing, live);
+    // row blocks pay in the kernel for n <= 10; the kernels of n = 11, 12
+    // (mostly spills either way) run faster without them
+    reg_lu_solve<N, true, (N <= kDenseMaxN)>(J, b, dx, sing, live);
     this->rk.unpark(xc);
   }
 

@@ -30,9 +30,11 @@ __device__ __forceinline__ bool opaque_true() {
 // With RowBlocks the elimination of each row sits behind a wave-uniform
 // branch whose condition the compiler cannot evaluate (always true): every
 // row becomes a block of its own, which keeps the scheduler from
-// interleaving rows and lowers the register pressure in the dense kernels
-// (fewer spills, 13 % less time on a batch of dense systems); the
-// specialised kernels run slower with it (n = 8) or spill more (n = 9, 10).
+// interleaving rows and lowers the register pressure in the dense kernel
+// for n <= 10 (fewer spills, 13 % less time on a batch of dense systems);
+// the specialised kernels run slower with it (n = 8) or spill more
+// (n = 9, 10), and so do the dense kernels of n = 11, 12 on the serving
+// sample, where they carry most of the paths.
 template <int N, bool SkipRows, bool RowBlocks>
 __device__ __forceinline__ void reg_lu_solve(cd (&J)[N][N], cd (&b)[N], cd dx[N], bool &sing,
                                              bool live) {
