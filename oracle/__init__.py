@@ -72,6 +72,11 @@ def lib():
                                           vp, vp, vp, i64, ctypes.POINTER(RefTolerances),
                                           vp, vp, vp, i32]
             L.ref_track_paths.restype = ctypes.c_int
+            L.ref_eval_system_dd.argtypes = [ctypes.POINTER(RefSystem), vp, vp, vp, vp]
+            L.ref_residual_dd.argtypes = [ctypes.POINTER(RefSystem), vp]
+            L.ref_residual_dd.restype = ctypes.c_double
+            L.ref_refine_dd.argtypes = [ctypes.POINTER(RefSystem), vp, ctypes.c_int, vp]
+            L.ref_dd_ops.argtypes = [ctypes.c_double] * 4 + [vp, vp]
             L.ref_find_duplicates.argtypes = [ctypes.c_int, i64, vp, vp, ctypes.c_double, vp, i64]
             L.ref_find_duplicates.restype = i64
             _lib = L
@@ -109,6 +114,41 @@ def eval_system(s, x):
     jac = np.zeros((s.n, s.n), np.complex128)
     lib().ref_eval_system(ctypes.byref(S.st), _ptr(x), _ptr(fx), _ptr(jac))
     return fx, jac
+
+
+def eval_system_dd(s, x_hi, x_lo=None):
+    """f at x_hi + x_lo in double-double: returns (f_hi, f_lo) complex[n]."""
+    S = _Sys(s)
+    xh = np.ascontiguousarray(x_hi, dtype=np.complex128)
+    xl = np.ascontiguousarray(x_lo, dtype=np.complex128) if x_lo is not None else None
+    fh = np.zeros(s.n, np.complex128)
+    fl = np.zeros(s.n, np.complex128)
+    lib().ref_eval_system_dd(ctypes.byref(S.st), _ptr(xh), _ptr(xl), _ptr(fh), _ptr(fl))
+    return fh, fl
+
+
+def residual_dd(s, x):
+    """The end game's residual ||f(x)||_inf (f in double-double) at x."""
+    S = _Sys(s)
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    return float(lib().ref_residual_dd(ctypes.byref(S.st), _ptr(x)))
+
+
+def refine_dd(s, x, iters=2):
+    """The end game's double-double Newton refinement of x; nearest double."""
+    S = _Sys(s)
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    out = np.zeros_like(x)
+    lib().ref_refine_dd(ctypes.byref(S.st), _ptr(x), int(iters), _ptr(out))
+    return out
+
+
+def dd_ops(a_hi, a_lo, b_hi, b_lo):
+    """Double-double (sum, product) of a and b, each as (hi, lo)."""
+    s = np.zeros(2)
+    p = np.zeros(2)
+    lib().ref_dd_ops(float(a_hi), float(a_lo), float(b_hi), float(b_lo), _ptr(s), _ptr(p))
+    return (float(s[0]), float(s[1])), (float(p[0]), float(p[1]))
 
 
 def lu_solve(A, b):

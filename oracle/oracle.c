@@ -163,6 +163,166 @@ int ref_lu_solve(int n, const double *A, const double *b, double *y) {
 }
 
 /* ---------------------------------------------------------------------- */
+/* Double-double arithmetic for the end game: a value is hi + lo with      */
+/* |lo| <= ulp(hi)/2.  Error-free transformations: Knuth's two-sum and the  */
+/* exact product from a fused multiply-add (C99 fma rounds once).          */
+/* ---------------------------------------------------------------------- */
+
+typedef struct { double hi, lo; } dd;
+typedef struct { dd re, im; } cdd;
+
+/* s + e == a + b exactly, s = fl(a + b) (Knuth, TAOCP vol. 2, 4.2.2) */
+static dd two_sum(double a, double b) {
+  double s = a + b;
+  double bb = s - a;
+  double e = (a - (s - bb)) + (b - bb);
+  dd r = {s, e};
+  return r;
+}
+
+/* s + e == a + b exactly when |a| >= |b| or a == 0 (Dekker) */
+static dd fast_two_sum(double a, double b) {
+  double s = a + b;
+  dd r = {s, b - (s - a)};
+  return r;
+}
+
+/* p + e == a * b exactly */
+static dd two_prod(double a, double b) {
+  double p = a * b;
+  dd r = {p, fma(a, b, -p)};
+  return r;
+}
+
+static dd dd_from(double a) { dd r = {a, 0.0}; return r; }
+
+/* (a.hi + a.lo) + (b.hi + b.lo): both high parts and both low parts are
+ * summed error-free, then renormalised */
+static dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi);
+  dd t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = fast_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+
+static dd dd_neg(dd a) { dd r = {-a.hi, -a.lo}; return r; }
+
+/* (a.hi + a.lo)(b.hi + b.lo) without the lo*lo term */
+static dd dd_mul(dd a, dd b) {
+  dd p = two_prod(a.hi, b.hi);
+  p.lo += a.hi * b.lo + a.lo * b.hi;
+  return fast_two_sum(p.hi, p.lo);
+}
+
+static cdd cdd_from(cplx z) { cdd r = {dd_from(creal(z)), dd_from(cimag(z))}; return r; }
+
+static cdd cdd_add(cdd a, cdd b) {
+  cdd r = {dd_add(a.re, b.re), dd_add(a.im, b.im)};
+  return r;
+}
+
+static cdd cdd_mul(cdd a, cdd b) {
+  cdd r = {dd_add(dd_mul(a.re, b.re), dd_neg(dd_mul(a.im, b.im))),
+           dd_add(dd_mul(a.re, b.im), dd_mul(a.im, b.re))};
+  return r;
+}
+
+/* the nearest complex double of z */
+static cplx cdd_round(cdd z) { return CMPLX(z.re.hi + z.re.lo, z.im.hi + z.im.lo); }
+
+/* f(x) in double-double at the double-double point x: every term by
+ * repeated multiplication, summed per equation */
+static void eval_f_dd(const ref_system *s, const cdd *x, cdd *fx) {
+  const int n = s->n;
+  for (int i = 0; i < n; ++i) {
+    cdd acc = cdd_from(0.0);
+    for (int t = s->eq_ptr[i]; t < s->eq_ptr[i + 1]; ++t) {
+      const uint8_t *a = s->exps + (size_t)t * n;
+      cdd v = cdd_from(load(s->coeff, t));
+      for (int l = 0; l < n; ++l)
+        for (int e = 0; e < a[l]; ++e) v = cdd_mul(v, x[l]);
+      acc = cdd_add(acc, v);
+    }
+    fx[i] = acc;
+  }
+}
+
+/* ||f(x)||_inf at the double point x, with f evaluated in double-double
+ * and each |f_i| taken of its nearest complex double */
+static double residual_dd(const ref_system *s, const cplx *x) {
+  const int n = s->n;
+  cdd xv[MAXN], fv[MAXN];
+  cplx fr[MAXN];
+  for (int i = 0; i < n; ++i) xv[i] = cdd_from(x[i]);
+  eval_f_dd(s, xv, fv);
+  for (int i = 0; i < n; ++i) fr[i] = cdd_round(fv[i]);
+  return norm_inf(n, fr);
+}
+
+/* Newton refinement at t = 1 with the residual in double-double: x is
+ * carried as a double-double point, each iteration solves J_f(x) d = f(x)
+ * in double (J_f at the double part of x, f rounded to double) and
+ * subtracts d in double-double.  Stops early on a zero pivot or a
+ * non-finite update (x is kept).  On return x holds the nearest double of
+ * the refined point. */
+static void refine_dd(const ref_system *s, cplx *x, int iters) {
+  const int n = s->n;
+  cdd xv[MAXN], fv[MAXN];
+  for (int i = 0; i < n; ++i) xv[i] = cdd_from(x[i]);
+  for (int it = 0; it < iters; ++it) {
+    cplx xh[MAXN], J[MAXN * MAXN], r[MAXN], d[MAXN];
+    for (int i = 0; i < n; ++i) xh[i] = cdd_round(xv[i]);
+    eval_f_dd(s, xv, fv);
+    for (int i = 0; i < n; ++i) r[i] = cdd_round(fv[i]);
+    eval_f(s, xh, NULL, J);
+    if (lu_solve(n, J, r, d) != 0 || !all_finite(n, d)) break;
+    for (int i = 0; i < n; ++i) xv[i] = cdd_add(xv[i], cdd_from(-d[i]));
+  }
+  for (int i = 0; i < n; ++i) x[i] = cdd_round(xv[i]);
+}
+
+void ref_eval_system_dd(const ref_system *s, const double *x_hi, const double *x_lo,
+                        double *f_hi, double *f_lo) {
+  const int n = s->n;
+  cdd xv[MAXN], fv[MAXN];
+  for (int i = 0; i < n; ++i) {
+    xv[i].re = fast_two_sum(x_hi[2 * i], x_lo ? x_lo[2 * i] : 0.0);
+    xv[i].im = fast_two_sum(x_hi[2 * i + 1], x_lo ? x_lo[2 * i + 1] : 0.0);
+  }
+  eval_f_dd(s, xv, fv);
+  for (int i = 0; i < n; ++i) {
+    f_hi[2 * i] = fv[i].re.hi;
+    f_hi[2 * i + 1] = fv[i].im.hi;
+    if (f_lo) {
+      f_lo[2 * i] = fv[i].re.lo;
+      f_lo[2 * i + 1] = fv[i].im.lo;
+    }
+  }
+}
+
+double ref_residual_dd(const ref_system *s, const double *x) {
+  cplx xv[MAXN];
+  for (int i = 0; i < s->n; ++i) xv[i] = load(x, i);
+  return residual_dd(s, xv);
+}
+
+void ref_refine_dd(const ref_system *s, const double *x, int iters, double *x_out) {
+  cplx xv[MAXN];
+  for (int i = 0; i < s->n; ++i) xv[i] = load(x, i);
+  refine_dd(s, xv, iters);
+  for (int i = 0; i < s->n; ++i) store(x_out, i, xv[i]);
+}
+
+void ref_dd_ops(double a_hi, double a_lo, double b_hi, double b_lo, double *sum, double *prod) {
+  dd a = fast_two_sum(a_hi, a_lo), b = fast_two_sum(b_hi, b_lo);
+  dd s = dd_add(a, b), p = dd_mul(a, b);
+  sum[0] = s.hi; sum[1] = s.lo;
+  prod[0] = p.hi; prod[1] = p.lo;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Homotopy H(x,t) = gamma (1-t) g(x) + t f(x)                              */
 /* ---------------------------------------------------------------------- */
 
@@ -316,11 +476,22 @@ static void track_one(const homotopy *h, const cplx *x_start, const ref_toleranc
   }
 
   if (stat < 0) {
-    /* t = 1: Newton on f = H(., 1) without the contraction test */
+    /* t = 1: Newton on f = H(., 1) without the contraction test, then the
+     * double-double refinement to the nearest double of the root and the
+     * residual there, evaluated in double-double: two implementations that
+     * differ in rounding reach the same endpoint and the same decision */
     newton(h, x, 1.0, tol->max_newton_final, tol->tol_final, 0, st);
-    cplx fx[MAXN];
-    eval_f(h->f, x, fx, NULL);
-    double res = norm_inf(n, fx), nx = norm_inf(n, x);
+    double nx = norm_inf(n, x);
+    double res;
+    if (all_finite(n, x) && nx <= tol->div_radius) {
+      refine_dd(h->f, x, REF_REFINE_ITERS);
+      nx = norm_inf(n, x);
+      res = residual_dd(h->f, x);
+    } else {
+      cplx fx[MAXN];
+      eval_f(h->f, x, fx, NULL);
+      res = norm_inf(n, fx);
+    }
     st->residual = res;
     if (res <= tol->tol_residual && nx <= tol->div_radius) stat = REF_CONVERGED;
     else if (nx > tol->div_radius) stat = REF_DIVERGED;

@@ -14,7 +14,12 @@
  * jobs from a queue whose next-job pointer is guarded (Section 1).  It gives
  * no predictor, corrector or step control; the steps below are the reading
  * this project adopts (RK4 predictor on the Davidenko equation, Newton
- * corrector, halving/doubling step control, final Newton at t = 1).
+ * corrector, halving/doubling step control, final Newton at t = 1).  The end
+ * game refines the endpoint with Newton iterations whose residual is
+ * evaluated in double-double arithmetic, rounds it to the nearest double,
+ * and takes the residual test there, again in double-double: the endpoint
+ * and the decision then no longer depend on the order of the double
+ * precision arithmetic that led to them.
  *
  * Plain by design: every term and every partial derivative is evaluated by
  * repeated multiplication, the linear solver is textbook Gaussian
@@ -49,6 +54,10 @@ typedef struct {
   int32_t max_steps, max_newton, max_newton_final;
 } ref_tolerances;
 
+/* Newton iterations in double-double at t = 1 after the double-precision
+ * final Newton (see ref_refine_dd). */
+#define REF_REFINE_ITERS 2
+
 enum { REF_CONVERGED = 0, REF_DIVERGED = 1, REF_FAILED_MINSTEP = 2,
        REF_FAILED_MAXSTEPS = 3, REF_FAILED_NEWTON_T1 = 4 };
 
@@ -73,6 +82,26 @@ void ref_eval_system(const ref_system *s, const double *x, double *fx, double *j
  * column, ties to the lowest row).  A: [2n*n] row-major, b: [2n], y: [2n].
  * Returns 0, or -1 if a pivot is exactly zero. */
 int ref_lu_solve(int n, const double *A, const double *b, double *y);
+
+/* f(x) in double-double arithmetic at x = x_hi + x_lo (x_lo may be NULL):
+ * [2n] interleaved complex each; f = f_hi + f_lo (f_lo may be NULL). */
+void ref_eval_system_dd(const ref_system *s, const double *x_hi, const double *x_lo,
+                        double *f_hi, double *f_lo);
+
+/* ||f(x)||_inf at the double point x with f evaluated in double-double, each
+ * |f_i| the modulus of the nearest complex double of f_i: the residual of
+ * the end game. */
+double ref_residual_dd(const ref_system *s, const double *x);
+
+/* End-game refinement: `iters` Newton iterations on f from x carried in
+ * double-double (f in double-double, J_f and the solve in double), then the
+ * nearest double of the result to x_out.  A zero pivot or a non-finite
+ * update stops the iteration early. */
+void ref_refine_dd(const ref_system *s, const double *x, int iters, double *x_out);
+
+/* Double-double sum and product of a = a_hi + a_lo and b = b_hi + b_lo:
+ * sum[2], prod[2] (hi, lo); for pinning the arithmetic. */
+void ref_dd_ops(double a_hi, double a_lo, double b_hi, double b_lo, double *sum, double *prod);
 
 /* Start point of a total-degree path: path id p is read in mixed radix,
  * p = sum_i k_i prod_{j<i} d_j (k_1 fastest), x_i = exp(2 pi i k_i/d_i). */
