@@ -22,8 +22,13 @@
  * when ||dx||_inf <= tol_corr * max(1, ||x||_inf), failure when an iteration
  * does not halve the update), step halving on failure and doubling after
  * three successes (capped at h_max, last step clipped to t = 1), truncation
- * of paths with ||x||_inf > div_radius, and a final Newton at t = 1 with the
- * residual test ||f(x)||_inf <= tol_residual.
+ * of paths with ||x||_inf > div_radius, and a final Newton at t = 1.  The
+ * end game then refines the endpoint by Newton iterations with f evaluated
+ * in double-double arithmetic (the paper's means to accuracy: Section 1,
+ * Section 5.1), rounds it to the nearest double, and takes the residual test
+ * ||f(x)||_inf <= tol_residual there with f again in double-double, so that
+ * the endpoint and its classification do not depend on the order of the
+ * double-precision arithmetic that led to it.
  *
  * Start points.  Path p (0 <= p < prod d_i) starts at x_i = exp(2 pi i k_i / d_i)
  * where p = sum_i k_i prod_{j<i} d_j (k_1 varies fastest).  Endpoint arrays
@@ -109,7 +114,8 @@ typedef struct {
   int32_t solves;       /* linear solves                                      */
   int32_t pad;
   double t_final;       /* t where tracking stopped                           */
-  double residual;      /* ||f(x_end)||_inf                                   */
+  double residual;      /* ||f(x_end)||_inf (double-double f for paths that  */
+                        /* reached t = 1 with a finite endpoint)              */
 } hp_path_stats;
 
 typedef struct {
@@ -130,7 +136,11 @@ typedef struct hp_server hp_server;
  * A call that takes a context, a plan or a server may make the context's
  * device the current HIP device of the calling thread, and leaves it so. */
 int hp_context_create(int device, hp_context **out);
-/* Every plan and server made from ctx must be destroyed first. */
+/* Ends the caller's use of ctx.  Plans and servers made from ctx may be
+ * destroyed before or after it: the context's stream and events are
+ * released once ctx and all of them are destroyed, so no order of
+ * destruction leaves a plan or server with a freed context (they stay
+ * usable until destroyed). */
 void hp_context_destroy(hp_context *ctx);
 /* Message of the last failed call on this thread ("" if none). */
 const char *hp_last_error(void);

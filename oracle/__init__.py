@@ -75,6 +75,7 @@ def lib():
             L.ref_eval_system_dd.argtypes = [ctypes.POINTER(RefSystem), vp, vp, vp, vp]
             L.ref_residual_dd.argtypes = [ctypes.POINTER(RefSystem), vp]
             L.ref_residual_dd.restype = ctypes.c_double
+            L.ref_residuals_dd.argtypes = [ctypes.POINTER(RefSystem), i64, vp, vp]
             L.ref_refine_dd.argtypes = [ctypes.POINTER(RefSystem), vp, ctypes.c_int, vp]
             L.ref_dd_ops.argtypes = [ctypes.c_double] * 4 + [vp, vp]
             L.ref_find_duplicates.argtypes = [ctypes.c_int, i64, vp, vp, ctypes.c_double, vp, i64]
@@ -132,6 +133,15 @@ def residual_dd(s, x):
     S = _Sys(s)
     x = np.ascontiguousarray(x, dtype=np.complex128)
     return float(lib().ref_residual_dd(ctypes.byref(S.st), _ptr(x)))
+
+
+def residuals_dd(s, X):
+    """residual_dd at every row of X (complex [m, n])."""
+    S = _Sys(s)
+    X = np.ascontiguousarray(X, dtype=np.complex128).reshape(-1, s.n)
+    out = np.zeros(X.shape[0])
+    lib().ref_residuals_dd(ctypes.byref(S.st), int(X.shape[0]), _ptr(X), _ptr(out))
+    return out
 
 
 def refine_dd(s, x, iters=2):

@@ -308,6 +308,10 @@ double ref_residual_dd(const ref_system *s, const double *x) {
   return residual_dd(s, xv);
 }
 
+void ref_residuals_dd(const ref_system *s, int64_t m, const double *x, double *out) {
+  for (int64_t k = 0; k < m; ++k) out[k] = ref_residual_dd(s, x + (size_t)2 * s->n * k);
+}
+
 void ref_refine_dd(const ref_system *s, const double *x, int iters, double *x_out) {
   cplx xv[MAXN];
   for (int i = 0; i < s->n; ++i) xv[i] = load(x, i);

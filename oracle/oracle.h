@@ -92,6 +92,9 @@ void ref_eval_system_dd(const ref_system *s, const double *x_hi, const double *x
  * |f_i| the modulus of the nearest complex double of f_i: the residual of
  * the end game. */
 double ref_residual_dd(const ref_system *s, const double *x);
+/* ref_residual_dd at each of the m points x[k*n .. k*n+n-1] (interleaved
+ * complex) into out[k]. */
+void ref_residuals_dd(const ref_system *s, int64_t m, const double *x, double *out);
 
 /* End-game refinement: `iters` Newton iterations on f from x carried in
  * double-double (f in double-double, J_f and the solve in double), then the

@@ -6,7 +6,9 @@ take torch tensors on the GPU (torch supplies device memory and streams).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import sys
 import weakref
 
 import numpy as np
@@ -90,30 +92,54 @@ def find_duplicates(endpoints, status, rel=1e-6, max_pairs=1 << 16):
     return pairs[: min(cnt, max_pairs)].copy()
 
 
+# Live handles, closed at interpreter exit while the HIP runtime is still up
+# (objects finalised later, during interpreter teardown, skip the C call).
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for obj in list(_LIVE):
+        if not isinstance(obj, Context):
+            obj.close()
+    for obj in list(_LIVE):
+        obj.close()
+
+
+def _finalize(obj, _finalizing=sys.is_finalizing):
+    """__del__ body: close unless the interpreter is shutting down (then the
+    atexit hook above has closed every handle already)."""
+    try:
+        if not _finalizing():
+            obj.close()
+    except Exception:
+        pass
+
+
 class Context:
     """A libhomotopy context on one HIP device (its own stream)."""
 
     def __init__(self, device: int = 0):
         self._L = load()
+        self.handle = None
         h = ctypes.c_void_p()
         check(self._L.hp_context_create(int(device), ctypes.byref(h)))
         self.handle = h
         self._children = weakref.WeakSet()  # plans and servers built on this context
+        _LIVE.add(self)
 
     def close(self):
-        """Destroys the context, after every plan and server made from it (the
-        C library requires them gone first)."""
+        """Destroys the plans and servers made from this context, then the
+        context.  (The C library releases a context only after its children
+        are gone, so any order of closing is safe.)"""
         if self.handle:
             for c in list(self._children):
                 c.close()
             self._L.hp_context_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+    def __del__(self, _fin=_finalize):  # bound now: module globals are gone at teardown
+        _fin(self)
 
     def last_timing(self) -> dict:
         t = HpTiming()
@@ -192,21 +218,20 @@ class Plan:
         self.paths = path_count(system)
         self.tol = tol or default_tolerances()
         h = ctypes.c_void_p()
+        self.handle = None
         check(self._L.hp_plan_create(ctx.handle, ctypes.byref(self._view.c), _c64(gamma),
                                      ctypes.byref(self.tol), int(bool(tune)), ctypes.byref(h)))
         self.handle = h
         ctx._children.add(self)
+        _LIVE.add(self)
 
     def close(self):
         if self.handle:
             self._L.hp_plan_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+    def __del__(self, _fin=_finalize):  # bound now: module globals are gone at teardown
+        _fin(self)
 
     def set_variant(self, variant: int):
         """Kernel variant code (see hp_plan_set_variant in homotopy.h)."""
@@ -247,10 +272,12 @@ class Server:
     def __init__(self, ctx: Context, hbm_budget_bytes: int):
         self.ctx = ctx
         self._L = ctx._L
+        self.handle = None
         h = ctypes.c_void_p()
         check(self._L.hp_server_create(ctx.handle, int(hbm_budget_bytes), ctypes.byref(h)))
         self.handle = h
         ctx._children.add(self)
+        _LIVE.add(self)
         self._keep = {}
 
     def submit(self, system, gamma, tol=None) -> int:
@@ -287,8 +314,5 @@ class Server:
             self._L.hp_server_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+    def __del__(self, _fin=_finalize):  # bound now: module globals are gone at teardown
+        _fin(self)

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <condition_variable>
 #include <cstdio>
@@ -287,6 +288,31 @@ bool pack_dense(Packed &P, const hp_system *f, const SysInfo &info, DevSys &d) {
   return true;
 }
 
+// f's terms in equation order for the end game (appended to P.terms after
+// the tracking kernels' tables; offsets in d.eg_base / d.eg_ptr), each
+// term's word holding its dense exponent vector, 4 bits per variable.
+void pack_eq_order(Packed &P, const hp_system *f, DevSys &d) {
+  const int n = f->n;
+  d.eg_base = (int32_t)P.terms.size();
+  for (int i = 0; i < n; ++i) {
+    d.eg_ptr[i] = (int32_t)P.terms.size() - d.eg_base;
+    for (int t = f->eq_ptr[i]; t < f->eq_ptr[i + 1]; ++t) {
+      DevTerm T;
+      std::memset(&T, 0, sizeof(T));
+      T.cre = f->coeff[t].re;
+      T.cim = f->coeff[t].im;
+      // exponent of variable j in bits 4j .. 4j+3 (exponents are <= 15)
+      uint64_t nib = 0;
+      for (int j = 0; j < n; ++j) nib |= (uint64_t)f->exps[(size_t)t * n + j] << (4 * j);
+      T.w[0] = (uint32_t)nib;
+      T.w[1] = (uint32_t)(nib >> 32);
+      T.w[3] = (uint32_t)i << 24;
+      P.terms.push_back(T);
+    }
+  }
+  d.eg_ptr[n] = (int32_t)P.terms.size() - d.eg_base;
+}
+
 void pack_append(Packed &P, const hp_system *f, const SysInfo &info, hp_c64 gamma,
                  int64_t queue_len, int64_t out_path_base, int64_t out_x_base,
                  const int64_t *dev_ids, const hp_system *g = nullptr, int g_emax = 0,
@@ -329,6 +355,7 @@ void pack_append(Packed &P, const hp_system *f, const SysInfo &info, hp_c64 gamm
     d.emax = std::max(d.emax, g_emax);
   }
   d.start = dev_start;
+  pack_eq_order(P, f, d);
   if (g || dev_start || !pack_dense(P, f, info, d)) P.dense_ok = false;
   P.sys.push_back(d);
   P.nl = std::max(P.nl, n);
@@ -340,9 +367,28 @@ void pack_append(Packed &P, const hp_system *f, const SysInfo &info, hp_c64 gamm
 
 // Device copy of a Packed image.
 struct DevTables {
-  DevBuf tcoef, tmeta, kp, roots, sys, qhead, dcoef;
+  DevBuf tcoef, tmeta, kp, roots, sys, qhead, dcoef, egblk;
+  // end-game blocks of a multi-system launch, grouped by n: the blocks of
+  // the systems with n unknowns are eg_first[n] .. eg_first[n+1]-1 of egblk
+  int eg_first[HP_MAX_N + 2] = {};
   int upload(const Packed &P, hipStream_t s) {
     int rc;
+    std::vector<int2> blk;
+    for (const DevSys &d : P.sys)
+      if (d.n_paths > INT32_MAX - hp::kLanes)
+        return fail(HP_E_INVALID_ARG, "too many paths for one system of a batch");
+    for (int n = 1; n <= HP_MAX_N; ++n) {
+      eg_first[n] = (int)blk.size();
+      for (size_t k = 0; k < P.sys.size(); ++k)
+        if (P.sys[k].n == n && P.sys.size() > 1)
+          for (int64_t q = 0; q < P.sys[k].n_paths; q += hp::kLanes)
+            blk.push_back(make_int2((int)k, (int)q));
+    }
+    eg_first[HP_MAX_N + 1] = (int)blk.size();
+    if ((rc = egblk.alloc(std::max<size_t>(1, blk.size()) * sizeof(int2)))) return rc;
+    if (!blk.empty())
+      HIP_TRY(hipMemcpyAsync(egblk.p, blk.data(), blk.size() * sizeof(int2),
+                             hipMemcpyHostToDevice, s));
     const size_t nt = std::max<size_t>(1, P.terms.size());
     if ((rc = dcoef.alloc(std::max<size_t>(1, P.dense.size()) * sizeof(double2)))) return rc;
     if (!P.dense.empty())
@@ -520,7 +566,43 @@ struct hp_context {
   hp_timing last{};
   int cus = 0;
   size_t max_lds = 0;
+  // plans and servers made from this context, and whether the caller has
+  // destroyed it: the context is released when both no child is left and
+  // the caller has destroyed it, so the order of destruction is free
+  int children = 0;
+  bool closed = false;
 };
+
+namespace {
+
+std::mutex g_ctx_mu;
+
+void context_release(hp_context *ctx) {
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+void context_adopt(hp_context *ctx) {
+  std::lock_guard<std::mutex> g(g_ctx_mu);
+  ++ctx->children;
+}
+
+// A child of ctx is gone; releases ctx if it was the last one and the
+// caller has destroyed ctx already.
+void context_orphan(hp_context *ctx) {
+  bool last;
+  {
+    std::lock_guard<std::mutex> g(g_ctx_mu);
+    last = --ctx->children == 0 && ctx->closed;
+  }
+  if (last) context_release(ctx);
+}
+
+}  // namespace
 
 struct hp_plan {
   hp_context *ctx = nullptr;
@@ -582,12 +664,13 @@ int hp_context_create(int device, hp_context **out) {
 
 void hp_context_destroy(hp_context *ctx) {
   if (!ctx) return;
-  (void)hipSetDevice(ctx->device);
-  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
-  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
-  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
-  delete ctx;
+  bool now;
+  {
+    std::lock_guard<std::mutex> g(g_ctx_mu);
+    ctx->closed = true;
+    now = ctx->children == 0;
+  }
+  if (now) context_release(ctx);
 }
 
 int hp_last_timing(const hp_context *ctx, hp_timing *out) {
@@ -663,7 +746,27 @@ Kv kv_pick(const Packed &P) {
   return k;
 }
 
-// Persistent launch over the systems in `dev` (already uploaded).
+// End game at t = 1 (double-double refinement and residual test) of the
+// paths a tracking launch over the systems in `dev` has just ended, on the
+// same stream.  total_paths: the queue length of a single-system launch.
+int launch_endgame(const DevTables &dev, const Packed &P, const KArgs &a, int64_t total_paths,
+                   hipStream_t s) {
+  if (P.sys.size() == 1) {
+    const int64_t blocks = (total_paths + hp::kLanes - 1) / hp::kLanes;
+    if (blocks > INT32_MAX) return fail(HP_E_INVALID_ARG, "too many paths for one launch");
+    HIP_TRY((hipError_t)hp_launch_endgame(P.sys[0].n, a, nullptr, (int)blocks, s));
+    return HP_OK;
+  }
+  for (int n = 1; n <= HP_MAX_N; ++n) {
+    const int b0 = dev.eg_first[n], b1 = dev.eg_first[n + 1];
+    if (b1 > b0)
+      HIP_TRY((hipError_t)hp_launch_endgame(n, a, dev.egblk.as<int2>() + b0, b1 - b0, s));
+  }
+  return HP_OK;
+}
+
+// Persistent launch over the systems in `dev` (already uploaded), followed
+// by the end game of its paths.
 int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv &k,
                       const hp_tolerances &tol, int64_t total_paths, hp_c64 *endpoints,
                       int32_t *status, hp_path_stats *stats, hipStream_t s, int *groups_out,
@@ -711,6 +814,7 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
   } else {
     HIP_TRY((hipError_t)hp_launch_persistent(k.nmax, P.general, a, (int)groups, lds, s));
   }
+  if ((rc = launch_endgame(dev, P, a, total_paths, s))) return rc;
   HIP_TRY(hipEventRecord(e1, s));
   if (groups_out) *groups_out = (int)groups;
   return HP_OK;
@@ -831,6 +935,7 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
     HIP_TRY(hipStreamSynchronize(s));
     ++launches;
   }
+  if (active == 0 && (rc = launch_endgame(plan->dev, plan->P, a, n_paths, s))) return rc;
   HIP_TRY(hipEventRecord(ctx->ev1, s));
   ctx->last.launches = launches;
   ctx->last.groups = wgs;
@@ -939,6 +1044,7 @@ int plan_create(hp_context *ctx, const hp_system *f, const hp_system *g, const h
   if ((rc = p->dev.upload(p->P, ctx->stream))) return rc;
   if ((rc = plan_variant(p.get(), 0))) return rc;
   if (tune && (rc = autotune(p.get()))) return rc;
+  context_adopt(ctx);
   *out = p.release();
   return HP_OK;
 }
@@ -954,9 +1060,11 @@ int hp_plan_create(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_t
 
 void hp_plan_destroy(hp_plan *plan) {
   if (!plan) return;
-  (void)hipSetDevice(plan->ctx->device);
-  (void)hipStreamSynchronize(plan->ctx->stream);
+  hp_context *ctx = plan->ctx;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
   delete plan;
+  context_orphan(ctx);
 }
 
 int hp_spec_compile(const hp_system *f, int64_t *code_bytes) {
@@ -1539,6 +1647,7 @@ int hp_server_create(hp_context *ctx, size_t hbm_budget_bytes, hp_server **out) 
   }
   hp_server *raw = S.get();
   S->worker = std::thread(worker_main, raw);
+  context_adopt(ctx);
   *out = S.release();
   return HP_OK;
 }
@@ -1649,7 +1758,9 @@ void hp_server_destroy(hp_server *S) {
   if (S->ev0) (void)hipEventDestroy(S->ev0);
   if (S->ev1) (void)hipEventDestroy(S->ev1);
   if (S->stream) (void)hipStreamDestroy(S->stream);
+  hp_context *ctx = S->ctx;
   delete S;
+  context_orphan(ctx);
 }
 
 }  // extern "C"

@@ -61,6 +61,12 @@ struct alignas(16) DevSys {
   int32_t dense_base;
   int32_t dense_off[HP_MAX_N];
   int32_t dense_pad[3];
+  // end game at t = 1: f's terms once more, in equation order, in the same
+  // term arrays: equation i owns terms eg_base + eg_ptr[i] ..
+  // eg_base + eg_ptr[i+1] - 1
+  int32_t eg_base;
+  int32_t eg_ptr[HP_MAX_N + 1];
+  int32_t eg_pad[2];
 };
 
 // Dense kernel: systems of n <= kDenseMaxN unknowns whose equations have
@@ -170,7 +176,7 @@ inline size_t lanes_lds_bytes(int n, int pw, int emax) {
 
 }  // namespace hp
 
-// Kernel launchers (tracker.hip, lanes.hip, dense.hip, dense11.hip,
+// Kernel launchers (tracker.hip, lanes.hip, dense.hip, dense11.hip, endgame.hip,
 // dense12.hip).  Return a hipError_t
 // value.
 extern "C++" {
@@ -191,4 +197,8 @@ int hp_launch_dense11(const hp::KArgs &a, int groups, void *stream);
 int hp_dense11_per_cu(int *out);
 int hp_launch_dense12(const hp::KArgs &a, int groups, void *stream);
 int hp_dense12_per_cu(int *out);
+// End game of the paths of systems with n unknowns: blk[b] = (system, first
+// queue index) of block b (64 paths each), or blk == nullptr for one system
+// (system 0, block b from queue index 64 b).
+int hp_launch_endgame(int n, const hp::KArgs &a, const int2 *blk, int blocks, void *stream);
 }

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import workloads as W
-from parity import REL, compare_paths
+from parity import assert_parity, assert_residuals
 
 pytestmark = pytest.mark.gpu
 
@@ -27,21 +27,9 @@ def ctx():
     c.close()
 
 
-def compare(e, st, sts, s, g, ids=None):
-    """Parity of one system's paths (all, or the sampled ids) with the oracle;
-    returns the number of borderline residual-gate flips."""
-    if ids is None:
-        ids = np.arange(s.bezout())
-    e_o, s_o, st_o = oracle.track_paths(s, g, path_ids=ids, n_threads=NTHREADS)
-    hard, flips = compare_paths(e[ids], st[ids], sts[ids], e_o, s_o, st_o)
-    assert len(hard) == 0, f"{s.name}: paths {ids[hard][:8]} differ from the oracle"
-    if len(flips):
-        log(f"  {s.name}: borderline residual-gate flips at {ids[flips]}")
-    return len(flips)
-
-
 def test_small_batch_full_parity(ctx):
-    """16 dense systems, n 3..10 as drawn, only those with <= 1000 paths."""
+    """16 dense systems, n 3..10 as drawn, only those with <= 1000 paths: every
+    path against the oracle."""
     wl = W.dense_batch(64, seed=3)
     pick = [i for i, s in enumerate(wl.systems) if s.bezout() <= 1000][:16]
     systems = [wl.systems[i] for i in pick]
@@ -49,12 +37,11 @@ def test_small_batch_full_parity(ctx):
     log("systems", [(s.name, s.bezout()) for s in systems])
     res = ctx.track_batch(systems, gammas)
     for (e, st, sts), s, g in zip(res, systems, gammas):
-        compare(e, st, sts, s, g)
-        # a generic dense system has prod d_i finite roots: every path reaches
-        # t = 1 (none diverges); a few large roots may miss the absolute
-        # residual gate by rounding and end FAILED_NEWTON_T1
+        e_o, s_o, _ = oracle.track_paths(s, g, n_paths=s.bezout(), n_threads=NTHREADS)
+        assert_parity(e, st, e_o, s_o, s.name, s)
+        assert_residuals(s, e, st)
+        # a generic dense system has prod d_i finite roots: every path reaches t = 1
         assert (sts["t_final"] == 1.0).all(), s.name
-        assert np.isin(st, [0, 4]).all(), s.name
 
 
 def test_batch_equals_single_system_launches(ctx):
@@ -66,26 +53,35 @@ def test_batch_equals_single_system_launches(ctx):
     bitwise = 0
     for (e, st, sts), s, g in zip(res, systems, gammas):
         e1, st1, sts1 = ctx.track_paths(s, g)
-        hard, flips = compare_paths(e, st, sts, e1, st1, sts1)
-        assert len(hard) == 0 and len(flips) == 0, s.name
+        assert_parity(e, st, e1, st1, s.name, s)
         bitwise += int(np.array_equal(e, e1) and np.array_equal(st, st1))
     log(f"bitwise-identical systems: {bitwise}/{len(systems)}")
 
 
 def test_full_256_system_batch_sampled(ctx):
-    """All 256 systems (n 3..10, degrees 2..3) in one launch; 6 stride-sampled
-    paths per system checked against the oracle; every path must reach t = 1
-    (generic dense systems have exactly prod d_i finite roots) and every
-    converged endpoint must pass the residual gate."""
+    """All 256 systems (n 3..10, degrees 2..3, 481,743 paths) in one launch.
+    Against the oracle: a stride sample of at least 20,000 paths over the
+    whole batch plus every path the GPU did not converge, all with identical
+    outcomes and matching endpoints.  Every converged endpoint passes the
+    residual gate evaluated by the oracle, and every path reaches t = 1
+    (generic dense systems have exactly prod d_i finite roots)."""
     wl = W.dense_batch(256, seed=3)
     gammas = [complex(g) for g in wl.gammas]
     log(f"total paths {wl.total_paths}")
     res = ctx.track_batch(wl.systems, gammas)
-    n_conv = flips = 0
-    for (e, st, sts), s, g in zip(res, wl.systems, gammas):
-        ids = W.stride_sample(s.bezout(), 6)
-        flips += compare(e, st, sts, s, g, ids)
-        assert (sts["residual"][st == 0] <= 1e-10).all(), s.name
+    base = np.cumsum([0] + [s.bezout() for s in wl.systems])
+    sample = set(W.stride_sample(wl.total_paths, 20000).tolist())
+    n_conv = n_checked = 0
+    for k, ((e, st, sts), s, g) in enumerate(zip(res, wl.systems, gammas)):
+        local = sorted({int(i - base[k]) for i in sample if base[k] <= i < base[k + 1]}
+                       | set(np.nonzero(st != 0)[0].tolist()))
+        ids = np.asarray(local, np.int64)
+        if len(ids):
+            e_o, s_o, _ = oracle.track_paths(s, g, path_ids=ids, n_threads=NTHREADS)
+            assert_parity(e[ids], st[ids], e_o, s_o, s.name, s, ids)
+        n_checked += len(ids)
         n_conv += int((st == 0).sum())
         assert (sts["t_final"] == 1.0).all(), s.name
-    log(f"converged {n_conv} of {wl.total_paths}; borderline flips in the sample {flips}")
+        assert_residuals(s, e, st)
+    log(f"converged {n_conv} of {wl.total_paths}; oracle-checked paths {n_checked}")
+    assert n_checked >= 20000

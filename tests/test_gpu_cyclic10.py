@@ -1,78 +1,149 @@
 """The large configuration: random unit-circle coefficients on the cyclic
-10-roots supports, all 10! = 3,628,800 total-degree paths in one persistent
-launch, divergent paths truncated at ||x||_inf > 1e8, then the duplicate
-post-pass (re-track both paths of every pair of coinciding endpoints).
+10-roots supports (seed 5), all 10! = 3,628,800 total-degree paths in one
+persistent launch of the kernel specialised to the support, divergent paths
+truncated at ||x||_inf > 1e8, then the duplicate post-pass.
 
-Checked against the CPU oracle path by path on a stride sample (the oracle
-cannot track all 3.6 M paths in test time) and by properties that hold at
-any size: the residual gate on every converged endpoint, pairwise distinct
-converged endpoints, and paths that end before t = 1 only by truncation or a
-failed step."""
+Exact parity with the CPU oracle over every path: the oracle's result for
+all 3,628,800 paths is stored in tests/golden/cyclic10_seed5.npz (written by
+tests/golden/make_cyclic10_golden.py, which calls only the oracle).  Every
+path must have the oracle's converged / not-converged outcome and every
+converged endpoint must match the oracle's within 1e-8 relative."""
+import json
 import os
 import sys
 
 import numpy as np
 import pytest
 
-import oracle
 import workloads as W
-from parity import compare_paths
+from parity import assert_parity, assert_residuals
 
 pytestmark = pytest.mark.gpu
 
-NTHREADS = min(16, os.cpu_count() or 1)
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden", "cyclic10_seed5.npz")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-@pytest.fixture(scope="module")
-def solved():
+def golden():
+    if not os.path.exists(GOLDEN):
+        pytest.skip("cyclic-10 oracle golden not written yet")
+    z = np.load(GOLDEN)
+    with open(GOLDEN.replace(".npz", ".json")) as fh:
+        meta = json.load(fh)
+    return z, meta
+
+
+def track(ctx, s, g):
+    import torch
     import paper_1804_03807_amd as hp
-    ctx = hp.Context(0)
+    plan = ctx.plan(s, g)
+    e, st, sts = plan.outputs(s.bezout())
+    plan.track_device(e, st, sts)
+    torch.cuda.synchronize()
+    variant = ctx.last_timing()["variant"]
+    out = hp.Plan.endpoints_to_numpy(e), st.cpu().numpy(), hp.Plan.stats_to_numpy(sts)
+    plan.close()
+    del e, st, sts
+    torch.cuda.empty_cache()
+    return out, variant
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1804_03807_amd as hp
+    c = hp.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def tracked(ctx):
     wl = W.cyclic10()
     s, g = wl.systems[0], complex(wl.gammas[0])
-    log(f"case cyclic10 paths={s.bezout()} (hp_solve)")
-    e, st, sts, remaining = ctx.solve(s, g)
-    t = ctx.last_timing()
-    log(f"  converged={int((st == 0).sum())} remaining duplicate pairs={remaining} "
-        f"total_ms={t['total_ms']:.0f}")
-    yield s, g, e, st, sts, remaining
-    ctx.close()
+    log(f"case cyclic10 paths={s.bezout()} (specialised plan)")
+    (e, st, sts), variant = track(ctx, s, g)
+    log(f"  variant {variant}, status counts {np.bincount(st, minlength=5).tolist()}")
+    return s, g, e, st, sts
 
 
-def test_cyclic10_no_duplicates_and_residual_gate(solved):
-    s, g, e, st, sts, remaining = solved
-    assert e.shape == (3628800, 10)
-    assert remaining == 0
+def test_cyclic10_exact_parity_with_oracle_golden(tracked):
+    s, g, e, st, sts = tracked
+    z, meta = golden()
+    st_o = z["status"].astype(np.int32)
+    e_o = np.zeros_like(e)
+    e_o[z["conv_ids"]] = z["conv_x"]
+    assert int((st_o == 0).sum()) == meta["converged"]
+    assert_parity(e, st, e_o, st_o, "cyclic10 / 310 vs oracle golden", s, log=log)
+    assert (np.bincount(st, minlength=5)[0] == meta["status_histogram"][0])
+
+
+def test_cyclic10_residual_gate_and_structure(tracked):
+    s, g, e, st, sts = tracked
     conv = st == 0
+    assert_residuals(s, e, st)
     assert (sts["residual"][conv] <= 1e-10).all()
-    assert (np.abs(e[conv]).max(axis=1) <= 1e8).all()
     # every coordinate of a finite root is nonzero: the last equation is
     # x_1 ... x_10 = c with c on the unit circle
     assert (np.abs(e[conv]).min(axis=1) > 1e-8).all()
-    # independent duplicate check (oracle's O(N^2) scan) on the converged set
-    ce = e[conv]
+    # converged paths reached t = 1; DIVERGED endpoints lie beyond the radius
+    assert (sts["t_final"][conv] == 1.0).all()
+    assert (np.abs(e[st == 1]).max(axis=1) > 1e8).all()
+
+
+def test_cyclic10_gamma_invariance(ctx):
+    """A second gamma tracks different paths to the same finite roots.  On
+    this workload the tracker loses a few hundred finite roots of large norm
+    to the minimum step size near t = 1 (the oracle as well), and which ones
+    depends on gamma; so the check is that both converged sets consist of
+    distinct roots (residual gate by the oracle's evaluator, no duplicates)
+    and share all but a fraction of a percent of their points."""
+    import oracle
+    from parity import assert_residuals
+    z, meta = golden()
+    wl = W.cyclic10()
+    s = wl.systems[0]
+    g2 = complex(np.exp(2j * np.pi * 0.613))
+    (e2, st2, _), _ = track(ctx, s, g2)
+    c1, c2 = z["conv_x"], e2[st2 == 0]
+    assert_residuals(s, e2, st2)
+    assert len(oracle.find_duplicates(c2, np.zeros(len(c2), np.int32))) == 0
+    common = len(c2) - count_unmatched(c2, c1)
+    log(f"  converged gamma'={len(c2)} oracle(gamma)={len(c1)} common={common}")
+    assert common >= 0.995 * min(len(c1), len(c2))
+
+
+def count_unmatched(a, b, rel=1e-8):
+    """Rows of a with no row of b within rel (sort on a random projection)."""
+    rng = np.random.default_rng(0)
+    w = rng.uniform(-1, 1, (2, a.shape[1]))
+    w /= np.abs(w).sum()
+    pa = a.real @ w[0] + a.imag @ w[1]
+    pb = b.real @ w[0] + b.imag @ w[1]
+    o = np.argsort(pb)
+    pbs = pb[o]
+    miss = 0
+    for i in range(len(a)):
+        tol = 2 * rel * max(1.0, float(np.abs(a[i]).max()))
+        lo, hi = np.searchsorted(pbs, pa[i] - tol), np.searchsorted(pbs, pa[i] + tol, "right")
+        if not any(np.abs(a[i] - b[j]).max() <= rel * max(1.0, np.abs(b[j]).max()) for j in o[lo:hi]):
+            miss += 1
+    return miss
+
+
+def test_cyclic10_solve_post_pass(ctx):
+    """hp_solve: tracking, then the duplicate post-pass; no duplicate pair is
+    left and the converged set contains the tracking's."""
+    import oracle
+    z, meta = golden()
+    wl = W.cyclic10()
+    s, g = wl.systems[0], complex(wl.gammas[0])
+    e, st, sts, remaining = ctx.solve(s, g)
+    log(f"  hp_solve: converged {int((st == 0).sum())}, remaining pairs {remaining}")
+    assert remaining == 0
+    ce = e[st == 0]
     assert len(oracle.find_duplicates(ce, np.zeros(len(ce), np.int32))) == 0
-
-
-def test_cyclic10_sampled_parity(solved):
-    s, g, e, st, sts, _ = solved
-    ids = W.stride_sample(s.bezout(), 1500)
-    ref = oracle.track_paths(s, g, path_ids=ids, n_threads=NTHREADS)
-    hard, flips = compare_paths(e[ids], st[ids], sts[ids], *ref)
-    log(f"  sample {len(ids)}: oracle converged {int((ref[1] == 0).sum())}, "
-        f"gpu {int((st[ids] == 0).sum())}, borderline flips {len(flips)}")
-    assert len(hard) == 0, ids[hard][:8]
-
-
-def test_cyclic10_statuses_consistent(solved):
-    _, _, e, st, sts, _ = solved
-    # converged and FAILED_NEWTON_T1 paths reached t = 1; the others stopped
-    # before it by truncation or a failed step
-    assert (sts["t_final"][(st == 0) | (st == 4)] == 1.0).all()
-    div = st == 1
-    assert (np.abs(e[div]).max(axis=1) > 1e8).all()
-    counts = np.bincount(st, minlength=5)
-    log(f"  status counts {counts.tolist()}")
+    assert int((st == 0).sum()) >= meta["converged"]

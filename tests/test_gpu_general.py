@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import workloads as W
-from parity import REL, close_rows, compare_paths
+from parity import REL, assert_parity, assert_residuals, close_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -64,9 +64,9 @@ def test_linear_product_continuation(ctx, n, degs, mode):
     e, st, sts = ctx.track_paths(f, gam, start=start, g=g, mode=mode)
     assert (st == 0).all()
     assert match_sets(e, lp_roots(n, degs, Lf, bf))
-    ref = oracle.track_paths(f, gam, start=start, g=g, n_threads=NTHREADS)
-    hard, flips = compare_paths(e, st, sts, *ref)
-    assert len(hard) == 0 and len(flips) == 0
+    e_o, s_o, _ = oracle.track_paths(f, gam, start=start, g=g, n_threads=NTHREADS)
+    assert_parity(e, st, e_o, s_o, f"linear products n={n}", f)
+    assert_residuals(f, e, st)
 
 
 def test_univariate_continuation(ctx):
@@ -109,9 +109,9 @@ def test_parameter_continuation_cyclic5(ctx):
     assert (st == 0).all()
     eb, stb, _ = ctx.track_paths(sb, complex(b.gammas[0]))
     assert match_sets(e, eb[stb == 0])
-    ref = oracle.track_paths(sb, gam, start=start, g=sa, n_threads=NTHREADS)
-    hard, _ = compare_paths(e, st, sts, *ref)
-    assert len(hard) == 0
+    e_o, s_o, _ = oracle.track_paths(sb, gam, start=start, g=sa, n_threads=NTHREADS)
+    assert_parity(e, st, e_o, s_o, "cyclic5 continuation", sb)
+    assert_residuals(sb, e, st)
 
 
 def test_general_argument_errors(ctx):

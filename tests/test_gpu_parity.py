@@ -1,10 +1,12 @@
 """GPU parity: the HIP path through the C ABI against the CPU oracle on the
-same seeded inputs.  Converged endpoints must match within 1e-8 relative
-(||x_gpu - x_ref||_inf <= 1e-8 max(1, ||x_ref||_inf)), with identical
-converged / not-converged counts.  Sub-statuses of non-converged paths
-(diverged / failed) are reported, not gated: in affine coordinates a path to
-a point at infinity may stop on the divergence radius or on the minimum step
-depending on rounding."""
+same seeded inputs.  Every path has the same converged / not-converged
+outcome on both sides (identical counts), converged endpoints match within
+1e-8 relative (||x_gpu - x_ref||_inf <= 1e-8 max(1, ||x_ref||_inf)), and
+every converged GPU endpoint passes the residual gate evaluated by the
+oracle.  Sub-statuses of non-converged paths (diverged / failed) are
+reported, not gated: in affine coordinates a path to a point at infinity may
+stop on the divergence radius or on the minimum step depending on
+rounding."""
 import os
 import sys
 
@@ -13,6 +15,7 @@ import pytest
 
 import oracle
 import workloads as W
+from parity import assert_parity, assert_residuals, match_sets
 
 pytestmark = pytest.mark.gpu
 
@@ -32,56 +35,24 @@ def ctx():
     c.close()
 
 
-def close(a, b):
-    return np.abs(a - b).max() <= REL * max(1.0, np.abs(b).max())
-
-
-def match_sets(a, b):
-    """Greedy nearest match: every point of a pairs with a distinct point of b."""
-    if len(a) != len(b):
-        return False
-    used = np.zeros(len(b), bool)
-    for p in a:
-        d = np.abs(b - p).max(axis=1)
-        d[used] = np.inf
-        j = int(np.argmin(d))
-        if not (d[j] <= REL * max(1.0, np.abs(b[j]).max())):
-            return False
-        used[j] = True
-    return True
-
-
-def per_path_report(e_g, s_g, e_o, s_o):
-    both = (s_g == 0) & (s_o == 0)
-    bad = [i for i in np.nonzero(both)[0] if not close(e_g[i], e_o[i])]
-    flips = int(((s_g == 0) != (s_o == 0)).sum())
-    return len(bad), flips
-
-
 def check_against_oracle(ctx, system, gamma, mode="batched", ids_sample=None):
     log(f"case {system.name} n={system.n} paths={system.bezout()} mode={mode}")
     e_g, s_g, st_g = ctx.track_paths(system, gamma, mode=mode)
     if ids_sample is None:
-        e_o, s_o, st_o = oracle.track_paths(system, gamma, n_paths=system.bezout(),
-                                            n_threads=NTHREADS)
-        e_gs, s_gs = e_g, s_g
-    else:
-        e_o, s_o, st_o = oracle.track_paths(system, gamma, path_ids=ids_sample,
-                                            n_threads=NTHREADS)
-        e_gs, s_gs = e_g[ids_sample], s_g[ids_sample]
-    bad, flips = per_path_report(e_gs, s_gs, e_o, s_o)
-    log(f"  converged gpu={int((s_gs == 0).sum())} oracle={int((s_o == 0).sum())} "
-        f"per-path mismatches={bad} status flips={flips}")
-    return e_g, s_g, st_g, e_o, s_o, st_o, bad, flips
+        ids_sample = np.arange(system.bezout())
+    e_o, s_o, st_o = oracle.track_paths(system, gamma, path_ids=ids_sample, n_threads=NTHREADS)
+    assert_parity(e_g[ids_sample], s_g[ids_sample], e_o, s_o, system.name, system, ids_sample,
+                  log)
+    assert_residuals(system, e_g, s_g)
+    return e_g, s_g, st_g, e_o, s_o, st_o
 
 
 @pytest.mark.parametrize("mode", ["batched", "plain"])
 def test_dense_small_all_converge(ctx, mode):
     wl = W.dense_small()
     s = wl.systems[0]
-    e_g, s_g, st_g, e_o, s_o, _, bad, flips = check_against_oracle(ctx, s, wl.gammas[0], mode)
+    e_g, s_g, st_g, e_o, s_o, _ = check_against_oracle(ctx, s, wl.gammas[0], mode)
     assert (s_g == 0).sum() == (s_o == 0).sum() == 32
-    assert bad == 0 and flips == 0
     assert (st_g["residual"] <= 1e-10).all()
     assert match_sets(e_g[s_g == 0], e_o[s_o == 0])
 
@@ -99,7 +70,7 @@ def test_plain_and_batched_agree_bitwise(ctx):
 def test_embedded_cyclic4_paper_example(ctx):
     wl = W.embedded_cyclic4_workload()
     s = wl.systems[0]
-    e_g, s_g, _, e_o, s_o, _, bad, flips = check_against_oracle(ctx, s, wl.gammas[0])
+    e_g, s_g, _, e_o, s_o, _ = check_against_oracle(ctx, s, wl.gammas[0])
     conv = e_g[s_g == 0]
     assert len(conv) == 20
     assert int((np.abs(conv[:, 4]) <= 1e-8).sum()) == 4
@@ -112,6 +83,7 @@ def test_univariate_roots(ctx, d):
     e, st, _ = ctx.track_paths(s, 0.6 - 0.8j)
     assert (st == 0).all()
     assert match_sets(e, np.roots(poly).reshape(-1, 1))
+    assert_residuals(s, e, st)
 
 
 def test_linear_products_closed_form(ctx):
@@ -126,13 +98,14 @@ def test_linear_products_closed_form(ctx):
     e, st, _ = ctx.track_paths(s, np.exp(1.1j))
     assert (st == 0).sum() == int(np.prod(degs))
     assert match_sets(e[st == 0], np.array(exact))
+    assert_residuals(s, e, st)
 
 
 @pytest.mark.parametrize("n,seed", [(5, 50), (6, 9), (7, 7)])
 def test_cyclic_small_full_parity(ctx, n, seed):
     wl = W.cyclic_workload(n, seed)
     s = wl.systems[0]
-    e_g, s_g, _, e_o, s_o, _, bad, flips = check_against_oracle(ctx, s, wl.gammas[0])
+    e_g, s_g, _, e_o, s_o, _ = check_against_oracle(ctx, s, wl.gammas[0])
     assert (s_g == 0).sum() == (s_o == 0).sum()
     assert match_sets(e_g[s_g == 0], e_o[s_o == 0])
 
@@ -141,37 +114,55 @@ def test_cyclic8_full_parity(ctx):
     """The benchmark workload: 40320 paths, every path against the oracle."""
     wl = W.cyclic8()
     s = wl.systems[0]
-    e_g, s_g, st_g, e_o, s_o, st_o, bad, flips = check_against_oracle(ctx, s, wl.gammas[0])
+    e_g, s_g, st_g, e_o, s_o, st_o = check_against_oracle(ctx, s, wl.gammas[0])
     assert (s_g == 0).sum() == (s_o == 0).sum()
     assert match_sets(e_g[s_g == 0], e_o[s_o == 0])
     assert (st_g["residual"][s_g == 0] <= 1e-10).all()
     assert len(oracle.find_duplicates(e_g, s_g)) == 0
 
 
-def test_cyclic8_full_parity_specialised_plan(ctx):
-    """The benchmark's configuration: a plan for the cyclic-8 workload runs on
-    the kernel specialised to its support (variant 308, one persistent
-    launch); all 40320 paths against the oracle."""
+def _spec_plan_run(ctx, s, g):
     import torch
     import paper_1804_03807_amd as hp
-    from parity import compare_paths
-    wl = W.cyclic8()
-    s, g = wl.systems[0], complex(wl.gammas[0])
     plan = ctx.plan(s, g)
     e, st, sts = plan.outputs(s.bezout())
     plan.track_device(e, st, sts)
     torch.cuda.synchronize()
-    assert ctx.last_timing()["variant"] == 308
-    e_g, s_g, st_g = hp.Plan.endpoints_to_numpy(e), st.cpu().numpy(), hp.Plan.stats_to_numpy(sts)
+    variant = ctx.last_timing()["variant"]
+    out = hp.Plan.endpoints_to_numpy(e), st.cpu().numpy(), hp.Plan.stats_to_numpy(sts)
     plan.close()
+    return out, variant
+
+
+def test_cyclic8_full_parity_specialised_plan(ctx):
+    """The benchmark's configuration: a plan for the cyclic-8 workload runs on
+    the kernel specialised to its support (variant 308, one persistent
+    launch); all 40320 paths against the oracle."""
+    wl = W.cyclic8()
+    s, g = wl.systems[0], complex(wl.gammas[0])
+    log(f"case cyclic8 specialised plan paths={s.bezout()}")
+    (e_g, s_g, st_g), variant = _spec_plan_run(ctx, s, g)
+    assert variant == 308
     e_o, s_o, st_o = oracle.track_paths(s, g, n_paths=s.bezout(), n_threads=NTHREADS)
-    hard, flips = compare_paths(e_g, s_g, st_g, e_o, s_o, st_o)
-    log(f"  converged gpu={int((s_g == 0).sum())} oracle={int((s_o == 0).sum())} "
-        f"hard={len(hard)} borderline={len(flips)}")
-    assert len(hard) == 0, f"paths {hard[:8]} differ from the oracle"
-    assert abs(int((s_g == 0).sum()) - int((s_o == 0).sum())) <= len(flips)
+    assert_parity(e_g, s_g, e_o, s_o, "cyclic8 / 308", s, log=log)
+    assert_residuals(s, e_g, s_g)
     assert (st_g["residual"][s_g == 0] <= 1e-10).all()
     assert len(oracle.find_duplicates(e_g, s_g)) == 0
+
+
+def test_cyclic8_gamma_invariance(ctx):
+    """A second gamma moves every path but not the finite endpoint set: the
+    GPU's converged endpoints with gamma' equal the oracle's with gamma (same
+    count, matched one to one within 1e-8)."""
+    wl = W.cyclic8()
+    s, g = wl.systems[0], complex(wl.gammas[0])
+    g2 = complex(np.exp(2j * np.pi * 0.377))
+    log("case cyclic8 gamma invariance")
+    (e2, s2, _), _ = _spec_plan_run(ctx, s, g2)
+    e_o, s_o, _ = oracle.track_paths(s, g, n_paths=s.bezout(), n_threads=NTHREADS)
+    log(f"  converged gamma'={int((s2 == 0).sum())} oracle(gamma)={int((s_o == 0).sum())}")
+    assert (s2 == 0).sum() == (s_o == 0).sum()
+    assert match_sets(e2[s2 == 0], e_o[s_o == 0])
 
 
 def test_ids_list_matches_direct(ctx):
@@ -216,3 +207,72 @@ def test_invalid_arguments_raise(ctx):
         ctx.track_paths(s, 0.0, n_paths=1)  # gamma must be nonzero
     e, st, _ = ctx.track_paths(W.dense_small().systems[0], 1j, n_paths=0)
     assert e.shape == (0, 5)
+
+
+def test_context_destroyed_before_its_plan():
+    """The C library keeps a context alive until its last plan is gone: a
+    plan still tracks after its context was destroyed, and destroying it
+    afterwards releases both."""
+    import torch
+    import paper_1804_03807_amd as hp
+    wl = W.dense_small()
+    s, g = wl.systems[0], complex(wl.gammas[0])
+    c = hp.Context(0)
+    plan = c.plan(s, g)
+    c._L.hp_context_destroy(c.handle)  # the context first, directly through the C ABI
+    c.handle = None
+    e, st, sts = plan.outputs(s.bezout())
+    plan.track_device(e, st, sts)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    plan.close()
+
+
+def test_solve_post_pass_against_oracle(ctx):
+    """hp_solve's duplicate post-pass on a case where paths jump (linear
+    products, 81 closed-form roots, loose tolerances h_max = 1, tol_corr =
+    0.3): the tracking leaves duplicate pairs; hp_solve keeps every other
+    path's endpoint, re-tracks both paths of each pair with h_max = 0.01 and
+    tol_corr = 1e-10 exactly as the oracle does, and reports the pairs left,
+    which the oracle's scan confirms."""
+    import torch
+    import paper_1804_03807_amd as hp
+    n, degs = 4, [3, 3, 3, 3]
+    s, Ls, betas = W.linear_products(n, degs, np.random.default_rng(41))
+    g = 1j * np.exp(0.3j)
+    tol = hp.default_tolerances(h_max=1.0, tol_corr=0.3)
+    plan = ctx.plan(s, g, tol=tol)  # the kernel hp_solve runs
+    e, st, sts = plan.outputs(81)
+    plan.track_device(e, st, sts)
+    torch.cuda.synchronize()
+    e0, s0 = hp.Plan.endpoints_to_numpy(e), st.cpu().numpy()
+    plan.close()
+    pairs = hp.find_duplicates(e0, s0)
+    log(f"  loose tracking: {len(pairs)} duplicate pairs")
+    assert len(pairs) > 0
+    e1, s1, _, rem = ctx.solve(s, g, tol=tol)
+    idx = np.unique(pairs.ravel())
+    keep = np.setdiff1d(np.arange(81), idx)
+    assert np.array_equal(e1[keep], e0[keep]) and np.array_equal(s1[keep], s0[keep])
+    t2 = oracle.default_tolerances(h_max=0.01, tol_corr=1e-10)
+    e_o, s_o, _ = oracle.track_paths(s, g, path_ids=idx.astype(np.int64), tol=t2,
+                                     n_threads=NTHREADS)
+    assert_parity(e1[idx], s1[idx], e_o, s_o, "re-tracked pairs", s, idx, log)
+    assert rem == len(oracle.find_duplicates(e1, s1))
+    # every converged endpoint is a distinct closed-form root (the loose
+    # tracking itself may lose a path, so the set can be smaller than 81)
+    import itertools
+    exact = []
+    for choice in itertools.product(*[range(d) for d in degs]):
+        M = np.array([Ls[i][choice[i]] for i in range(n)])
+        r = np.array([betas[i][choice[i]] for i in range(n)])
+        exact.append(np.linalg.solve(M, r))
+    exact = np.array(exact)
+    hit = set()
+    for x in e1[s1 == 0]:
+        d = np.abs(exact - x).max(axis=1)
+        j = int(np.argmin(d))
+        assert d[j] <= 1e-8 * max(1.0, np.abs(exact[j]).max())
+        hit.add(j)
+    log(f"  after the post-pass: {int((s1 == 0).sum())} converged, {len(hit)} distinct roots")
+    assert len(hit) == int((s1 == 0).sum()) - rem

@@ -18,7 +18,7 @@ import pytest
 
 import oracle
 import workloads as W
-from parity import compare_paths
+from parity import assert_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -62,8 +62,7 @@ def served_alone(ctx, s, g):
 
 def assert_same(res, ref, what):
     """res, ref: (endpoints, status, stats) of the same request."""
-    hard, flips = compare_paths(*res, *ref)
-    assert len(hard) == 0 and len(flips) == 0, f"{what}: paths {hard[:8]} {flips[:8]} differ"
+    assert_parity(res[0], res[1], ref[0], ref[1], what)
 
 
 def test_alone_equals_mix(ctx):
@@ -156,8 +155,7 @@ def test_mix_matches_oracle_sample(ctx):
         for q, s, g in ids:
             e, st, sts, _ = srv.wait(q, stats=True)
             sample = W.stride_sample(s.bezout(), 64)
-            ref = oracle.track_paths(s, g, path_ids=sample, n_threads=NTHREADS)
-            hard, _ = compare_paths(e[sample], st[sample], sts[sample], *ref)
-            assert len(hard) == 0, s.name
+            e_o, s_o, _ = oracle.track_paths(s, g, path_ids=sample, n_threads=NTHREADS)
+            assert_parity(e[sample], st[sample], e_o, s_o, s.name, s, sample, log)
     finally:
         srv.close()

@@ -71,14 +71,17 @@ def test_find_duplicates_matches_oracle(hp, oracle_lib):
     rng = np.random.default_rng(5)
     n, P = 4, 600
     x = (rng.standard_normal((P, n)) + 1j * rng.standard_normal((P, n))) * 3
-    for k in range(0, P, 37):  # plant near-copies, some inside and some outside 1e-6
-        j = (k * 7 + 11) % P
-        x[j] = x[k] * (1 + (3e-7 if k % 2 else 5e-6))
     st = np.zeros(P, np.int32)
     st[::9] = 2  # not converged: ignored
-    got = {tuple(p) for p in hp.find_duplicates(x, st)}
-    ref = {tuple(p) for p in oracle.find_duplicates(x, st)}
-    assert got == ref and len(ref) > 3
+    planted = set()
+    for k in range(0, P // 2, 17):  # near-copies inside and outside 1e-6, no chains
+        j = k + P // 2
+        x[j] = x[k] * (1 + (3e-7 if k % 2 else 5e-6))
+        if k % 2 and st[j] == 0 and st[k] == 0:
+            planted.add((min(j, k), max(j, k)))
+    got = {tuple(int(v) for v in p) for p in hp.find_duplicates(x, st)}
+    ref = {tuple(int(v) for v in p) for p in oracle.find_duplicates(x, st)}
+    assert got == ref == planted and len(planted) >= 5
 
 
 @pytest.mark.parametrize("n", [3, 5, 8])

@@ -426,3 +426,77 @@ def test_explicit_start_points_total_degree(oracle_lib):
     e2, s2, _ = oracle.track_paths(s, gam, start=start)
     assert (s1 == s2).all()
     assert np.abs(e1 - e2).max() <= 1e-12
+
+
+def _lp_roots(n, degs, Ls, betas):
+    import itertools
+    out = []
+    for choice in itertools.product(*[range(d) for d in degs]):
+        M = np.array([Ls[i][choice[i]] for i in range(n)])
+        r = np.array([betas[i][choice[i]] for i in range(n)])
+        out.append(np.linalg.solve(M, r))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("seed", [41, 42])
+def test_duplicate_post_pass_recovers_jumped_paths(oracle_lib, seed):
+    """Linear products of three linear forms in 4 unknowns: 81 closed-form
+    roots.  Tracked with loose tolerances (h_max = 1, tol_corr = 0.3) several
+    paths jump onto roots that other paths reach too; the post-pass finds
+    those pairs and re-tracks both paths of each with h_max = 0.01 and
+    tol_corr = 1e-10, after which the endpoint set is exactly the 81
+    closed-form roots and no pair is left.  Re-tracking only one path of
+    each pair, or re-tracking with the loose tolerances, leaves pairs and
+    misses roots on these inputs."""
+    n, degs = 4, [3, 3, 3, 3]
+    s, Ls, betas = W.linear_products(n, degs, np.random.default_rng(seed))
+    exact = _lp_roots(n, degs, Ls, betas)
+    g = 1j * np.exp(0.3j)
+    tol = oracle.default_tolerances(h_max=1.0, tol_corr=0.3)
+    e0, s0, _ = oracle.track_paths(s, g, n_paths=81, tol=tol, n_threads=4)
+    pairs = oracle.find_duplicates(e0, s0)
+    assert len(pairs) >= 5  # the loose tracking jumps
+    assert not _match_sets(e0[s0 == 0], exact)
+    e, st, _, rem = oracle.solve(s, g, n_threads=4, tol=tol)
+    assert len(rem) == 0
+    assert (st == 0).sum() == 81
+    assert _match_sets(e[st == 0], exact)
+    # paths outside the pairs keep their first endpoints
+    keep = np.setdiff1d(np.arange(81), np.unique(pairs.ravel()))
+    assert np.array_equal(e[keep], e0[keep])
+
+
+def test_find_duplicates_reports_exactly_the_planted_pairs(oracle_lib):
+    """Near-copies planted at relative distance 3e-7 (a duplicate at the
+    1e-6 test) and 5e-6 (not one), among well separated random points; paths
+    that did not converge are ignored."""
+    rng = np.random.default_rng(5)
+    n, P = 4, 600
+    x = (rng.standard_normal((P, n)) + 1j * rng.standard_normal((P, n))) * 3
+    st = np.zeros(P, np.int32)
+    st[::9] = 2
+    planted = set()
+    for k in range(0, P // 2, 17):  # sources and copies disjoint: no chains
+        j = k + P // 2
+        close = k % 2 == 1
+        x[j] = x[k] * (1 + (3e-7 if close else 5e-6))
+        if close and st[j] == 0 and st[k] == 0:
+            planted.add((min(j, k), max(j, k)))
+    got = {tuple(int(v) for v in p) for p in oracle.find_duplicates(x, st)}
+    assert got == planted and len(planted) >= 5
+
+
+def test_gamma_invariance_cyclic8(oracle_lib):
+    """The cyclic-8 workload (40,320 paths) with its gamma and with another:
+    the same number of finite endpoints, matched one to one within 1e-8."""
+    import sys
+    sys.path.insert(0, HERE)
+    from parity import match_sets
+    wl = W.cyclic8()
+    s, g = wl.systems[0], complex(wl.gammas[0])
+    nt = os.cpu_count() or 1
+    e1, s1, _ = oracle.track_paths(s, g, n_paths=s.bezout(), n_threads=nt)
+    e2, s2, _ = oracle.track_paths(s, np.exp(2j * np.pi * 0.377), n_paths=s.bezout(), n_threads=nt)
+    c1, c2 = e1[s1 == 0], e2[s2 == 0]
+    assert len(c1) == len(c2)
+    assert match_sets(c1, c2)
