@@ -120,6 +120,8 @@ typedef struct {
 
 typedef struct {
   double kernel_ms;   /* device time of the tracking kernels (HIP events)     */
+  double endgame_ms;  /* device time of the end game after them (HIP events)  */
+  double post_ms;     /* host wall time of a solve's duplicate post-pass      */
   double total_ms;    /* host wall time of the whole call                     */
   int64_t launches;   /* tracking kernel launches                             */
   int32_t paths_per_wave; /* paths one wavefront holds at a time          */
@@ -245,6 +247,29 @@ int hp_track_batch(hp_context *ctx, const hp_system *fs, int32_t n_systems,
  * pairs to pairs[2k], pairs[2k+1]; returns the number of pairs found. */
 int64_t hp_find_duplicates(int32_t n, int64_t n_paths, const hp_c64 *endpoints,
                            const int32_t *status, double rel, int64_t *pairs, int64_t max_pairs);
+
+/* Device-memory duplicate scan, the same pairs as hp_find_duplicates (any
+ * order): endpoints [n_paths*n] and status [n_paths] are device arrays (as
+ * hp_plan_track_device writes them); up to max_pairs pairs go to the device
+ * array pairs[2*max_pairs] (NULL if max_pairs is 0); *n_pairs (host) receives
+ * the number of pairs found, which may exceed max_pairs.  The converged
+ * endpoints are projected and sorted on the device (workspace owned by ctx,
+ * grown on demand); the call waits for `stream` (NULL: the context's) to
+ * read two counts back. */
+int hp_find_duplicates_device(hp_context *ctx, int32_t n, int64_t n_paths, const hp_c64 *endpoints,
+                              const int32_t *status, double rel, int64_t *pairs, int64_t max_pairs,
+                              int64_t *n_pairs, void *stream);
+
+/* The solve of the plan's system with device outputs: every total-degree
+ * path (HP_BATCHED, end game included) into endpoints [P*n], status [P] and
+ * stats [P] (nullable), P = hp_path_count; then the duplicate post-pass of
+ * hp_solve on the device: pairs at 1e-6 relative (*pairs_found), both paths
+ * of each tracked once more with h_max = min(h_max, 0.01) and tol_corr =
+ * min(tol_corr, 1e-10) and written back in place, and the pairs left
+ * counted (*pairs_left; both host pointers, nullable).  Returns when the
+ * outputs are complete on `stream` (NULL: the context's). */
+int hp_plan_solve_device(hp_plan *plan, hp_c64 *endpoints, int32_t *status, hp_path_stats *stats,
+                         int64_t *pairs_found, int64_t *pairs_left, void *stream);
 
 /* Tracks all paths of f (HP_BATCHED), then re-tracks both paths of every
  * duplicate pair once with h_max = min(h_max, 0.01) and tol_corr =

@@ -47,6 +47,13 @@ class _SysView:
                           self.coeff.ctypes.data, self.exps.ctypes.data)
 
 
+def _stream(stream):
+    """HIP stream handle of a torch stream (or an int), None for the default."""
+    if stream is None:
+        return None
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
 def _c64(z):
     z = complex(z)
     return HpC64(z.real, z.imag)
@@ -206,6 +213,19 @@ class Context:
     def plan(self, system, gamma, tol=None, tune=False):
         return Plan(self, system, gamma, tol, tune)
 
+    def find_duplicates_device(self, endpoints, status, rel=1e-6, max_pairs=1 << 16, stream=None):
+        """Duplicate scan of device tensors (endpoints float64 [P, n, 2] or
+        complex128 [P, n], status int32 [P]).  Returns (pairs int64 device
+        tensor [min(found, max_pairs), 2], number found)."""
+        import torch
+        P, n = int(status.shape[0]), int(endpoints.shape[1])
+        pairs = torch.zeros((max(1, max_pairs), 2), dtype=torch.int64, device=status.device)
+        found = ctypes.c_int64(0)
+        check(self._L.hp_find_duplicates_device(self.handle, n, P, _ptr(endpoints), _ptr(status),
+                                                float(rel), _ptr(pairs), int(max_pairs),
+                                                ctypes.byref(found), _stream(stream)))
+        return pairs[: min(found.value, max_pairs)], int(found.value)
+
 
 class Plan:
     """A system resident on the device; tracks paths into torch tensors."""
@@ -250,11 +270,18 @@ class Plan:
                      mode="batched", stream=None):
         """Tracks into device tensors.  ids: optional int64 device tensor."""
         P = int(n_paths if n_paths is not None else status.shape[0])
-        sp = None
-        if stream is not None:
-            sp = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
         check(self._L.hp_plan_track_device(self.handle, _ptr(ids), P, _ptr(endpoints),
-                                           _ptr(status), _ptr(stats), _MODES[mode], sp))
+                                           _ptr(status), _ptr(stats), _MODES[mode],
+                                           _stream(stream)))
+
+    def solve_device(self, endpoints, status, stats=None, stream=None):
+        """Every path, then the duplicate post-pass, into device tensors
+        (hp_plan_solve_device).  Returns (pairs found, pairs left)."""
+        found, left = ctypes.c_int64(0), ctypes.c_int64(0)
+        check(self._L.hp_plan_solve_device(self.handle, _ptr(endpoints), _ptr(status), _ptr(stats),
+                                           ctypes.byref(found), ctypes.byref(left),
+                                           _stream(stream)))
+        return int(found.value), int(left.value)
 
     @staticmethod
     def stats_to_numpy(stats_tensor):

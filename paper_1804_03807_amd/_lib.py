@@ -25,6 +25,7 @@ EXPORTED = [
     "hp_plan_set_variant", "hp_plan_track_device", "hp_batch_layout", "hp_track_batch",
     "hp_find_duplicates", "hp_solve", "hp_server_create", "hp_server_submit", "hp_server_poll",
     "hp_server_wait", "hp_server_peak_bytes", "hp_server_destroy", "hp_spec_compile",
+    "hp_find_duplicates_device", "hp_plan_solve_device",
 ]
 
 
@@ -46,7 +47,8 @@ class HpTolerances(ctypes.Structure):
 
 
 class HpTiming(ctypes.Structure):
-    _fields_ = [("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+    _fields_ = [("kernel_ms", ctypes.c_double), ("endgame_ms", ctypes.c_double),
+                ("post_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("launches", ctypes.c_int64), ("paths_per_wave", ctypes.c_int32),
                 ("max_n", ctypes.c_int32), ("groups", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
@@ -104,6 +106,9 @@ def load():
             "hp_track_batch": (ctypes.c_int, [vp, vp, i32, vp, P(HpTolerances), vp, vp, vp]),
             "hp_find_duplicates": (i64, [i32, i64, vp, vp, ctypes.c_double, vp, i64]),
             "hp_solve": (ctypes.c_int, [vp, P(HpSystem), c64, P(HpTolerances), vp, vp, vp, vp]),
+            "hp_find_duplicates_device": (ctypes.c_int, [vp, i32, i64, vp, vp, ctypes.c_double,
+                                                         vp, i64, P(i64), vp]),
+            "hp_plan_solve_device": (ctypes.c_int, [vp, vp, vp, vp, P(i64), P(i64), vp]),
             "hp_server_create": (ctypes.c_int, [vp, ctypes.c_size_t, P(vp)]),
             "hp_server_submit": (ctypes.c_int, [vp, P(HpSystem), c64, P(HpTolerances), P(i64)]),
             "hp_server_poll": (ctypes.c_int, [vp, i64, P(i32)]),

@@ -559,10 +559,34 @@ void tune_store(const std::string &key, int nmax) {
 // Context
 // ---------------------------------------------------------------------------
 
+// Workspace of the device duplicate scan (grown on demand).
+struct DupWork {
+  DevBuf keys, ids, keys_sorted, ids_sorted, temp, counts, pairs;
+  long long cap = 0, max_pairs = 0;
+  size_t temp_bytes = 0;
+  int reserve(long long want_cap, long long want_pairs) {
+    int rc;
+    if (want_cap > cap) {
+      cap = std::max<long long>(want_cap, 1 << 12);
+      temp_bytes = hp_dup_sort_temp_bytes(cap);
+      if ((rc = keys.alloc(cap * sizeof(double))) || (rc = ids.alloc(cap * sizeof(long long))) ||
+          (rc = keys_sorted.alloc(cap * sizeof(double))) ||
+          (rc = ids_sorted.alloc(cap * sizeof(long long))) || (rc = temp.alloc(temp_bytes)))
+        return rc;
+    }
+    if (want_pairs > max_pairs) {
+      max_pairs = std::max<long long>(want_pairs, 1 << 12);
+      if ((rc = pairs.alloc(2 * max_pairs * sizeof(long long)))) return rc;
+    }
+    return counts.alloc(2 * sizeof(unsigned long long));
+  }
+};
+
 struct hp_context {
   int device = 0;
   hipStream_t stream = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evm = nullptr;  // evm: tracking kernel done
+  DupWork dup;
   hp_timing last{};
   int cus = 0;
   size_t max_lds = 0;
@@ -582,6 +606,7 @@ void context_release(hp_context *ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->evm) (void)hipEventDestroy(ctx->evm);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -658,6 +683,7 @@ int hp_context_create(int device, hp_context **out) {
   HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
   HIP_TRY(hipEventCreate(&c->ev0));
   HIP_TRY(hipEventCreate(&c->ev1));
+  HIP_TRY(hipEventCreate(&c->evm));
   *out = c.release();
   return HP_OK;
 }
@@ -770,9 +796,12 @@ int launch_endgame(const DevTables &dev, const Packed &P, const KArgs &a, int64_
 int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv &k,
                       const hp_tolerances &tol, int64_t total_paths, hp_c64 *endpoints,
                       int32_t *status, hp_path_stats *stats, hipStream_t s, int *groups_out,
-                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
-  if (!e0) e0 = ctx->ev0;
-  if (!e1) e1 = ctx->ev1;
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, hipEvent_t em = nullptr) {
+  if (!e0) {  // the context's events: e0 .. em the tracking kernel, em .. e1 the end game
+    e0 = ctx->ev0;
+    e1 = ctx->ev1;
+    em = ctx->evm;
+  }
   if (P.nl > k.nmax || (k.lanes && P.nmin != k.nmax) ||
       (k.spec && (P.nl != k.nmax || P.nmin != k.nmax || !k.sm)) || (k.dense && !dense_fits(k, P)))
     return fail(HP_E_INVALID_ARG, "kernel variant does not match the systems' n");
@@ -814,6 +843,7 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
   } else {
     HIP_TRY((hipError_t)hp_launch_persistent(k.nmax, P.general, a, (int)groups, lds, s));
   }
+  if (em) HIP_TRY(hipEventRecord(em, s));
   if ((rc = launch_endgame(dev, P, a, total_paths, s))) return rc;
   HIP_TRY(hipEventRecord(e1, s));
   if (groups_out) *groups_out = (int)groups;
@@ -935,6 +965,7 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
     HIP_TRY(hipStreamSynchronize(s));
     ++launches;
   }
+  HIP_TRY(hipEventRecord(ctx->evm, s));
   if (active == 0 && (rc = launch_endgame(plan->dev, plan->P, a, n_paths, s))) return rc;
   HIP_TRY(hipEventRecord(ctx->ev1, s));
   ctx->last.launches = launches;
@@ -1125,9 +1156,11 @@ int hp_plan_track_device(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_
     ctx->last.groups = groups;
   }
   HIP_TRY(hipEventSynchronize(ctx->ev1));
-  float ms = 0.f;
-  HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  float ms = 0.f, eg = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->evm));
+  HIP_TRY(hipEventElapsedTime(&eg, ctx->evm, ctx->ev1));
   ctx->last.kernel_ms = ms;
+  ctx->last.endgame_ms = eg;
   ctx->last.total_ms = now_ms() - t0;
   return HP_OK;
 }
@@ -1217,8 +1250,10 @@ int hp_track_batch(hp_context *ctx, const hp_system *fs, int32_t n_systems, cons
                               ctx->stream, &groups)))
     return rc;
   HIP_TRY(hipEventSynchronize(ctx->ev1));
-  float ms = 0.f;
-  HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  float ms = 0.f, eg = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->evm));
+  HIP_TRY(hipEventElapsedTime(&eg, ctx->evm, ctx->ev1));
+  ctx->last.endgame_ms = eg;
   HIP_TRY(hipMemcpy(endpoints, e.p, (size_t)xo[n_systems] * sizeof(hp_c64), hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(status, st.p, (size_t)total * sizeof(int32_t), hipMemcpyDeviceToHost));
   if (stats)
@@ -1293,6 +1328,148 @@ int64_t hp_find_duplicates(int32_t n, int64_t n_paths, const hp_c64 *x, const in
   return count;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Projection weights of the duplicate scans (host and device): uniform in
+// [-1, 1] from a fixed seed, scaled to sum |u_j| + |v_j| = 1, so that
+// |proj(a) - proj(b)| <= ||a - b||_inf.
+void dup_weights(int n, double *w) {
+  std::mt19937_64 rng(0x9e3779b97f4a7c15ULL);
+  std::uniform_real_distribution<double> U(-1.0, 1.0);
+  double sum = 0.0;
+  for (int j = 0; j < 2 * n; ++j) {
+    w[j] = U(rng);
+    sum += std::fabs(w[j]);
+  }
+  for (int j = 0; j < 2 * n; ++j) w[j] /= sum;
+}
+
+// The device duplicate scan into the context's workspace: *found = pairs
+// found; the first min(found, max_pairs) pairs are at W.pairs (device).
+// Waits for stream s (two counts read back).
+int dup_scan(hp_context *ctx, int n, int64_t n_paths, const hp_c64 *e, const int32_t *st,
+             double rel, int64_t want_pairs, int64_t *found, hipStream_t s) {
+  DupWork &W = ctx->dup;
+  int rc;
+  if ((rc = W.reserve(1, want_pairs))) return rc;
+  hp::DupArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.n_paths = n_paths;
+  a.endpoints = (const double2 *)e;
+  a.status = st;
+  a.rel = rel;
+  dup_weights(n, a.w);
+  unsigned long long cnt[2] = {0, 0};
+  for (int pass = 0; pass < 2; ++pass) {
+    a.keys = W.keys.as<double>();
+    a.ids = W.ids.as<long long>();
+    a.keys_sorted = W.keys_sorted.as<double>();
+    a.ids_sorted = W.ids_sorted.as<long long>();
+    a.cap = W.cap;
+    a.count = W.counts.as<unsigned long long>();
+    a.pair_count = a.count + 1;
+    a.temp = W.temp.p;
+    a.temp_bytes = W.temp_bytes;
+    HIP_TRY(hipMemsetAsync(W.counts.p, 0, 2 * sizeof(unsigned long long), s));
+    HIP_TRY((hipError_t)hp_launch_dup_project(a, s));
+    HIP_TRY(hipMemcpyAsync(cnt, W.counts.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if ((long long)cnt[0] <= W.cap) break;
+    if ((rc = W.reserve((long long)cnt[0], want_pairs))) return rc;  // more converged paths than room
+  }
+  const long long m = (long long)cnt[0];
+  a.pairs = W.pairs.as<long long>();
+  a.max_pairs = W.max_pairs;
+  HIP_TRY((hipError_t)hp_launch_dup_sort(a, m, s));
+  HIP_TRY((hipError_t)hp_launch_dup_scan(a, m, s));
+  HIP_TRY(hipMemcpyAsync(&cnt[1], a.pair_count, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *found = (int64_t)cnt[1];
+  return HP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hp_find_duplicates_device(hp_context *ctx, int32_t n, int64_t n_paths, const hp_c64 *endpoints,
+                              const int32_t *status, double rel, int64_t *pairs, int64_t max_pairs,
+                              int64_t *n_pairs, void *stream) {
+  if (!ctx || !n_pairs) return fail(HP_E_INVALID_ARG, "NULL argument");
+  if (n < 1 || n > HP_MAX_N || n_paths < 0 || max_pairs < 0 || !(rel >= 0.0) ||
+      (n_paths > 0 && (!endpoints || !status)) || (max_pairs > 0 && !pairs))
+    return fail(HP_E_INVALID_ARG, "bad arguments");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+  int64_t found = 0;
+  int rc = dup_scan(ctx, n, n_paths, endpoints, status, rel, max_pairs, &found, s);
+  if (rc) return rc;
+  const int64_t k = std::min(found, max_pairs);
+  if (k > 0)
+    HIP_TRY(hipMemcpyAsync(pairs, ctx->dup.pairs.p, (size_t)k * 2 * sizeof(int64_t),
+                           hipMemcpyDeviceToDevice, s));
+  *n_pairs = found;
+  return HP_OK;
+}
+
+int hp_plan_solve_device(hp_plan *plan, hp_c64 *endpoints, int32_t *status, hp_path_stats *stats,
+                         int64_t *pairs_found, int64_t *pairs_left, void *stream) {
+  if (!plan || !endpoints || !status) return fail(HP_E_INVALID_ARG, "NULL argument");
+  if (plan->P.general) return fail(HP_E_INVALID_ARG, "a solve tracks the total-degree start system");
+  hp_context *ctx = plan->ctx;
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+  const double t0 = now_ms();
+  const int n = plan->info.n;
+  const int64_t P = plan->info.paths;
+  int rc = hp_plan_track_device(plan, nullptr, P, endpoints, status, stats, HP_BATCHED, s);
+  if (rc) return rc;
+  const hp_timing track = ctx->last;
+  const double tp = now_ms();
+  constexpr double kRel = 1e-6;
+  int64_t found = 0;
+  if ((rc = dup_scan(ctx, n, P, endpoints, status, kRel, 1 << 16, &found, s))) return rc;
+  if (found > ctx->dup.max_pairs &&
+      (rc = dup_scan(ctx, n, P, endpoints, status, kRel, found, &found, s)))
+    return rc;
+  int64_t left = found;
+  if (found > 0) {
+    // both paths of every pair, each once, tracked again with tighter steps
+    std::vector<int64_t> pr(2 * found);
+    HIP_TRY(hipMemcpy(pr.data(), ctx->dup.pairs.p, pr.size() * sizeof(int64_t),
+                      hipMemcpyDeviceToHost));
+    std::sort(pr.begin(), pr.end());
+    pr.erase(std::unique(pr.begin(), pr.end()), pr.end());
+    const int64_t m = (int64_t)pr.size();
+    DevBuf dids, e2, st2, sts2;
+    if ((rc = dids.alloc(m * sizeof(int64_t))) || (rc = e2.alloc((size_t)m * n * sizeof(hp_c64))) ||
+        (rc = st2.alloc((size_t)m * sizeof(int32_t))) ||
+        (rc = sts2.alloc((size_t)m * sizeof(hp_path_stats))))
+      return rc;
+    HIP_TRY(hipMemcpyAsync(dids.p, pr.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    const hp_tolerances keep = plan->tol;
+    plan->tol.h_max = std::min(keep.h_max, 0.01);
+    plan->tol.tol_corr = std::min(keep.tol_corr, 1e-10);
+    rc = hp_plan_track_device(plan, dids.as<int64_t>(), m, e2.as<hp_c64>(), st2.as<int32_t>(),
+                              sts2.as<hp_path_stats>(), HP_BATCHED, s);
+    plan->tol = keep;
+    if (rc) return rc;
+    HIP_TRY((hipError_t)hp_launch_scatter(dids.as<long long>(), m, n, e2.as<double2>(),
+                                          st2.as<int32_t>(), sts2.as<hp_path_stats>(),
+                                          (double2 *)endpoints, status, stats, s));
+    if ((rc = dup_scan(ctx, n, P, endpoints, status, kRel, 0, &left, s))) return rc;
+  }
+  if (pairs_found) *pairs_found = found;
+  if (pairs_left) *pairs_left = left;
+  ctx->last = track;
+  ctx->last.post_ms = now_ms() - tp;
+  ctx->last.total_ms = now_ms() - t0;
+  return HP_OK;
+}
+
 int hp_solve(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
              hp_c64 *endpoints, int32_t *status, hp_path_stats *stats, int64_t *remaining_pairs) {
   if (!ctx || !endpoints || !status) return fail(HP_E_INVALID_ARG, "NULL argument");
@@ -1307,51 +1484,17 @@ int hp_solve(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_toleran
   if ((rc = e.alloc((size_t)P * n * sizeof(hp_c64)))) return rc;
   if ((rc = st.alloc((size_t)P * sizeof(int32_t)))) return rc;
   if ((rc = sts.alloc((size_t)P * sizeof(hp_path_stats)))) return rc;
-  rc = hp_plan_track_device(plan, nullptr, P, e.as<hp_c64>(), st.as<int32_t>(),
-                            sts.as<hp_path_stats>(), HP_BATCHED, nullptr);
+  int64_t left = 0;
+  rc = hp_plan_solve_device(plan, e.as<hp_c64>(), st.as<int32_t>(), sts.as<hp_path_stats>(),
+                            nullptr, &left, nullptr);
   if (rc) return rc;
-  const double kms = ctx->last.kernel_ms;
+  const hp_timing keep = ctx->last;
   HIP_TRY(hipMemcpy(endpoints, e.p, (size_t)P * n * sizeof(hp_c64), hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(status, st.p, (size_t)P * sizeof(int32_t), hipMemcpyDeviceToHost));
-  std::vector<hp_path_stats> hst(P);
-  HIP_TRY(hipMemcpy(hst.data(), sts.p, (size_t)P * sizeof(hp_path_stats), hipMemcpyDeviceToHost));
-  int64_t npairs = hp_find_duplicates(n, P, endpoints, status, 1e-6, nullptr, 0);
-  if (npairs > 0) {
-    std::vector<int64_t> pairs(2 * npairs);
-    hp_find_duplicates(n, P, endpoints, status, 1e-6, pairs.data(), npairs);
-    std::sort(pairs.begin(), pairs.end());
-    pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
-    const int64_t m = (int64_t)pairs.size();
-    hp_tolerances t2 = plan->tol;
-    t2.h_max = std::min(t2.h_max, 0.01);
-    t2.tol_corr = std::min(t2.tol_corr, 1e-10);
-    plan->tol = t2;
-    DevBuf dids, e2, st2, sts2;
-    if ((rc = dids.alloc(m * sizeof(int64_t)))) return rc;
-    if ((rc = e2.alloc((size_t)m * n * sizeof(hp_c64)))) return rc;
-    if ((rc = st2.alloc((size_t)m * sizeof(int32_t)))) return rc;
-    if ((rc = sts2.alloc((size_t)m * sizeof(hp_path_stats)))) return rc;
-    HIP_TRY(hipMemcpy(dids.p, pairs.data(), m * sizeof(int64_t), hipMemcpyHostToDevice));
-    rc = hp_plan_track_device(plan, dids.as<int64_t>(), m, e2.as<hp_c64>(), st2.as<int32_t>(),
-                              sts2.as<hp_path_stats>(), HP_BATCHED, nullptr);
-    if (rc) return rc;
-    std::vector<hp_c64> he(m * n);
-    std::vector<int32_t> hs(m);
-    std::vector<hp_path_stats> hss(m);
-    HIP_TRY(hipMemcpy(he.data(), e2.p, (size_t)m * n * sizeof(hp_c64), hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(hs.data(), st2.p, (size_t)m * sizeof(int32_t), hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(hss.data(), sts2.p, (size_t)m * sizeof(hp_path_stats), hipMemcpyDeviceToHost));
-    for (int64_t k = 0; k < m; ++k) {
-      const int64_t p = pairs[k];
-      std::memcpy(&endpoints[p * n], &he[k * n], n * sizeof(hp_c64));
-      status[p] = hs[k];
-      hst[p] = hss[k];
-    }
-    npairs = hp_find_duplicates(n, P, endpoints, status, 1e-6, nullptr, 0);
-  }
-  if (stats) std::memcpy(stats, hst.data(), (size_t)P * sizeof(hp_path_stats));
-  if (remaining_pairs) *remaining_pairs = npairs;
-  ctx->last.kernel_ms = kms;
+  if (stats)
+    HIP_TRY(hipMemcpy(stats, sts.p, (size_t)P * sizeof(hp_path_stats), hipMemcpyDeviceToHost));
+  if (remaining_pairs) *remaining_pairs = left;
+  ctx->last = keep;
   ctx->last.total_ms = now_ms() - t0;
   return HP_OK;
 }

@@ -113,6 +113,27 @@ struct KArgs {
 
 enum Mode : int32_t { M_IDLE = 0, M_TRACK = 1, M_FINAL = 2 };
 
+// Arguments of the duplicate-endpoint scan (dedup.hip).
+struct DupArgs {
+  int32_t n;
+  long long n_paths;
+  const double2 *endpoints;  // [n_paths][n]
+  const int32_t *status;     // [n_paths]
+  double rel;
+  double w[2 * HP_MAX_N];    // projection weights (re, im) per unknown, sum |w| = 1
+  double *keys;              // [cap] projections of the converged paths
+  long long *ids;            // [cap] their path indices
+  double *keys_sorted;       // [cap]
+  long long *ids_sorted;     // [cap]
+  long long cap;
+  unsigned long long *count;       // converged paths seen (may exceed cap)
+  long long *pairs;                // [2 max_pairs]
+  long long max_pairs;
+  unsigned long long *pair_count;  // pairs found (may exceed max_pairs)
+  void *temp;                      // radix sort workspace
+  size_t temp_bytes;
+};
+
 // Kernel variants compiled into the library: the register arrays hold up to
 // n_max unknowns; a system of n unknowns runs on the smallest n_max >= n.
 constexpr int kNmaxVariants[] = {4, 8, 10, 12};
@@ -176,8 +197,8 @@ inline size_t lanes_lds_bytes(int n, int pw, int emax) {
 
 }  // namespace hp
 
-// Kernel launchers (tracker.hip, lanes.hip, dense.hip, dense11.hip, endgame.hip,
-// dense12.hip).  Return a hipError_t
+// Kernel launchers (tracker.hip, lanes.hip, dense.hip, dense11.hip, dense12.hip,
+// endgame.hip, dedup.hip).  Return a hipError_t
 // value.
 extern "C++" {
 // general: the systems use a general start system or explicit start points
@@ -197,6 +218,16 @@ int hp_launch_dense11(const hp::KArgs &a, int groups, void *stream);
 int hp_dense11_per_cu(int *out);
 int hp_launch_dense12(const hp::KArgs &a, int groups, void *stream);
 int hp_dense12_per_cu(int *out);
+// Duplicate scan (dedup.hip): projection and compaction of the converged
+// endpoints, radix sort of m keys, window scan over the m sorted keys; and
+// the scatter of re-tracked results into the full outputs.
+size_t hp_dup_sort_temp_bytes(long long cap);
+int hp_launch_dup_project(const hp::DupArgs &a, void *stream);
+int hp_launch_dup_sort(const hp::DupArgs &a, long long m, void *stream);
+int hp_launch_dup_scan(const hp::DupArgs &a, long long m, void *stream);
+int hp_launch_scatter(const long long *ids, long long m, int n, const double2 *e_src,
+                      const int32_t *s_src, const hp_path_stats *st_src, double2 *e_dst,
+                      int32_t *s_dst, hp_path_stats *st_dst, void *stream);
 // End game of the paths of systems with n unknowns: blk[b] = (system, first
 // queue index) of block b (64 paths each), or blk == nullptr for one system
 // (system 0, block b from queue index 64 b).

@@ -276,3 +276,30 @@ def test_solve_post_pass_against_oracle(ctx):
         hit.add(j)
     log(f"  after the post-pass: {int((s1 == 0).sum())} converged, {len(hit)} distinct roots")
     assert len(hit) == int((s1 == 0).sum()) - rem
+
+
+def test_device_duplicate_scan_matches_host(ctx):
+    """hp_find_duplicates_device reports the same pairs as the host scan
+    (and the oracle's O(N^2) scan) on planted near-copies."""
+    import torch
+    import paper_1804_03807_amd as hp
+    rng = np.random.default_rng(5)
+    n, P = 6, 20000
+    x = (rng.standard_normal((P, n)) + 1j * rng.standard_normal((P, n))) * 3
+    st = np.zeros(P, np.int32)
+    st[::9] = 2
+    for k in range(0, P // 2, 97):
+        x[k + P // 2] = x[k] * (1 + (3e-7 if k % 2 else 5e-6))
+    ref = {tuple(int(v) for v in p) for p in hp.find_duplicates(x, st)}
+    e_d = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    s_d = torch.from_numpy(st).cuda()
+    pairs, found = ctx.find_duplicates_device(e_d, s_d, 1e-6, max_pairs=1 << 12)
+    got = {tuple(int(v) for v in p) for p in pairs.cpu().numpy()}
+    log(f"  pairs host {len(ref)} device {found}")
+    assert found == len(ref) == len(got) and got == ref and len(ref) > 10
+    sub = np.arange(0, P, 7)  # the oracle's scan on a subset
+    assert {tuple(int(v) for v in p) for p in oracle.find_duplicates(x[sub], st[sub])} == \
+        {tuple(int(v) for v in p) for p in hp.find_duplicates(x[sub], st[sub])}
+    # max_pairs smaller than the number found: the count is still exact
+    pairs2, found2 = ctx.find_duplicates_device(e_d, s_d, 1e-6, max_pairs=3)
+    assert found2 == found and len(pairs2) == 3
