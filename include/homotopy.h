@@ -260,6 +260,19 @@ int hp_find_duplicates_device(hp_context *ctx, int32_t n, int64_t n_paths, const
                               const int32_t *status, double rel, int64_t *pairs, int64_t max_pairs,
                               int64_t *n_pairs, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the scan of
+ * hp_find_duplicates_device, same arguments and results, in a workspace the
+ * library holds per GPU for the life of the process (a fixed array of about
+ * 36 MiB on each GPU it runs on) instead of memory it allocates; the call
+ * allocates nothing.  At most 524,288 converged endpoints per call
+ * (HP_E_BUDGET beyond).  Every call on a GPU uses that GPU's one workspace:
+ * calls that overlap on one GPU race, so callers serialise them. */
+int hp_find_duplicates_device_static(hp_context *ctx, int32_t n, int64_t n_paths,
+                                     const hp_c64 *endpoints, const int32_t *status, double rel,
+                                     int64_t *pairs, int64_t max_pairs, int64_t *n_pairs,
+                                     void *stream);
+
 /* The solve of the plan's system with device outputs: every total-degree
  * path (HP_BATCHED, end game included) into endpoints [P*n], status [P] and
  * stats [P] (nullable), P = hp_path_count; then the duplicate post-pass of

@@ -226,6 +226,18 @@ class Context:
                                                 ctypes.byref(found), _stream(stream)))
         return pairs[: min(found.value, max_pairs)], int(found.value)
 
+    def find_duplicates_device_static(self, endpoints, status, pairs, rel=1e-6, stream=None):
+        """The same scan in the library's fixed per-GPU workspace (no device
+        allocation; hp_find_duplicates_device_static) into the caller's int64
+        device tensor pairs [max_pairs, 2]; returns the number found."""
+        P, n = int(status.shape[0]), int(endpoints.shape[1])
+        found = ctypes.c_int64(0)
+        check(self._L.hp_find_duplicates_device_static(self.handle, n, P, _ptr(endpoints),
+                                                       _ptr(status), float(rel), _ptr(pairs),
+                                                       int(pairs.shape[0]), ctypes.byref(found),
+                                                       _stream(stream)))
+        return int(found.value)
+
 
 class Plan:
     """A system resident on the device; tracks paths into torch tensors."""

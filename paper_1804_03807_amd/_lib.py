@@ -25,7 +25,7 @@ EXPORTED = [
     "hp_plan_set_variant", "hp_plan_track_device", "hp_batch_layout", "hp_track_batch",
     "hp_find_duplicates", "hp_solve", "hp_server_create", "hp_server_submit", "hp_server_poll",
     "hp_server_wait", "hp_server_peak_bytes", "hp_server_destroy", "hp_spec_compile",
-    "hp_find_duplicates_device", "hp_plan_solve_device",
+    "hp_find_duplicates_device", "hp_plan_solve_device", "hp_find_duplicates_device_static",
 ]
 
 
@@ -109,6 +109,9 @@ def load():
             "hp_find_duplicates_device": (ctypes.c_int, [vp, i32, i64, vp, vp, ctypes.c_double,
                                                          vp, i64, P(i64), vp]),
             "hp_plan_solve_device": (ctypes.c_int, [vp, vp, vp, vp, P(i64), P(i64), vp]),
+            "hp_find_duplicates_device_static": (ctypes.c_int, [vp, i32, i64, vp, vp,
+                                                                ctypes.c_double, vp, i64, P(i64),
+                                                                vp]),
             "hp_server_create": (ctypes.c_int, [vp, ctypes.c_size_t, P(vp)]),
             "hp_server_submit": (ctypes.c_int, [vp, P(HpSystem), c64, P(HpTolerances), P(i64)]),
             "hp_server_poll": (ctypes.c_int, [vp, i64, P(i32)]),

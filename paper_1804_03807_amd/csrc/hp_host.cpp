@@ -1415,6 +1415,35 @@ int hp_find_duplicates_device(hp_context *ctx, int32_t n, int64_t n_paths, const
   return HP_OK;
 }
 
+int hp_find_duplicates_device_static(hp_context *ctx, int32_t n, int64_t n_paths,
+                                     const hp_c64 *endpoints, const int32_t *status, double rel,
+                                     int64_t *pairs, int64_t max_pairs, int64_t *n_pairs,
+                                     void *stream) {
+  if (!ctx || !n_pairs) return fail(HP_E_INVALID_ARG, "NULL argument");
+  if (n < 1 || n > HP_MAX_N || n_paths < 0 || max_pairs < 0 || !(rel >= 0.0) ||
+      (n_paths > 0 && (!endpoints || !status)) || (max_pairs > 0 && !pairs))
+    return fail(HP_E_INVALID_ARG, "bad arguments");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+  hp::DupArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.n_paths = n_paths;
+  a.endpoints = (const double2 *)endpoints;
+  a.status = status;
+  a.rel = rel;
+  dup_weights(n, a.w);
+  a.pairs = (long long *)pairs;
+  a.max_pairs = max_pairs;
+  long long found = 0;
+  std::string err;
+  const int rc = hp_dup_static_scan(ctx->device, a, &found, err, s);
+  if (rc == -2) return fail(HP_E_BUDGET, err);
+  if (rc) return fail(HP_E_DEVICE, "static duplicate scan: " + err);
+  *n_pairs = found;
+  return HP_OK;
+}
+
 int hp_plan_solve_device(hp_plan *plan, hp_c64 *endpoints, int32_t *status, hp_path_stats *stats,
                          int64_t *pairs_found, int64_t *pairs_left, void *stream) {
   if (!plan || !endpoints || !status) return fail(HP_E_INVALID_ARG, "NULL argument");

@@ -6,6 +6,8 @@
 
 #ifndef __HIPCC_RTC__  // hiprtc declares the HIP device API itself
 #include <hip/hip_runtime.h>
+
+#include <string>
 #endif
 
 #include "homotopy.h"
@@ -198,7 +200,7 @@ inline size_t lanes_lds_bytes(int n, int pw, int emax) {
 }  // namespace hp
 
 // Kernel launchers (tracker.hip, lanes.hip, dense.hip, dense11.hip, dense12.hip,
-// endgame.hip, dedup.hip).  Return a hipError_t
+// endgame.hip, dedup.hip, dedup_static.hip).  Return a hipError_t
 // value.
 extern "C++" {
 // general: the systems use a general start system or explicit start points
@@ -225,6 +227,15 @@ size_t hp_dup_sort_temp_bytes(long long cap);
 int hp_launch_dup_project(const hp::DupArgs &a, void *stream);
 int hp_launch_dup_sort(const hp::DupArgs &a, long long m, void *stream);
 int hp_launch_dup_scan(const hp::DupArgs &a, long long m, void *stream);
+#ifndef __HIPCC_RTC__
+// The duplicate scan in the library's static per-GPU workspace
+// (dedup_static.hip), allocating nothing: 0, -1 (device error, text in err)
+// or -2 (more converged endpoints than the workspace holds).  Pairs go to
+// a.pairs (up to a.max_pairs), their number to *n_pairs.
+long long hp_dup_static_max_converged();
+int hp_dup_static_scan(int device, hp::DupArgs a, long long *n_pairs, std::string &err,
+                       void *stream);
+#endif
 int hp_launch_scatter(const long long *ids, long long m, int n, const double2 *e_src,
                       const int32_t *s_src, const hp_path_stats *st_src, double2 *e_dst,
                       int32_t *s_dst, hp_path_stats *st_dst, void *stream);
