@@ -45,9 +45,17 @@ METRIC = "paths/sec at endpoint residual<=1e-10, batched vs plain; p50/p99 solve
 COUNTER_PROFILE = {
     "workload": "cyclic10",
     "variant": 310,
-    "sources_sha256": {},
-    "fetch_kib": None, "fetch_scale": None, "write_kib": None, "write_scale": None,
-    "fma_f64": None, "mul_f64": None, "add_f64": None,
+    "sources_sha256": {
+        "spec_track.hpp": "bb636574221bdf00805a21bbf4a783b4222c9c83e6ae6b0d1ef22211410816f1",
+        "lane_track.hpp": "d88e396d1469da3c3c901e2aaa6170c2cb2c893162686c6fafd3989921cf3ff4",
+        "hp_device.hpp": "f785014ca74114e45d5b32364f08af0b41660996c35cbf08085ef6fbc53b0a3e",
+        "hp_internal.hpp": "e8034b6ecb25a95b6f5974700c46bb6f261e0e981ce138c2fe7f3e48902fc286",
+        "hp_jit.cpp": "161eb0b1682f3e9c2e6298568b857aa590840c85fd0c98555fde715ce4f31b59",
+        "reg_lu.hpp": "488a287cfdfca4d8c1b616ad7aa2ae6bd41dfae4f8f485f55d55bd2819711eb2",
+    },
+    "fetch_kib": 37142961.6875, "fetch_scale": 262144 / 131088.6875,
+    "write_kib": 1223088794.21875, "write_scale": 262144 / 262144,
+    "fma_f64": 232873573265, "mul_f64": 89306916092, "add_f64": 14735514329,
 }
 COUNTER_SOURCES = ["spec_track.hpp", "lane_track.hpp", "hp_device.hpp", "hp_internal.hpp",
                    "hp_jit.cpp", "reg_lu.hpp"]
