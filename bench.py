@@ -12,7 +12,8 @@ re-tracking of duplicate pairs, all on the device.
 
 Also measured (sub-keys, outside the timed region): cyclic-8 (40,320 paths)
 batched vs plain, the dense n = 5 system (32 paths) batched vs plain, 256 dense
-systems in one launch, and the serving loop on 1,000 requests.
+systems in one launch, coefficient-parameter continuation between two
+cyclic-8 systems (2,560 paths), and the serving loop on 1,000 requests.
 
 Prints one JSON line.
 """
@@ -155,6 +156,33 @@ def batched_vs_plain(ctx, name, steps=3):
             "batched_over_plain": dtp / dt, "kernel_variant": tm["variant"],
             "kernel_ms": float(np.mean(kms)),
             "achieved_tflops": achieved, "frac_of_fp64_peak": achieved / FP64_PEAK_TFLOPS}
+
+
+def continuation_run(ctx):
+    """Coefficient-parameter continuation on the cyclic-8 supports: the 2,560
+    finite roots of one random-coefficient system (the cyclic-8 workload,
+    solved first) moved to those of another system on the same supports."""
+    import torch
+    import paper_1804_03807_amd as hp
+    import workloads as W
+    a, b = W.cyclic8(), W.cyclic_workload(8, 12)
+    sa, sb = a.systems[0], b.systems[0]
+    plan = ctx.plan(sa, complex(a.gammas[0]))
+    e, st, _ = plan.outputs(sa.bezout())
+    plan.solve_device(e, st)
+    torch.cuda.synchronize()
+    start = hp.Plan.endpoints_to_numpy(e)[st.cpu().numpy() == 0]
+    plan.close()
+    gam = complex(np.exp(1.3j))
+    ctx.track_paths(sb, gam, start=start, g=sa)  # warm-up
+    t0 = time.perf_counter()
+    ee, ss, _ = ctx.track_paths(sb, gam, start=start, g=sa)
+    dt = time.perf_counter() - t0
+    tm = ctx.last_timing()
+    return {"paths": int(len(start)), "converged": int((ss == 0).sum()),
+            "kernel_ms": tm["kernel_ms"], "endgame_ms": tm["endgame_ms"],
+            "end_to_end_ms": dt * 1e3, "paths_per_s": len(start) / dt,
+            "kernel_variant": tm["variant"]}
 
 
 def batch_run(ctx, n_systems=256):
@@ -392,6 +420,7 @@ def main():
         out["cyclic8"] = batched_vs_plain(ctx, "cyclic8")
         out["dense5"] = batched_vs_plain(ctx, "dense5", steps=20)
         out["batch256"] = batch_run(ctx)
+        out["continuation_cyclic8"] = continuation_run(ctx)
 
     if args.serving_requests > 0:
         out["serving"] = serving_run(ctx, args.serving_requests,

@@ -230,7 +230,11 @@ int hp_plan_track_device(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_
                          int32_t *status, hp_path_stats *stats, int32_t mode, void *stream);
 
 /* Many systems of different n in one persistent launch (one refill queue per
- * system).  System s owns the paths path_offsets[s] .. path_offsets[s+1]-1
+ * system), the batched form of the work crew: the paper's speedup of
+ * tracking n paths with p workers is bounded by the tail of n mod p paths
+ * (Section 3.2, Theorem 3.2) and, for a sequence of path sets, by one tail
+ * per set (the corollary after it); one launch over all systems leaves one
+ * tail for the whole batch instead of one per system.  System s owns the paths path_offsets[s] .. path_offsets[s+1]-1
  * of the output (path_offsets[0] = 0, path_offsets[s+1] - path_offsets[s] =
  * hp_path_count(&fs[s])); its endpoints start at hp_c64 index x_offsets[s]
  * (x_offsets[s+1] = x_offsets[s] + paths_s * n_s).  Both offset arrays have
@@ -292,7 +296,10 @@ int hp_solve(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_toleran
              hp_c64 *endpoints, int32_t *status, hp_path_stats *stats, int64_t *remaining_pairs);
 
 /* Serving: a request loop with continuous batching (a worker thread with its
- * own stream).  The server allocates an output arena of at most
+ * own stream), in the manner of the paper's pipeline in which tracking of
+ * the paths of one piece of work starts while other pieces are still being
+ * produced (Section 2.2, Figure 1: a producer stage feeding tracking
+ * threads).  The server allocates an output arena of at most
  * hbm_budget_bytes: path slots of HP_MAX_N endpoint coordinates + status +
  * stats (236 B each).  Requests (one system each, all its total-degree
  * paths) are admitted in arrival order while their slot regions fit;  a

@@ -85,3 +85,38 @@ def test_full_256_system_batch_sampled(ctx):
         assert_residuals(s, e, st)
     log(f"converged {n_conv} of {wl.total_paths}; oracle-checked paths {n_checked}")
     assert n_checked >= 20000
+
+
+def test_refill_queue_hands_out_every_path(ctx):
+    """The device refill queue on a workload with far more paths than lanes
+    and very uneven path lengths (cyclic-9: 362,880 paths, most of them to
+    infinity, on 65,536 resident lanes): outputs pre-filled with a sentinel
+    are all written, and every path's result is bitwise the same when the
+    ids are handed out in reverse order (so it does not depend on which lane
+    or refill round took it)."""
+    import torch
+    import paper_1804_03807_amd as hp
+    wl = W.cyclic_workload(9, 42)
+    s, g = wl.systems[0], complex(wl.gammas[0])
+    P = s.bezout()
+    plan = ctx.plan(s, g)
+    e, st, sts = plan.outputs(P)
+    e.fill_(float("nan"))
+    st.fill_(-7)
+    plan.track_device(e, st, sts)
+    ids = torch.arange(P - 1, -1, -1, dtype=torch.int64, device="cuda")
+    e2, st2, sts2 = plan.outputs(P)
+    st2.fill_(-7)
+    plan.track_device(e2, st2, sts2, ids=ids)
+    torch.cuda.synchronize()
+    plan.close()
+    s1, s2 = st.cpu().numpy(), st2.cpu().numpy()[::-1]
+    steps = hp.Plan.stats_to_numpy(sts)["steps"]
+    log(f"  paths {P}, steps per path {steps.min()}..{steps.max()} (mean {steps.mean():.0f}), "
+        f"status counts {np.bincount(s1, minlength=5).tolist()}")
+    assert (s1 >= 0).all() and (s2 >= 0).all()
+    assert np.array_equal(s1, s2)
+    e1 = hp.Plan.endpoints_to_numpy(e)
+    e2n = hp.Plan.endpoints_to_numpy(e2)[::-1]
+    assert np.array_equal(e1, e2n)
+    assert steps.max() > 4 * steps.min()
