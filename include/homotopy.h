@@ -295,6 +295,24 @@ int hp_plan_solve_device(hp_plan *plan, hp_c64 *endpoints, int32_t *status, hp_p
 int hp_solve(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
              hp_c64 *endpoints, int32_t *status, hp_path_stats *stats, int64_t *remaining_pairs);
 
+/* Homotopy membership test (Section 4.1, Example 4.1): whether test points
+ * lie on a positive-dimensional solution set given by witness points.
+ *   e: the embedded system (Section 2.1): its last n_hyper equations are the
+ *      linear hyperplanes that cut the set (degree 1; each may have a
+ *      constant term);
+ *   witness [m*n]: the m witness points (solutions of e on the set);
+ *   tests [n_tests*n]: points to test, in e's unknowns (slack variables 0).
+ * For each test point y the witness points are tracked along
+ * (1 - t) e + t e_y, where e_y is e with the constant of each hyperplane
+ * replaced so that it passes through y (gamma = 1: only those constants
+ * move, c0 to c3); all tests run in one persistent launch.  Outputs (host):
+ * endpoints [n_tests*m*n], status [n_tests*m], member [n_tests] = 1 when a
+ * CONVERGED endpoint of that test satisfies ||x - y||_inf <= rel max(1,
+ * ||y||_inf).  HP_E_INVALID_ARG if a hyperplane equation is not linear. */
+int hp_membership_test(hp_context *ctx, const hp_system *e, int32_t n_hyper, const hp_c64 *witness,
+                       int64_t m, const hp_c64 *tests, int32_t n_tests, const hp_tolerances *tol,
+                       double rel, hp_c64 *endpoints, int32_t *status, int32_t *member);
+
 /* Serving: a request loop with continuous batching (a worker thread with its
  * own stream), in the manner of the paper's pipeline in which tracking of
  * the paths of one piece of work starts while other pieces are still being

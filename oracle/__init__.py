@@ -249,3 +249,58 @@ def solve(f, gamma, n_threads=1, path_ids=None, tol=None, retrack=True):
         ends[idx], status[idx], stats[idx] = e2, s2, st2
         pairs = find_duplicates(ends, status)
     return ends, status, stats, pairs
+
+
+def moved_hyperplanes(e_sys, n_hyper, y):
+    """The target system of a homotopy membership test (Section 4.1,
+    Example 4.1): e_sys with the constant term of each of its last n_hyper
+    equations (linear: the hyperplanes of the embedding) replaced so that the
+    equation vanishes at the test point y, c3 = -(sum of the other terms at y).
+    A hyperplane without a constant term gets one."""
+    import dataclasses
+    y = np.asarray(y, np.complex128)
+    n = e_sys.n
+    eq_ptr, coeff, exps = [0], [], []
+    for i in range(n):
+        a, b = int(e_sys.eq_ptr[i]), int(e_sys.eq_ptr[i + 1])
+        cs = list(e_sys.coeff[a:b])
+        ex = [np.asarray(e_sys.exps[t]) for t in range(a, b)]
+        if i >= n - n_hyper:
+            if any(int(e.sum()) > 1 for e in ex):
+                raise ValueError("the moved equations must be linear")
+            rest = sum(c * np.prod(y ** e) for c, e in zip(cs, ex) if e.sum() > 0)
+            const = [k for k, e in enumerate(ex) if e.sum() == 0]
+            if const:
+                cs[const[0]] = -rest
+            else:
+                cs.append(-rest)
+                ex.append(np.zeros(n, np.uint8))
+        coeff += cs
+        exps += ex
+        eq_ptr.append(len(coeff))
+    return dataclasses.replace(e_sys, eq_ptr=np.asarray(eq_ptr, np.int32),
+                               coeff=np.asarray(coeff, np.complex128),
+                               exps=np.asarray(exps, np.uint8).reshape(len(coeff), n),
+                               name=f"{e_sys.name}_moved")
+
+
+def membership_test(e_sys, n_hyper, witness, tests, tol: RefTolerances | None = None,
+                    rel=1e-6, n_threads=1):
+    """Homotopy membership test (Section 4.1, Example 4.1): for each test
+    point y, the witness points of a solution set (solutions of the embedded
+    system e_sys on it) are tracked along (1 - t) g + t f, g = e_sys, f = the
+    same system with its hyperplanes moved through y (gamma = 1: only the
+    hyperplane constants move, from c0 to c3).  y lies on the set when an
+    endpoint coincides with it, ||x - y||_inf <= rel max(1, ||y||_inf).
+    Returns (endpoints [T, m, n], status [T, m], member bool [T])."""
+    witness = np.ascontiguousarray(witness, np.complex128).reshape(-1, e_sys.n)
+    tests = np.asarray(tests, np.complex128).reshape(-1, e_sys.n)
+    E, S, M = [], [], []
+    for y in tests:
+        f = moved_hyperplanes(e_sys, n_hyper, y)
+        ends, st, _ = track_paths(f, 1.0, start=witness, g=e_sys, tol=tol, n_threads=n_threads)
+        hit = (st == CONVERGED) & (np.abs(ends - y).max(axis=1) <= rel * max(1.0, np.abs(y).max()))
+        E.append(ends)
+        S.append(st)
+        M.append(bool(hit.any()))
+    return np.asarray(E), np.asarray(S), np.asarray(M)

@@ -210,6 +210,23 @@ class Context:
                                _ptr(ends), _ptr(st), _ptr(sts), ctypes.byref(rem)))
         return ends, st, sts, int(rem.value)
 
+    def membership_test(self, e_sys, n_hyper, witness, tests, tol=None, rel=1e-6):
+        """Homotopy membership test (hp_membership_test): the witness points
+        of e_sys tracked as its last n_hyper hyperplanes move through each test
+        point.  Returns (endpoints [T, m, n], status [T, m], member bool [T])."""
+        v = _SysView(e_sys)
+        w = np.ascontiguousarray(witness, np.complex128).reshape(-1, v.n)
+        y = np.ascontiguousarray(tests, np.complex128).reshape(-1, v.n)
+        T, m = y.shape[0], w.shape[0]
+        ends = np.zeros((T, m, v.n), np.complex128)
+        st = np.full((T, m), -1, np.int32)
+        mem = np.zeros(T, np.int32)
+        tol = tol or default_tolerances()
+        check(self._L.hp_membership_test(self.handle, ctypes.byref(v.c), int(n_hyper), _ptr(w), m,
+                                         _ptr(y), T, ctypes.byref(tol), float(rel), _ptr(ends),
+                                         _ptr(st), _ptr(mem)))
+        return ends, st, mem.astype(bool)
+
     def plan(self, system, gamma, tol=None, tune=False):
         return Plan(self, system, gamma, tol, tune)
 

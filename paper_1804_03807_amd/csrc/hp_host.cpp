@@ -1531,6 +1531,144 @@ int hp_solve(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_toleran
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// Homotopy membership test (Section 4.1, Example 4.1)
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// e with the constant term of each of its last n_hyper equations replaced so
+// that the equation vanishes at y (a hyperplane without a constant term gets
+// one).  The arrays of the result live in the given vectors.
+int moved_system(const hp_system *e, int n_hyper, const hp_c64 *y, std::vector<int32_t> &eq_ptr,
+                 std::vector<hp_c64> &coeff, std::vector<uint8_t> &exps, hp_system &out) {
+  const int n = e->n;
+  eq_ptr.assign(1, 0);
+  coeff.clear();
+  exps.clear();
+  for (int i = 0; i < n; ++i) {
+    const bool hyper = i >= n - n_hyper;
+    double rre = 0.0, rim = 0.0;  // the non-constant terms at y
+    int const_at = -1;
+    for (int t = e->eq_ptr[i]; t < e->eq_ptr[i + 1]; ++t) {
+      int deg = 0, var = -1;
+      for (int j = 0; j < n; ++j) {
+        const int a = e->exps[(size_t)t * n + j];
+        deg += a;
+        if (a) var = j;
+      }
+      if (hyper && deg > 1) return fail(HP_E_INVALID_ARG, "a hyperplane equation is not linear");
+      if (hyper && deg == 1) {
+        const hp_c64 c = e->coeff[t], v = y[var];
+        rre += c.re * v.re - c.im * v.im;
+        rim += c.re * v.im + c.im * v.re;
+      }
+      if (hyper && deg == 0 && const_at < 0) const_at = (int)coeff.size();
+      coeff.push_back(e->coeff[t]);
+      exps.insert(exps.end(), e->exps + (size_t)t * n, e->exps + (size_t)(t + 1) * n);
+    }
+    if (hyper) {
+      if (const_at < 0) {
+        const_at = (int)coeff.size();
+        coeff.push_back(hp_c64{0.0, 0.0});
+        exps.insert(exps.end(), (size_t)n, (uint8_t)0);
+      }
+      coeff[const_at] = hp_c64{-rre, -rim};
+    }
+    eq_ptr.push_back((int32_t)coeff.size());
+  }
+  out = hp_system{n, (int32_t)coeff.size(), eq_ptr.data(), coeff.data(), exps.data()};
+  return HP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hp_membership_test(hp_context *ctx, const hp_system *e, int32_t n_hyper, const hp_c64 *witness,
+                       int64_t m, const hp_c64 *tests, int32_t n_tests, const hp_tolerances *tol,
+                       double rel, hp_c64 *endpoints, int32_t *status, int32_t *member) {
+  if (!ctx || !e || !witness || !tests || !endpoints || !status || !member)
+    return fail(HP_E_INVALID_ARG, "NULL argument");
+  SysInfo info;
+  int rc = check_system(e, info);
+  if (rc) return rc;
+  if (n_hyper < 1 || n_hyper >= e->n || m < 1 || n_tests < 1 || !(rel >= 0.0))
+    return fail(HP_E_INVALID_ARG, "bad membership-test sizes");
+  if ((rc = check_tol(tol))) return rc;
+  hp_tolerances T;
+  if (tol) T = *tol;
+  else hp_default_tolerances(&T);
+  const int n = e->n;
+  for (int64_t k = 0; k < m * n; ++k)
+    if (!std::isfinite(witness[k].re) || !std::isfinite(witness[k].im))
+      return fail(HP_E_INVALID_ARG, "witness points must be finite");
+  const double t0 = now_ms();
+  HIP_TRY(hipSetDevice(ctx->device));
+  DevBuf dstart;
+  if ((rc = dstart.alloc((size_t)m * n * sizeof(hp_c64)))) return rc;
+  HIP_TRY(hipMemcpy(dstart.p, witness, (size_t)m * n * sizeof(hp_c64), hipMemcpyHostToDevice));
+  // one target system per test point, all with start system e and the
+  // witness points as start solutions, in one launch (gamma = 1)
+  Packed P;
+  std::vector<std::vector<int32_t>> ep(n_tests);
+  std::vector<std::vector<hp_c64>> cf(n_tests);
+  std::vector<std::vector<uint8_t>> ex(n_tests);
+  for (int k = 0; k < n_tests; ++k) {
+    hp_system f;
+    if ((rc = moved_system(e, n_hyper, tests + (size_t)k * n, ep[k], cf[k], ex[k], f))) return rc;
+    SysInfo fi;
+    if ((rc = check_system(&f, fi))) return rc;
+    pack_append(P, &f, fi, hp_c64{1.0, 0.0}, m, (int64_t)k * m, (int64_t)k * m * n, nullptr, e,
+                info.emax, dstart.as<double2>());
+  }
+  DevTables dev;
+  if ((rc = dev.upload(P, ctx->stream))) return rc;
+  const int64_t total = (int64_t)n_tests * m;
+  DevBuf de, ds;
+  if ((rc = de.alloc((size_t)total * n * sizeof(hp_c64))) ||
+      (rc = ds.alloc((size_t)total * sizeof(int32_t))))
+    return rc;
+  Kv kv;
+  kv_decode(nmax_for(n), kv);  // general start systems run on the group kernels
+  int groups = 0;
+  ctx->last = hp_timing{};
+  if ((rc = launch_persistent(ctx, dev, P, kv, T, total, de.as<hp_c64>(), ds.as<int32_t>(), nullptr,
+                              ctx->stream, &groups)))
+    return rc;
+  HIP_TRY(hipEventSynchronize(ctx->ev1));
+  float ms = 0.f, eg = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->evm));
+  HIP_TRY(hipEventElapsedTime(&eg, ctx->evm, ctx->ev1));
+  HIP_TRY(hipMemcpy(endpoints, de.p, (size_t)total * n * sizeof(hp_c64), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(status, ds.p, (size_t)total * sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int k = 0; k < n_tests; ++k) {
+    const hp_c64 *y = tests + (size_t)k * n;
+    double ny = 0.0;
+    for (int j = 0; j < n; ++j) ny = std::max(ny, std::hypot(y[j].re, y[j].im));
+    member[k] = 0;
+    for (int64_t p = 0; p < m; ++p) {
+      const int64_t q = (int64_t)k * m + p;
+      if (status[q] != HP_CONVERGED) continue;
+      double d = 0.0;
+      for (int j = 0; j < n; ++j)
+        d = std::max(d, std::hypot(endpoints[q * n + j].re - y[j].re, endpoints[q * n + j].im - y[j].im));
+      if (d <= rel * std::max(1.0, ny)) member[k] = 1;
+    }
+  }
+  ctx->last.kernel_ms = ms;
+  ctx->last.endgame_ms = eg;
+  ctx->last.launches = 1;
+  ctx->last.groups = groups;
+  ctx->last.paths_per_wave = hp::kLanes / n;
+  ctx->last.max_n = kv.nmax;
+  ctx->last.variant = kv.code;
+  ctx->last.total_ms = now_ms() - t0;
+  return HP_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
 // Serving: continuous batching over the persistent tracker
 // ---------------------------------------------------------------------------
 //

@@ -219,6 +219,87 @@ def linear_products(n: int, degrees, rng: np.random.Generator):
     return _assemble(n, eqs, "linear_products"), Ls, betas
 
 
+def _expand(n, factors):
+    """Product of polynomials given as dicts {exponent tuple: coefficient}."""
+    poly = {tuple([0] * n): 1.0 + 0j}
+    for q in factors:
+        poly = _poly_mul(poly, q)
+    return {a: c for a, c in poly.items() if c != 0}
+
+
+def _lin(n, j, root):
+    """x_j - root as a polynomial dict."""
+    e = [0] * n
+    e[j] = 1
+    return {tuple(e): 1.0 + 0j, tuple([0] * n): -complex(root)}
+
+
+def _var_pow(n, j, p):
+    e = [0] * n
+    e[j] = p
+    return {tuple(e): 1.0 + 0j}
+
+
+def membership_example() -> PolySystem:
+    """The system of Example 4.1 (homotopy membership test), exact integer
+    coefficients: (x1 - 1)(x1 - 2) = 0, (x1 - 1) x2^2 = 0: the line x1 = 1
+    and the double point (2, 0)."""
+    n = 2
+    f1 = _expand(n, [_lin(n, 0, 1), _lin(n, 0, 2)])
+    f2 = _expand(n, [_lin(n, 0, 1), _var_pow(n, 1, 2)])
+    return _assemble(n, [sorted(((c, a) for a, c in f.items()), key=lambda t: (sum(t[1]), t[1]))
+                         for f in (f1, f2)], "membership41")
+
+
+def multistep_system() -> PolySystem:
+    """The system of Example 3.1 (a 3-stage cascade), exact integer
+    coefficients, expanded from its factored form:
+    (x1-1)(x1-2)(x1-3)(x1-4), (x1-1)(x2-1)(x2-2)(x2-3),
+    (x1-1)(x1-2)(x3-1)(x3-2), (x1-1)(x2-1)(x3-1)(x4-1)."""
+    n = 4
+    eqs = [
+        _expand(n, [_lin(n, 0, 1), _lin(n, 0, 2), _lin(n, 0, 3), _lin(n, 0, 4)]),
+        _expand(n, [_lin(n, 0, 1), _lin(n, 1, 1), _lin(n, 1, 2), _lin(n, 1, 3)]),
+        _expand(n, [_lin(n, 0, 1), _lin(n, 0, 2), _lin(n, 2, 1), _lin(n, 2, 2)]),
+        _expand(n, [_lin(n, 0, 1), _lin(n, 1, 1), _lin(n, 2, 1), _lin(n, 3, 1)]),
+    ]
+    return _assemble(n, [sorted(((c, a) for a, c in f.items()), key=lambda t: (sum(t[1]), t[1]))
+                         for f in eqs], "multistep")
+
+
+def embed(f: PolySystem, k: int, rng: np.random.Generator, name=None) -> PolySystem:
+    """The embedding of Section 2.1 (Example 2.1 for k = 1): k slack
+    variables z_1..z_k and k random hyperplanes.  Equation i of f becomes
+    f_i + sum_j gamma_ij z_j; hyperplane j is c_j0 + sum_l c_jl x_l + z_j = 0.
+    Unknowns (x_1..x_n, z_1..z_k).  Draw order: gamma_ij (i outer, j inner),
+    then c_j0, c_j1, .., c_jn for j = 1..k, all uniform on the unit circle."""
+    n = f.n
+    m = n + k
+    gam = unit_circle(rng, (n, k))
+    cs = unit_circle(rng, (k, n + 1))
+    eqs = []
+    for i in range(n):
+        terms = []
+        for t in range(int(f.eq_ptr[i]), int(f.eq_ptr[i + 1])):
+            terms.append((f.coeff[t], tuple(int(v) for v in f.exps[t]) + (0,) * k))
+        for j in range(k):
+            e = [0] * m
+            e[n + j] = 1
+            terms.append((gam[i, j], tuple(e)))
+        eqs.append(terms)
+    for j in range(k):
+        terms = [(cs[j, 0], tuple([0] * m))]
+        for l in range(n):
+            e = [0] * m
+            e[l] = 1
+            terms.append((cs[j, l + 1], tuple(e)))
+        e = [0] * m
+        e[n + j] = 1
+        terms.append((1.0, tuple(e)))
+        eqs.append(terms)
+    return _assemble(m, eqs, name or f"embedded_{f.name}_{k}")
+
+
 # ---------------------------------------------------------------------------
 # Named workloads (seeded)
 # ---------------------------------------------------------------------------
