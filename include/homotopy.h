@@ -313,6 +313,37 @@ int hp_membership_test(hp_context *ctx, const hp_system *e, int32_t n_hyper, con
                        int64_t m, const hp_c64 *tests, int32_t n_tests, const hp_tolerances *tol,
                        double rel, hp_c64 *endpoints, int32_t *status, int32_t *member);
 
+/* Cascade of homotopies (Section 3.1, Example 3.1, Figure 3): candidate
+ * generic points on the solution sets of every dimension k, k-1, .., 0.
+ *   e: an embedded system (Section 2.1) of top dimension k: unknowns
+ *      (x_1..x_{n-k}, z_1..z_k), equations f_i + sum_j gamma_ij z_j
+ *      (i < n - k), then the k hyperplanes, hyperplane j holding z_j;
+ *   gammas [k+1]: the random constant of each stage's homotopy.
+ * Stage 0 solves e (hp_plan_solve_device: every total-degree path, end
+ * game, duplicate post-pass); its CONVERGED endpoints with |z_k| <=
+ * slack_tol are the candidates of dimension k, those with z_k != 0 the start
+ * points of stage 1.  Stage s (dimension d = k - s) tracks them with
+ * gammas[s] from the previous system to the one where z_{d+1} leaves the
+ * first n - k equations and its hyperplane becomes z_{d+1} = 0 (a general
+ * start system, so the group kernels); its CONVERGED endpoints with
+ * |z_d| <= slack_tol are the candidates of dimension d, the rest start
+ * stage s + 1; at dimension 0 every CONVERGED endpoint is a candidate.
+ * Outputs (host): stages [k+1]; the first min(total, cap) candidates in
+ * witness [cap*n] with their dimensions in witness_dim [cap], stage after
+ * stage; *n_witness = total candidates. */
+typedef struct {
+  int32_t dim;            /* dimension of the stage's candidates           */
+  int32_t pad;
+  int64_t paths;          /* paths tracked in the stage                    */
+  int64_t converged;
+  int64_t candidates;     /* converged with zero slack (dim 0: converged)  */
+  int64_t nonzero;        /* converged with nonzero slack: next stage      */
+  double kernel_ms;       /* tracking kernel time of the stage             */
+} hp_cascade_stage;
+int hp_cascade(hp_context *ctx, const hp_system *e, int32_t k, const hp_c64 *gammas,
+               const hp_tolerances *tol, double slack_tol, hp_cascade_stage *stages,
+               hp_c64 *witness, int32_t *witness_dim, int64_t cap, int64_t *n_witness);
+
 /* Serving: a request loop with continuous batching (a worker thread with its
  * own stream), in the manner of the paper's pipeline in which tracking of
  * the paths of one piece of work starts while other pieces are still being

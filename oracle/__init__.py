@@ -304,3 +304,69 @@ def membership_test(e_sys, n_hyper, witness, tests, tol: RefTolerances | None = 
         S.append(st)
         M.append(bool(hit.any()))
     return np.asarray(E), np.asarray(S), np.asarray(M)
+
+
+def cascade_stage_system(e_cur, k, d):
+    """The target system of the cascade stage that removes slack variable
+    z_d (Section 3.1, Example 3.1): in the current system e_cur (unknowns x,
+    then z_1..z_k; its last k equations the hyperplanes, in slack order), the
+    terms in z_d leave the first n - k equations and equation n - k + d - 1
+    becomes z_d = 0."""
+    import dataclasses
+    n = e_cur.n
+    nx = n - k
+    zi = nx + d - 1
+    eq_ptr, coeff, exps = [0], [], []
+    for i in range(n):
+        a, b = int(e_cur.eq_ptr[i]), int(e_cur.eq_ptr[i + 1])
+        if i == zi:
+            ex = np.zeros(n, np.uint8)
+            ex[zi] = 1
+            coeff.append(1.0 + 0j)
+            exps.append(ex)
+        else:
+            for t in range(a, b):
+                if i < nx and e_cur.exps[t][zi] > 0:
+                    continue
+                coeff.append(complex(e_cur.coeff[t]))
+                exps.append(np.asarray(e_cur.exps[t]))
+        eq_ptr.append(len(coeff))
+    return dataclasses.replace(e_cur, eq_ptr=np.asarray(eq_ptr, np.int32),
+                               coeff=np.asarray(coeff, np.complex128),
+                               exps=np.asarray(exps, np.uint8).reshape(len(coeff), n),
+                               name=f"{e_cur.name}_z{d}")
+
+
+def cascade(e, k, gammas, tol: RefTolerances | None = None, slack_tol=1e-6, n_threads=1):
+    """Cascade of homotopies (Section 3.1, Example 3.1, Figure 3) on the
+    embedded system e (top dimension k).  Stage 0 solves e (all total-degree
+    paths, then the duplicate post-pass) with gammas[0]; its converged
+    endpoints with z_k = 0 are candidate generic points of dimension k, those
+    with z_k != 0 start the next stage.  Stage s (dimension d = k - s) tracks
+    them with gammas[s] from the current system to the one without z_{d+1}
+    (cascade_stage_system); converged endpoints with z_d = 0 (|z_d| <=
+    slack_tol) are candidates of dimension d, the others start stage s + 1;
+    at dimension 0 every converged endpoint is a candidate isolated solution.
+    Returns a list of k + 1 stage records (dict: dim, paths, status
+    histogram, candidates complex [c, n], nonzero count)."""
+    out = []
+    ends, st, _, _ = solve(e, gammas[0], n_threads=n_threads, tol=tol)
+    cur = e
+    nx = e.n - k
+    for s in range(k + 1):
+        d = k - s
+        conv = st == CONVERGED
+        if d > 0:
+            zero = conv & (np.abs(ends[:, nx + d - 1]) <= slack_tol)
+        else:
+            zero = conv
+        nz = conv & ~zero
+        out.append({"dim": d, "paths": len(st), "status": np.bincount(st, minlength=5),
+                    "candidates": ends[zero], "nonzero": int(nz.sum())})
+        if d == 0:
+            break
+        nxt = cascade_stage_system(cur, k, d)
+        ends, st, _ = track_paths(nxt, gammas[s + 1], start=ends[nz], g=cur, tol=tol,
+                                  n_threads=n_threads)
+        cur = nxt
+    return out

@@ -16,7 +16,7 @@ import numpy as np
 from . import _lib
 from ._lib import (CONVERGED, DIVERGED, FAILED_MAXSTEPS, FAILED_MINSTEP, FAILED_NEWTON_T1,
                    HP_BATCHED, HP_MAX_N, HP_PLAIN, STATS_DTYPE, HomotopyError, HpC64,
-                   HpSystem, HpTiming, HpTolerances, check, load)
+                   HpCascadeStage, HpSystem, HpTiming, HpTolerances, check, load)
 
 __all__ = [
     "Context", "Plan", "Server", "default_tolerances", "path_count", "batch_layout",
@@ -226,6 +226,26 @@ class Context:
                                          _ptr(y), T, ctypes.byref(tol), float(rel), _ptr(ends),
                                          _ptr(st), _ptr(mem)))
         return ends, st, mem.astype(bool)
+
+    def cascade(self, e_sys, k, gammas, tol=None, slack_tol=1e-6, cap=1 << 16):
+        """Cascade of homotopies (hp_cascade) on an embedded system of top
+        dimension k.  Returns (stages: list of dicts, candidates complex
+        [c, n], their dimensions int [c])."""
+        v = _SysView(e_sys)
+        g = np.ascontiguousarray(np.asarray(gammas, np.complex128).reshape(-1))
+        if g.shape[0] != k + 1:
+            raise ValueError("need k + 1 gammas")
+        stages = (HpCascadeStage * (k + 1))()
+        wit = np.zeros((cap, v.n), np.complex128)
+        dims = np.zeros(cap, np.int32)
+        total = ctypes.c_int64(0)
+        tol = tol or default_tolerances()
+        check(self._L.hp_cascade(self.handle, ctypes.byref(v.c), int(k), _ptr(g), ctypes.byref(tol),
+                                 float(slack_tol), stages, _ptr(wit), _ptr(dims), cap,
+                                 ctypes.byref(total)))
+        c = min(cap, int(total.value))
+        recs = [{f: getattr(s, f) for f, _ in HpCascadeStage._fields_ if f != "pad"} for s in stages]
+        return recs, wit[:c], dims[:c]
 
     def plan(self, system, gamma, tol=None, tune=False):
         return Plan(self, system, gamma, tol, tune)

@@ -26,7 +26,7 @@ EXPORTED = [
     "hp_find_duplicates", "hp_solve", "hp_server_create", "hp_server_submit", "hp_server_poll",
     "hp_server_wait", "hp_server_peak_bytes", "hp_server_destroy", "hp_spec_compile",
     "hp_find_duplicates_device", "hp_plan_solve_device", "hp_find_duplicates_device_static",
-    "hp_membership_test",
+    "hp_membership_test", "hp_cascade",
 ]
 
 
@@ -45,6 +45,12 @@ class HpTolerances(ctypes.Structure):
                 ("h_init", ctypes.c_double), ("h_min", ctypes.c_double),
                 ("h_max", ctypes.c_double), ("max_steps", ctypes.c_int32),
                 ("max_newton", ctypes.c_int32), ("max_newton_final", ctypes.c_int32)]
+
+
+class HpCascadeStage(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("pad", ctypes.c_int32), ("paths", ctypes.c_int64),
+                ("converged", ctypes.c_int64), ("candidates", ctypes.c_int64),
+                ("nonzero", ctypes.c_int64), ("kernel_ms", ctypes.c_double)]
 
 
 class HpTiming(ctypes.Structure):
@@ -112,6 +118,9 @@ def load():
             "hp_plan_solve_device": (ctypes.c_int, [vp, vp, vp, vp, P(i64), P(i64), vp]),
             "hp_membership_test": (ctypes.c_int, [vp, P(HpSystem), i32, vp, i64, vp, i32,
                                                   P(HpTolerances), ctypes.c_double, vp, vp, vp]),
+            "hp_cascade": (ctypes.c_int, [vp, P(HpSystem), i32, vp, P(HpTolerances),
+                                          ctypes.c_double, P(HpCascadeStage), vp, vp, i64,
+                                          P(i64)]),
             "hp_find_duplicates_device_static": (ctypes.c_int, [vp, i32, i64, vp, vp,
                                                                 ctypes.c_double, vp, i64, P(i64),
                                                                 vp]),

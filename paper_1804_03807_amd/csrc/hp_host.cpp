@@ -1669,6 +1669,157 @@ int hp_membership_test(hp_context *ctx, const hp_system *e, int32_t n_hyper, con
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// Cascade of homotopies (Section 3.1, Example 3.1, Figure 3)
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// A system that owns its arrays.
+struct OwnedSystem {
+  std::vector<int32_t> eq_ptr;
+  std::vector<hp_c64> coeff;
+  std::vector<uint8_t> exps;
+  hp_system sys{};
+  void copy_from(const hp_system *s) {
+    const int n = s->n;
+    eq_ptr.assign(s->eq_ptr, s->eq_ptr + n + 1);
+    coeff.assign(s->coeff, s->coeff + s->n_terms);
+    exps.assign(s->exps, s->exps + (size_t)s->n_terms * n);
+    sys = hp_system{n, s->n_terms, eq_ptr.data(), coeff.data(), exps.data()};
+  }
+};
+
+// The cascade stage's target: in cur (n unknowns, the last k slack), the
+// terms in z_d (unknown n - k + d - 1) leave the first n - k equations and
+// equation n - k + d - 1 becomes z_d = 0.
+void stage_system(const hp_system *cur, int k, int d, OwnedSystem &out) {
+  const int n = cur->n, nx = n - k, zi = nx + d - 1;
+  out.eq_ptr.assign(1, 0);
+  out.coeff.clear();
+  out.exps.clear();
+  for (int i = 0; i < n; ++i) {
+    if (i == zi) {
+      out.coeff.push_back(hp_c64{1.0, 0.0});
+      for (int j = 0; j < n; ++j) out.exps.push_back(j == zi ? 1 : 0);
+    } else {
+      for (int t = cur->eq_ptr[i]; t < cur->eq_ptr[i + 1]; ++t) {
+        if (i < nx && cur->exps[(size_t)t * n + zi] > 0) continue;
+        out.coeff.push_back(cur->coeff[t]);
+        out.exps.insert(out.exps.end(), cur->exps + (size_t)t * n, cur->exps + (size_t)(t + 1) * n);
+      }
+    }
+    out.eq_ptr.push_back((int32_t)out.coeff.size());
+  }
+  out.sys = hp_system{n, (int32_t)out.coeff.size(), out.eq_ptr.data(), out.coeff.data(),
+                      out.exps.data()};
+}
+
+}  // namespace
+
+extern "C" {
+
+int hp_cascade(hp_context *ctx, const hp_system *e, int32_t k, const hp_c64 *gammas,
+               const hp_tolerances *tol, double slack_tol, hp_cascade_stage *stages,
+               hp_c64 *witness, int32_t *witness_dim, int64_t cap, int64_t *n_witness) {
+  if (!ctx || !e || !gammas || !stages || !n_witness || (cap > 0 && (!witness || !witness_dim)))
+    return fail(HP_E_INVALID_ARG, "NULL argument");
+  SysInfo info;
+  int rc = check_system(e, info);
+  if (rc) return rc;
+  if (k < 1 || k >= e->n || cap < 0 || !(slack_tol >= 0.0))
+    return fail(HP_E_INVALID_ARG, "bad cascade arguments");
+  const int n = e->n, nx = n - k;
+  for (int j = 0; j < k; ++j)  // hyperplane j is linear and holds z_j
+    for (int t = e->eq_ptr[nx + j]; t < e->eq_ptr[nx + j + 1]; ++t) {
+      int deg = 0;
+      for (int v = 0; v < n; ++v) deg += e->exps[(size_t)t * n + v];
+      if (deg > 1) return fail(HP_E_INVALID_ARG, "a hyperplane equation is not linear");
+    }
+  int64_t total = 0;
+  auto take = [&](const std::vector<hp_c64> &x, int64_t p, int dim) {
+    if (total < cap) {
+      std::memcpy(witness + total * n, x.data() + p * n, n * sizeof(hp_c64));
+      witness_dim[total] = dim;
+    }
+    ++total;
+  };
+  // stage 0: the top system
+  std::vector<hp_c64> ends;
+  std::vector<int32_t> st;
+  double kms = 0.0;
+  {
+    hp_plan *plan = nullptr;
+    if ((rc = hp_plan_create(ctx, e, gammas[0], tol, 0, &plan))) return rc;
+    std::unique_ptr<hp_plan, void (*)(hp_plan *)> guard(plan, hp_plan_destroy);
+    const int64_t P = plan->info.paths;
+    DevBuf de, ds;
+    if ((rc = de.alloc((size_t)P * n * sizeof(hp_c64))) || (rc = ds.alloc((size_t)P * sizeof(int32_t))))
+      return rc;
+    if ((rc = hp_plan_solve_device(plan, de.as<hp_c64>(), ds.as<int32_t>(), nullptr, nullptr,
+                                   nullptr, nullptr)))
+      return rc;
+    kms = ctx->last.kernel_ms;
+    ends.resize((size_t)P * n);
+    st.resize(P);
+    HIP_TRY(hipMemcpy(ends.data(), de.p, ends.size() * sizeof(hp_c64), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(st.data(), ds.p, st.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  }
+  OwnedSystem cur, nxt;
+  cur.copy_from(e);
+  for (int s = 0; s <= k; ++s) {
+    const int d = k - s;
+    hp_cascade_stage &S = stages[s];
+    std::memset(&S, 0, sizeof(S));
+    S.dim = d;
+    S.paths = (int64_t)st.size();
+    S.kernel_ms = kms;
+    std::vector<hp_c64> starts;
+    for (int64_t p = 0; p < (int64_t)st.size(); ++p) {
+      if (st[p] != HP_CONVERGED) continue;
+      ++S.converged;
+      const hp_c64 z = d > 0 ? ends[p * n + nx + d - 1] : hp_c64{0.0, 0.0};
+      if (std::hypot(z.re, z.im) <= slack_tol) {
+        ++S.candidates;
+        take(ends, p, d);
+      } else {
+        ++S.nonzero;
+        starts.insert(starts.end(), ends.begin() + p * n, ends.begin() + (p + 1) * n);
+      }
+    }
+    if (d == 0 || starts.empty()) {
+      for (int r = s + 1; r <= k; ++r) {  // nothing left to track
+        std::memset(&stages[r], 0, sizeof(hp_cascade_stage));
+        stages[r].dim = k - r;
+      }
+      break;
+    }
+    stage_system(&cur.sys, k, d, nxt);
+    const int64_t m = (int64_t)starts.size() / n;
+    hp_plan *plan = nullptr;
+    if ((rc = plan_create(ctx, &nxt.sys, &cur.sys, starts.data(), m, gammas[s + 1], tol, 0, false,
+                          &plan)))
+      return rc;
+    std::unique_ptr<hp_plan, void (*)(hp_plan *)> guard(plan, hp_plan_destroy);
+    DevBuf de, ds;
+    if ((rc = de.alloc((size_t)m * n * sizeof(hp_c64))) || (rc = ds.alloc((size_t)m * sizeof(int32_t))))
+      return rc;
+    if ((rc = hp_plan_track_device(plan, nullptr, m, de.as<hp_c64>(), ds.as<int32_t>(), nullptr,
+                                   HP_BATCHED, nullptr)))
+      return rc;
+    kms = ctx->last.kernel_ms;
+    ends.resize((size_t)m * n);
+    st.resize(m);
+    HIP_TRY(hipMemcpy(ends.data(), de.p, ends.size() * sizeof(hp_c64), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(st.data(), ds.p, st.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    cur.copy_from(&nxt.sys);
+  }
+  *n_witness = total;
+  return HP_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
 // Serving: continuous batching over the persistent tracker
 // ---------------------------------------------------------------------------
 //
