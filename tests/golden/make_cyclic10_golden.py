@@ -9,9 +9,10 @@ path.  Takes over an hour on 8 host threads:
     python tests/golden/make_cyclic10_golden.py [n_threads]
 
 Output: ``cyclic10_seed5.npz`` (status int8 per path id, ids and endpoints of
-the converged paths, each path's t_final and ||x||_inf at its end) and
-``cyclic10_seed5.json`` (status histogram, the digest of the oracle source the
-values were made with, run time).
+the converged paths, and one bit per path, packed: the path stopped in the end
+zone t >= 1 - 1e-9) and ``cyclic10_seed5.json`` (status histogram, the
+smallest t at which a FAILED_MINSTEP path stopped, the digest of the oracle
+source the values were made with, run time).
 """
 import hashlib
 import json
@@ -65,8 +66,17 @@ def main():
     conv_ids = np.concatenate(conv_ids)
     conv_x = np.concatenate(conv_x)
     hist = np.bincount(status, minlength=5).tolist()
+    write(status, conv_ids, conv_x, t_final, xnorm, hist, n_threads, time.time() - t0)
+
+
+ENDZONE = 1e-9
+
+
+def write(status, conv_ids, conv_x, t_final, xnorm, hist, n_threads, seconds):
     np.savez_compressed(os.path.join(HERE, "cyclic10_seed5.npz"), status=status,
-                        conv_ids=conv_ids, conv_x=conv_x, t_final=t_final, xnorm=xnorm)
+                        conv_ids=conv_ids, conv_x=conv_x,
+                        endzone=np.packbits(t_final >= 1.0 - ENDZONE))
+    ms = status == 2
     meta = {
         "workload": "cyclic-10 supports, random unit-circle coefficients, seed 5; "
                     "total-degree homotopy, 3,628,800 paths, default tolerances",
@@ -76,8 +86,11 @@ def main():
         "status_names": ["CONVERGED", "DIVERGED", "FAILED_MINSTEP", "FAILED_MAXSTEPS",
                          "FAILED_NEWTON_T1"],
         "converged": int(hist[0]),
+        "endzone": f"t_final >= 1 - {ENDZONE:g}",
+        "minstep_min_t_final": float(t_final[ms].min()) if ms.any() else None,
+        "minstep_norm_range": [float(xnorm[ms].min()), float(xnorm[ms].max())] if ms.any() else None,
         "n_threads": n_threads,
-        "seconds": round(time.time() - t0, 1),
+        "seconds": round(seconds, 1),
     }
     with open(os.path.join(HERE, "cyclic10_seed5.json"), "w") as fh:
         json.dump(meta, fh, indent=1)

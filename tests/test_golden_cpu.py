@@ -31,3 +31,7 @@ def test_cyclic10_golden_matches_oracle(oracle_lib):
     assert np.array_equal(st, status[ids].astype(np.int32))
     where = np.searchsorted(conv_ids, ids[st == 0])
     assert np.array_equal(e[st == 0], conv_x[where])
+    # every FAILED_MINSTEP path stopped in the end zone
+    endzone = np.unpackbits(z["endzone"])[:len(status)].astype(bool)
+    assert endzone[status == 2].all()
+    assert meta["minstep_min_t_final"] >= 1 - 1e-9
