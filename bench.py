@@ -13,7 +13,8 @@ re-tracking of duplicate pairs, all on the device.
 Also measured (sub-keys, outside the timed region): cyclic-8 (40,320 paths)
 batched vs plain, the dense n = 5 system (32 paths) batched vs plain, 256 dense
 systems in one launch, coefficient-parameter continuation between two
-cyclic-8 systems (2,560 paths), and the serving loop on 1,000 requests.
+cyclic-8 systems (2,560 paths), the double-double tracker on cyclic-8, and
+the serving loop on 1,000 requests.
 
 Prints one JSON line.
 """
@@ -183,6 +184,24 @@ def continuation_run(ctx):
             "kernel_ms": tm["kernel_ms"], "endgame_ms": tm["endgame_ms"],
             "end_to_end_ms": dt * 1e3, "paths_per_s": len(start) / dt,
             "kernel_variant": tm["variant"]}
+
+
+def dd_run(ctx, double_ms):
+    """The double-double tracker on the cyclic-8 workload (all 40,320 paths,
+    n lanes per path), beside the double tracker's time on the same paths
+    (the paper's Table 2 compares double-double with double on cyclic 8)."""
+    import workloads as W
+    wl = W.cyclic8()
+    s, g = wl.systems[0], complex(wl.gammas[0])
+    ctx.track_paths_dd(s, g, stats=False)  # warm-up
+    t0 = time.perf_counter()
+    hi, lo, st, _ = ctx.track_paths_dd(s, g, stats=False)
+    dt = time.perf_counter() - t0
+    tm = ctx.last_timing()
+    return {"workload": WORKLOADS["cyclic8"], "paths": s.bezout(), "converged": int((st == 0).sum()),
+            "kernel_ms": tm["kernel_ms"], "end_to_end_ms": dt * 1e3,
+            "paths_per_s": s.bezout() / (tm["kernel_ms"] * 1e-3),
+            "slowdown_vs_double": tm["kernel_ms"] / double_ms}
 
 
 def batch_run(ctx, n_systems=256):
@@ -418,6 +437,7 @@ def main():
 
     if not args.no_extra:
         out["cyclic8"] = batched_vs_plain(ctx, "cyclic8")
+        out["double_double_cyclic8"] = dd_run(ctx, out["cyclic8"]["batched_ms"])
         out["dense5"] = batched_vs_plain(ctx, "dense5", steps=20)
         out["batch256"] = batch_run(ctx)
         out["continuation_cyclic8"] = continuation_run(ctx)

@@ -171,6 +171,24 @@ int hp_track_paths(hp_context *ctx, const hp_system *f, const hp_system *g, cons
                    int64_t n_paths, hp_c64 gamma, const hp_tolerances *tol, hp_c64 *endpoints,
                    int32_t *status, hp_path_stats *stats, int32_t mode);
 
+/* The double-double tracker (the paper's "quality up": Section 1; Section
+ * 5.1 and Table 2 run the solver in double-double): the homotopy, predictor,
+ * corrector, step control and end game of hp_track_paths with every
+ * operation on points, values, Jacobians and linear systems in complex
+ * double-double (t and h in double), the final Newton at t = 1 in
+ * double-double to tol->tol_final and the residual ||f(x)||_inf with f in
+ * double-double.  Total-degree start system; start == NULL: paths
+ * 0..n_paths-1 decoded from their ids, else path k starts at start[k*n..].
+ * Endpoints as double-double pairs: endpoints_hi + endpoints_lo, each
+ * [n_paths*n]; status [n_paths], stats [n_paths] or NULL.  Host memory.
+ * One path per group of n lanes on the device. */
+int hp_track_paths_dd(hp_context *ctx, const hp_system *f, const hp_c64 *start, int64_t n_paths,
+                      hp_c64 gamma, const hp_tolerances *tol, hp_c64 *endpoints_hi,
+                      hp_c64 *endpoints_lo, int32_t *status, hp_path_stats *stats);
+/* The double-double tracker's defaults: hp_default_tolerances with the final
+ * Newton run to tol_final = 1e-26. */
+void hp_default_tolerances_dd(hp_tolerances *tol);
+
 /* A plan: f packed and resident on the device, with a kernel variant chosen
  * (autotuned when tune != 0 and no cached choice exists).  Without tuning,
  * a plan for n <= 10 whose terms have at most 1024 factors in all runs on a

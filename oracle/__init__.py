@@ -78,6 +78,10 @@ def lib():
             L.ref_residuals_dd.argtypes = [ctypes.POINTER(RefSystem), i64, vp, vp]
             L.ref_refine_dd.argtypes = [ctypes.POINTER(RefSystem), vp, ctypes.c_int, vp]
             L.ref_dd_ops.argtypes = [ctypes.c_double] * 4 + [vp, vp]
+            L.ref_track_paths_dd.argtypes = [ctypes.POINTER(RefSystem), ctypes.POINTER(RefSystem),
+                                             vp, vp, vp, i64, ctypes.POINTER(RefTolerances),
+                                             vp, vp, vp, vp, i32]
+            L.ref_track_paths_dd.restype = ctypes.c_int
             L.ref_find_duplicates.argtypes = [ctypes.c_int, i64, vp, vp, ctypes.c_double, vp, i64]
             L.ref_find_duplicates.restype = i64
             _lib = L
@@ -218,6 +222,43 @@ def track_paths(f, gamma, path_ids=None, n_paths=None, start=None, g=None,
     if rc != 0:
         raise ValueError(f"ref_track_paths failed ({rc})")
     return ends, status, stats
+
+
+def dd_tolerances(**over) -> RefTolerances:
+    """The double-double tracker's defaults: the double tracker's, with the
+    final Newton at t = 1 run to 1e-26 relative."""
+    t = default_tolerances(tol_final=1e-26)
+    for k, v in over.items():
+        setattr(t, k, v)
+    return t
+
+
+def track_paths_dd(f, gamma, path_ids=None, n_paths=None, start=None, g=None,
+                   tol: RefTolerances | None = None, n_threads: int = 1):
+    """The double-double tracker.  Returns (endpoints_hi, endpoints_lo
+    complex [P, n], status int32 [P], stats)."""
+    F = _Sys(f)
+    G = _Sys(g) if g is not None else None
+    if path_ids is not None:
+        path_ids = np.ascontiguousarray(path_ids, dtype=np.int64)
+        P = int(path_ids.shape[0])
+    elif start is not None:
+        start = np.ascontiguousarray(start, dtype=np.complex128)
+        P = int(start.shape[0])
+    else:
+        P = int(n_paths if n_paths is not None else f.bezout())
+    gam = np.asarray([complex(gamma).real, complex(gamma).imag], np.float64)
+    hi = np.zeros((P, f.n), np.complex128)
+    lo = np.zeros((P, f.n), np.complex128)
+    status = np.full(P, -1, np.int32)
+    stats = np.zeros(P, STATS_DTYPE)
+    tol = tol or dd_tolerances()
+    rc = lib().ref_track_paths_dd(ctypes.byref(F.st), ctypes.byref(G.st) if G else None,
+                                  _ptr(gam), _ptr(start), _ptr(path_ids), P, ctypes.byref(tol),
+                                  _ptr(hi), _ptr(lo), _ptr(status), _ptr(stats), int(n_threads))
+    if rc != 0:
+        raise ValueError(f"ref_track_paths_dd failed ({rc})")
+    return hi, lo, status, stats
 
 
 def find_duplicates(endpoints, status, rel=1e-6, max_pairs=1 << 16):

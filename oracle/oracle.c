@@ -643,3 +643,360 @@ int64_t ref_find_duplicates(int n, int64_t n_paths, const double *endpoints,
   }
   return count;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Double-double tracker: the same homotopy, predictor, corrector, step    */
+/* control and end game as track_one, every operation on points, function  */
+/* values, Jacobians and linear systems in complex double-double (the      */
+/* paper's "quality up": Section 1, Section 5.1 and Table 2 track in       */
+/* double-double).  t and h stay doubles: the path parameter and the step  */
+/* size are exact in double.  Norms and the tests on them use the nearest  */
+/* double of each double-double value.                                     */
+/* ---------------------------------------------------------------------- */
+
+static dd dd_sub(dd a, dd b) { return dd_add(a, dd_neg(b)); }
+
+/* a / b: three quotient digits, each from the remainder (Dekker-style long
+ * division in double-double) */
+static dd dd_div(dd a, dd b) {
+  double q1 = a.hi / b.hi;
+  dd r = dd_sub(a, dd_mul(b, dd_from(q1)));
+  double q2 = r.hi / b.hi;
+  r = dd_sub(r, dd_mul(b, dd_from(q2)));
+  double q3 = r.hi / b.hi;
+  dd q = fast_two_sum(q1, q2);
+  return dd_add(q, dd_from(q3));
+}
+
+static double dd_to(dd a) { return a.hi + a.lo; }
+
+static cdd cdd_sub(cdd a, cdd b) {
+  cdd r = {dd_sub(a.re, b.re), dd_sub(a.im, b.im)};
+  return r;
+}
+
+static cdd cdd_scale(cdd a, double s) {
+  cdd r = {dd_mul(a.re, dd_from(s)), dd_mul(a.im, dd_from(s))};
+  return r;
+}
+
+/* Smith's division in double-double */
+static cdd cdd_div(cdd a, cdd b) {
+  cdd q;
+  if (fabs(dd_to(b.re)) >= fabs(dd_to(b.im))) {
+    dd r = dd_div(b.im, b.re);
+    dd den = dd_add(b.re, dd_mul(b.im, r));
+    q.re = dd_div(dd_add(a.re, dd_mul(a.im, r)), den);
+    q.im = dd_div(dd_sub(a.im, dd_mul(a.re, r)), den);
+  } else {
+    dd r = dd_div(b.re, b.im);
+    dd den = dd_add(dd_mul(b.re, r), b.im);
+    q.re = dd_div(dd_add(dd_mul(a.re, r), a.im), den);
+    q.im = dd_div(dd_sub(dd_mul(a.im, r), a.re), den);
+  }
+  return q;
+}
+
+static double cdd_abs(cdd z) { return cabs(cdd_round(z)); }
+static double cdd_abs1(cdd z) { return fabs(dd_to(z.re)) + fabs(dd_to(z.im)); }
+static int cdd_finite(cdd z) { return isfinite(dd_to(z.re)) && isfinite(dd_to(z.im)); }
+
+static double norm_inf_dd(int n, const cdd *v) {
+  double m = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double a = cdd_abs(v[i]);
+    if (!(a <= m)) m = a;
+  }
+  return m;
+}
+
+static int all_finite_dd(int n, const cdd *v) {
+  for (int i = 0; i < n; ++i)
+    if (!cdd_finite(v[i])) return 0;
+  return 1;
+}
+
+/* f(x) and J_f(x) in double-double: terms and partial derivatives by
+ * repeated multiplication, as eval_f */
+static void eval_f_ddj(const ref_system *s, const cdd *x, cdd *fx, cdd *jac) {
+  const int n = s->n;
+  const cdd zero = cdd_from(0.0);
+  for (int i = 0; i < n; ++i) {
+    if (fx) fx[i] = zero;
+    if (jac)
+      for (int j = 0; j < n; ++j) jac[i * n + j] = zero;
+    for (int t = s->eq_ptr[i]; t < s->eq_ptr[i + 1]; ++t) {
+      const uint8_t *a = s->exps + (size_t)t * n;
+      cdd c = cdd_from(load(s->coeff, t));
+      if (fx) {
+        cdd v = c;
+        for (int l = 0; l < n; ++l)
+          for (int e = 0; e < a[l]; ++e) v = cdd_mul(v, x[l]);
+        fx[i] = cdd_add(fx[i], v);
+      }
+      if (jac)
+        for (int j = 0; j < n; ++j) {
+          if (a[j] == 0) continue;
+          cdd v = cdd_scale(c, (double)a[j]);
+          for (int l = 0; l < n; ++l) {
+            int el = a[l] - (l == j ? 1 : 0);
+            for (int e = 0; e < el; ++e) v = cdd_mul(v, x[l]);
+          }
+          jac[i * n + j] = cdd_add(jac[i * n + j], v);
+        }
+    }
+  }
+}
+
+static void eval_g_dd(const homotopy *h, const cdd *x, cdd *gx, cdd *jg) {
+  const int n = h->n;
+  if (h->g) { eval_f_ddj(h->g, x, gx, jg); return; }
+  for (int i = 0; i < n; ++i) {
+    cdd p = cdd_from(1.0);
+    for (int e = 0; e < h->deg[i] - 1; ++e) p = cdd_mul(p, x[i]);
+    if (gx) gx[i] = cdd_sub(cdd_mul(p, x[i]), cdd_from(1.0));
+    if (jg) {
+      for (int j = 0; j < n; ++j) jg[i * n + j] = cdd_from(0.0);
+      jg[i * n + i] = cdd_scale(p, (double)h->deg[i]);
+    }
+  }
+}
+
+/* H, J_x and H_t at (x, t) in double-double (outputs may be NULL) */
+static void eval_h_dd(const homotopy *h, const cdd *x, double t, cdd *H, cdd *Jx, cdd *Ht) {
+  const int n = h->n;
+  cdd fx[MAXN], gx[MAXN], jf[MAXN * MAXN], jg[MAXN * MAXN];
+  eval_f_ddj(h->f, x, fx, Jx ? jf : NULL);
+  eval_g_dd(h, x, gx, Jx ? jg : NULL);
+  const cdd gam = cdd_from(h->gamma);
+  const cdd s = cdd_scale(gam, 1.0 - t);
+  for (int i = 0; i < n; ++i) {
+    if (H) H[i] = cdd_add(cdd_mul(s, gx[i]), cdd_scale(fx[i], t));
+    if (Ht) Ht[i] = cdd_sub(fx[i], cdd_mul(gam, gx[i]));
+  }
+  if (Jx)
+    for (int i = 0; i < n * n; ++i) Jx[i] = cdd_add(cdd_scale(jf[i], t), cdd_mul(s, jg[i]));
+}
+
+/* LU with partial pivoting (largest |re| + |im| of the nearest double, ties
+ * to the lowest row) and the two triangular solves, in double-double */
+static int lu_solve_dd(int n, cdd *A, const cdd *b, cdd *y) {
+  int piv[MAXN];
+  for (int k = 0; k < n; ++k) {
+    int mu = k;
+    double best = cdd_abs1(A[k * n + k]);
+    for (int i = k + 1; i < n; ++i) {
+      double v = cdd_abs1(A[i * n + k]);
+      if (v > best) { best = v; mu = i; }
+    }
+    piv[k] = mu;
+    if (mu != k)
+      for (int j = 0; j < n; ++j) {
+        cdd tmp = A[k * n + j]; A[k * n + j] = A[mu * n + j]; A[mu * n + j] = tmp;
+      }
+    cdd p = A[k * n + k];
+    if (dd_to(p.re) == 0.0 && dd_to(p.im) == 0.0) return -1;
+    for (int i = k + 1; i < n; ++i) {
+      A[i * n + k] = cdd_div(A[i * n + k], p);
+      for (int j = k + 1; j < n; ++j)
+        A[i * n + j] = cdd_sub(A[i * n + j], cdd_mul(A[i * n + k], A[k * n + j]));
+    }
+  }
+  cdd z[MAXN];
+  for (int i = 0; i < n; ++i) z[i] = b[i];
+  for (int k = 0; k < n; ++k) {
+    cdd tmp = z[k]; z[k] = z[piv[k]]; z[piv[k]] = tmp;
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) z[i] = cdd_sub(z[i], cdd_mul(A[i * n + j], z[j]));
+  for (int i = n - 1; i >= 0; --i) {
+    cdd v = z[i];
+    for (int j = i + 1; j < n; ++j) v = cdd_sub(v, cdd_mul(A[i * n + j], y[j]));
+    y[i] = cdd_div(v, A[i * n + i]);
+  }
+  return 0;
+}
+
+static int tangent_dd(const homotopy *h, const cdd *x, double t, cdd *k, ref_path_stats *st) {
+  const int n = h->n;
+  cdd J[MAXN * MAXN], Ht[MAXN], rhs[MAXN];
+  eval_h_dd(h, x, t, NULL, J, Ht);
+  st->evals++;
+  for (int i = 0; i < n; ++i) rhs[i] = cdd_scale(Ht[i], -1.0);
+  st->solves++;
+  if (lu_solve_dd(n, J, rhs, k) != 0) return -1;
+  return all_finite_dd(n, k) ? 0 : -1;
+}
+
+static int rk4_predict_dd(const homotopy *h, const cdd *x, double t, double hstep, double t_new,
+                          cdd *xp, ref_path_stats *st) {
+  const int n = h->n;
+  cdd xs[MAXN], k1[MAXN], k2[MAXN], k3[MAXN], k4[MAXN];
+  const double th = t + 0.5 * hstep;
+  if (tangent_dd(h, x, t, k1, st) != 0) return -1;
+  for (int i = 0; i < n; ++i) xs[i] = cdd_add(x[i], cdd_scale(k1[i], 0.5 * hstep));
+  if (tangent_dd(h, xs, th, k2, st) != 0) return -1;
+  for (int i = 0; i < n; ++i) xs[i] = cdd_add(x[i], cdd_scale(k2[i], 0.5 * hstep));
+  if (tangent_dd(h, xs, th, k3, st) != 0) return -1;
+  for (int i = 0; i < n; ++i) xs[i] = cdd_add(x[i], cdd_scale(k3[i], hstep));
+  if (tangent_dd(h, xs, t_new, k4, st) != 0) return -1;
+  for (int i = 0; i < n; ++i) {
+    cdd sum = cdd_add(cdd_add(k1[i], cdd_scale(k2[i], 2.0)), cdd_add(cdd_scale(k3[i], 2.0), k4[i]));
+    xp[i] = cdd_add(x[i], cdd_scale(sum, hstep / 6.0));
+  }
+  return all_finite_dd(n, xp) ? 0 : -1;
+}
+
+static int newton_dd(const homotopy *h, cdd *x, double t, int max_it, double tol,
+                     int check_contraction, ref_path_stats *st) {
+  const int n = h->n;
+  double prev = 0.0;
+  for (int it = 1; it <= max_it; ++it) {
+    cdd J[MAXN * MAXN], H[MAXN], dx[MAXN];
+    eval_h_dd(h, x, t, H, J, NULL);
+    st->evals++;
+    st->solves++;
+    st->newton_iters++;
+    if (lu_solve_dd(n, J, H, dx) != 0) return 0;
+    for (int i = 0; i < n; ++i) x[i] = cdd_sub(x[i], dx[i]);
+    if (!all_finite_dd(n, dx) || !all_finite_dd(n, x)) return 0;
+    double nd = norm_inf_dd(n, dx);
+    double nx = norm_inf_dd(n, x);
+    if (nd <= tol * (nx > 1.0 ? nx : 1.0)) return 1;
+    if (check_contraction && it >= 2 && nd > 0.5 * prev) return 0;
+    prev = nd;
+  }
+  return 0;
+}
+
+static void track_one_dd(const homotopy *h, const cplx *x_start, const ref_tolerances *tol,
+                         cdd *x_end, int32_t *status, ref_path_stats *st) {
+  const int n = h->n;
+  cdd x[MAXN], xp[MAXN];
+  memset(st, 0, sizeof(*st));
+  for (int i = 0; i < n; ++i) x[i] = cdd_from(x_start[i]);
+  double t = 0.0, hstep = tol->h_init;
+  int accepts = 0;
+  int32_t stat = -1;
+  while (t < 1.0) {
+    double t_new;
+    if (hstep >= 1.0 - t) { hstep = 1.0 - t; t_new = 1.0; }
+    else t_new = t + hstep;
+    int ok = rk4_predict_dd(h, x, t, hstep, t_new, xp, st) == 0;
+    if (ok) ok = newton_dd(h, xp, t_new, tol->max_newton, tol->tol_corr, 1, st);
+    st->steps++;
+    if (ok) {
+      t = t_new;
+      for (int i = 0; i < n; ++i) x[i] = xp[i];
+      if (++accepts == 3) {
+        hstep = 2.0 * hstep < tol->h_max ? 2.0 * hstep : tol->h_max;
+        accepts = 0;
+      }
+    } else {
+      st->rejections++;
+      hstep = 0.5 * hstep;
+      accepts = 0;
+    }
+    if (norm_inf_dd(n, x) > tol->div_radius) { stat = REF_DIVERGED; break; }
+    if (t >= 1.0) break;
+    if (hstep < tol->h_min) { stat = REF_FAILED_MINSTEP; break; }
+    if (st->steps > tol->max_steps) { stat = REF_FAILED_MAXSTEPS; break; }
+  }
+  cdd fx[MAXN];
+  if (stat < 0) {
+    /* t = 1: Newton on f in double-double, then the residual test */
+    newton_dd(h, x, 1.0, tol->max_newton_final, tol->tol_final, 0, st);
+    eval_f_ddj(h->f, x, fx, NULL);
+    double res = norm_inf_dd(n, fx), nx = norm_inf_dd(n, x);
+    st->residual = res;
+    if (res <= tol->tol_residual && nx <= tol->div_radius) stat = REF_CONVERGED;
+    else if (nx > tol->div_radius) stat = REF_DIVERGED;
+    else stat = REF_FAILED_NEWTON_T1;
+  } else {
+    eval_f_ddj(h->f, x, fx, NULL);
+    st->residual = norm_inf_dd(n, fx);
+  }
+  st->t_final = t;
+  for (int i = 0; i < n; ++i) x_end[i] = x[i];
+  *status = stat;
+}
+
+typedef struct {
+  const homotopy *h;
+  const double *start;
+  const int64_t *ids;
+  int64_t n_paths;
+  const ref_tolerances *tol;
+  double *ends_hi, *ends_lo;
+  int32_t *status;
+  ref_path_stats *stats;
+  atomic_llong next;
+} crew_dd;
+
+static void *crew_dd_worker(void *arg) {
+  crew_dd *c = (crew_dd *)arg;
+  const int n = c->h->n;
+  for (;;) {
+    int64_t k = atomic_fetch_add(&c->next, 1);
+    if (k >= c->n_paths) break;
+    cplx xs[MAXN];
+    if (c->start) {
+      for (int i = 0; i < n; ++i) xs[i] = load(c->start + (size_t)2 * n * k, i);
+    } else {
+      double tmp[2 * MAXN];
+      ref_start_point(n, c->h->deg, c->ids ? c->ids[k] : k, tmp);
+      for (int i = 0; i < n; ++i) xs[i] = load(tmp, i);
+    }
+    cdd xe[MAXN];
+    ref_path_stats st;
+    int32_t s;
+    track_one_dd(c->h, xs, c->tol, xe, &s, &st);
+    for (int i = 0; i < n; ++i) {
+      double *hi = c->ends_hi + (size_t)2 * n * k, *lo = c->ends_lo + (size_t)2 * n * k;
+      hi[2 * i] = xe[i].re.hi;
+      hi[2 * i + 1] = xe[i].im.hi;
+      lo[2 * i] = xe[i].re.lo;
+      lo[2 * i + 1] = xe[i].im.lo;
+    }
+    c->status[k] = s;
+    if (c->stats) c->stats[k] = st;
+  }
+  return NULL;
+}
+
+int ref_track_paths_dd(const ref_system *f, const ref_system *g, const double *gamma,
+                       const double *start, const int64_t *path_ids, int64_t n_paths,
+                       const ref_tolerances *tol, double *ends_hi, double *ends_lo,
+                       int32_t *status, ref_path_stats *stats, int32_t n_threads) {
+  if (!f || f->n < 1 || f->n > MAXN || n_paths < 0 || !ends_hi || !ends_lo || !status) return -1;
+  if (g && (g->n != f->n || !start)) return -1;
+  ref_tolerances deftol;
+  if (!tol) { ref_default_tolerances(&deftol); tol = &deftol; }
+  homotopy h;
+  if (make_homotopy(f, g, gamma, &h) != 0) return -1;
+  crew_dd c;
+  c.h = &h;
+  c.start = start;
+  c.ids = path_ids;
+  c.n_paths = n_paths;
+  c.tol = tol;
+  c.ends_hi = ends_hi;
+  c.ends_lo = ends_lo;
+  c.status = status;
+  c.stats = stats;
+  atomic_init(&c.next, 0);
+  if (n_threads < 1) n_threads = 1;
+  if (n_threads == 1) {
+    crew_dd_worker(&c);
+    return 0;
+  }
+  pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)n_threads);
+  if (!th) return -3;
+  int started = 0;
+  for (int i = 0; i < n_threads; ++i)
+    if (pthread_create(&th[i], NULL, crew_dd_worker, &c) == 0) ++started;
+  if (started == 0) crew_dd_worker(&c);
+  for (int i = 0; i < started; ++i) pthread_join(th[i], NULL);
+  free(th);
+  return 0;
+}

@@ -128,6 +128,16 @@ int ref_track_paths(const ref_system *f, const ref_system *g, const double *gamm
                     const ref_tolerances *tol, double *endpoints, int32_t *status,
                     ref_path_stats *stats, int32_t n_threads);
 
+/* The tracker of ref_track_paths with every operation on points, values,
+ * Jacobians and linear systems in complex double-double (t and h in
+ * double); the final Newton at t = 1 runs in double-double to tol_final and
+ * the residual is ||f(x)||_inf with f in double-double.  Endpoints as
+ * double-double pairs: ends_hi, ends_lo [2n*n_paths] each. */
+int ref_track_paths_dd(const ref_system *f, const ref_system *g, const double *gamma,
+                       const double *start, const int64_t *path_ids, int64_t n_paths,
+                       const ref_tolerances *tol, double *ends_hi, double *ends_lo,
+                       int32_t *status, ref_path_stats *stats, int32_t n_threads);
+
 /* Pairs (a, b), a < b, of CONVERGED endpoints with
  * ||x_a - x_b||_inf <= rel * max(1, ||x_a||_inf), by comparing every pair.
  * Writes up to max_pairs pairs into pairs[2*k]; returns the pair count. */

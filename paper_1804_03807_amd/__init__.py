@@ -67,6 +67,15 @@ def default_tolerances(**over) -> HpTolerances:
     return t
 
 
+def default_tolerances_dd(**over) -> HpTolerances:
+    """The double-double tracker's defaults (final Newton to 1e-26)."""
+    t = HpTolerances()
+    load().hp_default_tolerances_dd(ctypes.byref(t))
+    for k, v in over.items():
+        setattr(t, k, v)
+    return t
+
+
 def path_count(system) -> int:
     return int(load().hp_path_count(ctypes.byref(_SysView(system).c)))
 
@@ -175,6 +184,24 @@ class Context:
                                      _ptr(start), P, _c64(gamma), ctypes.byref(tol), _ptr(ends),
                                      _ptr(st), _ptr(sts), _MODES[mode]))
         return ends, st, sts
+
+    def track_paths_dd(self, system, gamma, n_paths=None, tol=None, stats=True, start=None):
+        """The double-double tracker (hp_track_paths_dd).  Returns
+        (endpoints_hi, endpoints_lo complex [P, n], status, stats)."""
+        v = _SysView(system)
+        if start is not None:
+            start = np.ascontiguousarray(start, dtype=np.complex128).reshape(-1, v.n)
+            P = int(start.shape[0])
+        else:
+            P = path_count(system) if n_paths is None else int(n_paths)
+        hi = np.zeros((P, v.n), np.complex128)
+        lo = np.zeros((P, v.n), np.complex128)
+        st = np.full(P, -1, np.int32)
+        sts = np.zeros(P, STATS_DTYPE) if stats else None
+        tol = tol or default_tolerances_dd()
+        check(self._L.hp_track_paths_dd(self.handle, ctypes.byref(v.c), _ptr(start), P, _c64(gamma),
+                                        ctypes.byref(tol), _ptr(hi), _ptr(lo), _ptr(st), _ptr(sts)))
+        return hi, lo, st, sts
 
     def track_batch(self, systems, gammas, tol=None, stats=True):
         """Many systems in one persistent launch.  Returns per-system lists of

@@ -26,7 +26,7 @@ EXPORTED = [
     "hp_find_duplicates", "hp_solve", "hp_server_create", "hp_server_submit", "hp_server_poll",
     "hp_server_wait", "hp_server_peak_bytes", "hp_server_destroy", "hp_spec_compile",
     "hp_find_duplicates_device", "hp_plan_solve_device", "hp_find_duplicates_device_static",
-    "hp_membership_test", "hp_cascade",
+    "hp_membership_test", "hp_cascade", "hp_track_paths_dd", "hp_default_tolerances_dd",
 ]
 
 
@@ -118,6 +118,9 @@ def load():
             "hp_plan_solve_device": (ctypes.c_int, [vp, vp, vp, vp, P(i64), P(i64), vp]),
             "hp_membership_test": (ctypes.c_int, [vp, P(HpSystem), i32, vp, i64, vp, i32,
                                                   P(HpTolerances), ctypes.c_double, vp, vp, vp]),
+            "hp_track_paths_dd": (ctypes.c_int, [vp, P(HpSystem), vp, i64, c64, P(HpTolerances),
+                                                 vp, vp, vp, vp]),
+            "hp_default_tolerances_dd": (None, [P(HpTolerances)]),
             "hp_cascade": (ctypes.c_int, [vp, P(HpSystem), i32, vp, P(HpTolerances),
                                           ctypes.c_double, P(HpCascadeStage), vp, vp, i64,
                                           P(i64)]),

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libhomotopy.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["tracker.hip", "lanes.hip", "dense.hip", "dense11.hip", "dense12.hip", "endgame.hip",
-           "dedup.hip", "dedup_static.hip", "hp_host.cpp", "hp_jit.cpp"]
+           "dedup.hip", "dedup_static.hip", "ddtrack.hip", "hp_host.cpp", "hp_jit.cpp"]
 # headers the run-time specialised kernels are compiled with (hiprtc)
 JIT_HEADERS = [("homotopy.h", os.path.join(ROOT, "include", "homotopy.h")),
                ("hp_internal.hpp", os.path.join(CSRC, "hp_internal.hpp")),

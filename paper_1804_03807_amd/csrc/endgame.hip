@@ -36,59 +36,12 @@
 #include "lane_track.hpp"
 #include "reg_lu.hpp"
 
-// The error-free transformations below are exact only if every sum and
-// product is rounded on its own: no multiply-add may be contracted into a
-// fused one behind the code's back (hipcc contracts across statements by
-// default).  The fused products that are meant are written as fma().
-#pragma clang fp contract(off)
+#include "dd_arith.hpp"  // switches floating-point contraction off for this file
 
 namespace hp {
 namespace {
 
 constexpr int kRefine = 2;  // double-double Newton iterations
-
-// ---- double-double: the value hi + lo, |lo| <= ulp(hi) / 2 -------------
-struct dd {
-  double hi, lo;
-};
-struct cdd {
-  dd re, im;
-};
-
-// s + e = a + b exactly (Knuth's branch-free two-sum)
-__device__ __forceinline__ dd two_sum(double a, double b) {
-  const double s = a + b;
-  const double v = s - a;
-  return {s, (a - (s - v)) + (b - v)};
-}
-// s + e = a + b exactly, for |a| >= |b| (Dekker)
-__device__ __forceinline__ dd quick_two_sum(double a, double b) {
-  const double s = a + b;
-  return {s, b - (s - a)};
-}
-// sum of two double-double values, both parts added error-free
-__device__ __forceinline__ dd ddadd(dd a, dd b) {
-  dd s = two_sum(a.hi, b.hi);
-  const dd t = two_sum(a.lo, b.lo);
-  s = quick_two_sum(s.hi, s.lo + t.hi);
-  return quick_two_sum(s.hi, s.lo + t.lo);
-}
-__device__ __forceinline__ dd ddneg(dd a) { return {-a.hi, -a.lo}; }
-// product; the exact product of the high parts from one fused multiply-add,
-// the cross terms in double, lo * lo dropped
-__device__ __forceinline__ dd ddmul(dd a, dd b) {
-  const double p = a.hi * b.hi;
-  const double e = fma(a.hi, b.hi, -p);
-  return quick_two_sum(p, e + (a.hi * b.lo + a.lo * b.hi));
-}
-__device__ __forceinline__ cdd cddadd(cdd a, cdd b) { return {ddadd(a.re, b.re), ddadd(a.im, b.im)}; }
-__device__ __forceinline__ cdd cddmul(cdd a, cdd b) {
-  return {ddadd(ddmul(a.re, b.re), ddneg(ddmul(a.im, b.im))),
-          ddadd(ddmul(a.re, b.im), ddmul(a.im, b.re))};
-}
-__device__ __forceinline__ cdd to_cdd(cd z) { return {{z.re, 0.0}, {z.im, 0.0}}; }
-// the nearest complex double
-__device__ __forceinline__ cd round_cd(cdd z) { return {z.re.hi + z.re.lo, z.im.hi + z.im.lo}; }
 
 // ---- terms ---------------------------------------------------------------
 // The end game's copy of a term: coefficient, and the exponent of variable j

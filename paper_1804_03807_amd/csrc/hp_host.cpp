@@ -1198,6 +1198,96 @@ int hp_track_paths(hp_context *ctx, const hp_system *f, const hp_system *g, cons
   return HP_OK;
 }
 
+void hp_default_tolerances_dd(hp_tolerances *t) {
+  if (!t) return;
+  hp_default_tolerances(t);
+  t->tol_final = 1e-26;
+}
+
+int hp_track_paths_dd(hp_context *ctx, const hp_system *f, const hp_c64 *start, int64_t n_paths,
+                      hp_c64 gamma, const hp_tolerances *tol, hp_c64 *endpoints_hi,
+                      hp_c64 *endpoints_lo, int32_t *status, hp_path_stats *stats) {
+  if (!ctx) return fail(HP_E_INVALID_ARG, "context is NULL");
+  if (n_paths < 0 || (n_paths > 0 && (!endpoints_hi || !endpoints_lo || !status)))
+    return fail(HP_E_INVALID_ARG, "bad outputs");
+  int rc = check_tol(tol);
+  if (rc) return rc;
+  if (!std::isfinite(gamma.re) || !std::isfinite(gamma.im) || (gamma.re == 0 && gamma.im == 0))
+    return fail(HP_E_INVALID_ARG, "gamma must be finite and nonzero");
+  SysInfo info;
+  if ((rc = check_system(f, info))) return rc;
+  const int n = f->n;
+  if (!start && n_paths > info.paths)
+    return fail(HP_E_INVALID_ARG, "n_paths exceeds the number of total-degree paths");
+  if (start)
+    for (int64_t i = 0; i < n_paths * n; ++i)
+      if (!std::isfinite(start[i].re) || !std::isfinite(start[i].im))
+        return fail(HP_E_INVALID_ARG, "start points must be finite");
+  hp_tolerances T;
+  if (tol) T = *tol;
+  else hp_default_tolerances_dd(&T);
+  const double t0 = now_ms();
+  HIP_TRY(hipSetDevice(ctx->device));
+  ctx->last = hp_timing{};
+  if (n_paths == 0) return HP_OK;
+  DevBuf dstart;
+  if (start) {
+    if ((rc = dstart.alloc((size_t)n_paths * n * sizeof(hp_c64)))) return rc;
+    HIP_TRY(hipMemcpy(dstart.p, start, (size_t)n_paths * n * sizeof(hp_c64), hipMemcpyHostToDevice));
+  }
+  Packed P;
+  pack_append(P, f, info, gamma, n_paths, 0, 0, nullptr, nullptr, 0,
+              start ? dstart.as<double2>() : nullptr);
+  DevTables dev;
+  if ((rc = dev.upload(P, ctx->stream))) return rc;
+  DevBuf e, elo, st, sts;
+  if ((rc = e.alloc((size_t)n_paths * n * sizeof(hp_c64))) ||
+      (rc = elo.alloc((size_t)n_paths * n * sizeof(hp_c64))) ||
+      (rc = st.alloc((size_t)n_paths * sizeof(int32_t))) ||
+      (stats && (rc = sts.alloc((size_t)n_paths * sizeof(hp_path_stats)))))
+    return rc;
+  KArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.sys = dev.sys.as<DevSys>();
+  a.n_systems = 1;
+  a.tcoef = dev.tcoef.as<double2>();
+  a.tmeta = dev.tmeta.as<uint4>();
+  a.eqp = dev.kp.as<int32_t>();
+  a.roots = dev.roots.as<double2>();
+  a.qhead = dev.qhead.as<unsigned long long>();
+  a.endpoints = e.as<double2>();
+  a.endpoints_lo = elo.as<double2>();
+  a.status = st.as<int32_t>();
+  a.stats = stats ? sts.as<hp_path_stats>() : nullptr;
+  a.tol = dev_tol(T);
+  int per_cu = 0;
+  HIP_TRY((hipError_t)hp_ddtrack_per_cu(n, &per_cu));
+  if (per_cu < 1) return fail(HP_E_DEVICE, "double-double kernel does not fit on a compute unit");
+  const int64_t per_wave = hp::kLanes / n;
+  const int64_t groups = std::min<int64_t>((int64_t)ctx->cus * per_cu,
+                                           std::max<int64_t>(1, (n_paths + per_wave - 1) / per_wave));
+  HIP_TRY(hipMemsetAsync(dev.qhead.p, 0, sizeof(unsigned long long), ctx->stream));
+  HIP_TRY(hipEventRecord(ctx->ev0, ctx->stream));
+  HIP_TRY((hipError_t)hp_launch_ddtrack(n, a, (int)groups, ctx->stream));
+  HIP_TRY(hipEventRecord(ctx->ev1, ctx->stream));
+  HIP_TRY(hipEventSynchronize(ctx->ev1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  HIP_TRY(hipMemcpy(endpoints_hi, e.p, (size_t)n_paths * n * sizeof(hp_c64), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(endpoints_lo, elo.p, (size_t)n_paths * n * sizeof(hp_c64), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(status, st.p, (size_t)n_paths * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (stats)
+    HIP_TRY(hipMemcpy(stats, sts.p, (size_t)n_paths * sizeof(hp_path_stats), hipMemcpyDeviceToHost));
+  ctx->last.kernel_ms = ms;
+  ctx->last.launches = 1;
+  ctx->last.groups = (int32_t)groups;
+  ctx->last.paths_per_wave = (int32_t)per_wave;
+  ctx->last.max_n = n;
+  ctx->last.variant = 500 + n;
+  ctx->last.total_ms = now_ms() - t0;
+  return HP_OK;
+}
+
 int hp_batch_layout(const hp_system *fs, int32_t n_systems, int64_t *path_offsets,
                     int64_t *x_offsets) {
   if (!fs || n_systems < 1 || !path_offsets || !x_offsets)

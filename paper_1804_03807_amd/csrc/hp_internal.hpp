@@ -111,6 +111,7 @@ struct KArgs {
   int32_t stage;         // group kernels: copy term tables of <= kMaxStagedTerms into LDS
   PlainState ps;         // plain mode only
   const double2 *dcoef;  // dense coefficient tables (dense kernel)
+  double2 *endpoints_lo; // low parts of the endpoints (double-double tracker)
 };
 
 enum Mode : int32_t { M_IDLE = 0, M_TRACK = 1, M_FINAL = 2 };
@@ -200,7 +201,7 @@ inline size_t lanes_lds_bytes(int n, int pw, int emax) {
 }  // namespace hp
 
 // Kernel launchers (tracker.hip, lanes.hip, dense.hip, dense11.hip, dense12.hip,
-// endgame.hip, dedup.hip, dedup_static.hip).  Return a hipError_t
+// endgame.hip, dedup.hip, dedup_static.hip, ddtrack.hip).  Return a hipError_t
 // value.
 extern "C++" {
 // general: the systems use a general start system or explicit start points
@@ -239,6 +240,10 @@ int hp_dup_static_scan(int device, hp::DupArgs a, long long *n_pairs, std::strin
 int hp_launch_scatter(const long long *ids, long long m, int n, const double2 *e_src,
                       const int32_t *s_src, const hp_path_stats *st_src, double2 *e_dst,
                       int32_t *s_dst, hp_path_stats *st_dst, void *stream);
+// Double-double tracker (ddtrack.hip): one system of n unknowns, n lanes
+// per path; resident workgroups per CU of its n instantiation.
+int hp_launch_ddtrack(int n, const hp::KArgs &a, int groups, void *stream);
+int hp_ddtrack_per_cu(int n, int *out);
 // End game of the paths of systems with n unknowns: blk[b] = (system, first
 // queue index) of block b (64 paths each), or blk == nullptr for one system
 // (system 0, block b from queue index 64 b).
