@@ -271,16 +271,17 @@ def serving_run(ctx, n_requests, budget_bytes, calib=200, load=0.8):
             conv += int((st == 0).sum())
         makespan = time.perf_counter() - t0
         peak = srv.peak_bytes()
+        info = srv.info()
         srv.close()
-        return np.asarray(lat), makespan, peak, conv
+        return np.asarray(lat), makespan, peak, conv, info
 
     sat = reqs[:calib]
-    lat_sat, span_sat, _, _ = run(sat, np.zeros(len(sat)))
+    lat_sat, span_sat, _, _, _ = run(sat, np.zeros(len(sat)))
     rate_sat = len(sat) / span_sat
     lam = load * rate_sat
     main = reqs[:n_requests]
     paths = sum(s.bezout() for s, _ in main)
-    lat, span, peak, conv = run(main, W.poisson_arrivals(len(main), lam))
+    lat, span, peak, conv, info = run(main, W.poisson_arrivals(len(main), lam))
     return {"requests": len(main), "paths": paths, "converged": conv,
             "spec_compile_ms": compile_ms,
             "sample": f"request ids 0..{len(main) - 1} of the seeded stream (seed 4); "
@@ -291,7 +292,11 @@ def serving_run(ctx, n_requests, budget_bytes, calib=200, load=0.8):
                            "p99": float(np.percentile(lat, 99))},
             "saturated_latency_ms": {"p50": float(np.percentile(lat_sat, 50)),
                                      "p99": float(np.percentile(lat_sat, 99))},
-            "hbm_budget_bytes": budget_bytes, "peak_resident_bytes": peak}
+            "hbm_budget_bytes": budget_bytes, "peak_resident_bytes": peak,
+            "slicing": {"slice_ms": info["slice_ms"], "epochs": info["epochs"],
+                        "epoch_ms_mean": info["epoch_ms_mean"], "epoch_ms_max": info["epoch_ms_max"],
+                        "carried_entries": info["carried"],
+                        "step_budget_range": [info["budget_min"], info["budget_max"]]}}
 
 
 def cpu_baseline(system, gamma, target_paths=20000):
@@ -315,6 +320,14 @@ def cpu_baseline(system, gamma, target_paths=20000):
                      f"({len(ids)} of {total} paths), {threads} threads, {dt:.1f} s",
            "one_thread_value": len(ids1) / dt1}
     return rec, (ids, e, st)
+
+
+T_START = time.perf_counter()
+
+
+def progress(msg):
+    """One line on stderr as each stage of the run ends (stdout keeps the JSON line)."""
+    print(f"[bench {time.perf_counter() - T_START:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -360,12 +373,14 @@ def main():
     t0 = time.perf_counter()
     plan = ctx.plan(system, gamma)  # writes and compiles the specialised kernel
     plan_ms = (time.perf_counter() - t0) * 1e3
+    progress(f"plan for {args.workload} ready ({plan_ms:.0f} ms)")
     if args.variant:
         plan.set_variant(args.variant)
     stream = torch.cuda.current_stream()
     elapsed, wall, kms, egms, post, pairs, (e, st, sts) = plan_solve_steps(
         ctx, plan, P, args.steps, args.warmup, stream)
     timing = ctx.last_timing()
+    progress(f"{args.steps} timed steps done ({elapsed * 1e3 / args.steps:.1f} ms/step)")
 
     status = st.cpu().numpy()
     stats = hp.Plan.stats_to_numpy(sts)
@@ -422,6 +437,7 @@ def main():
 
     if not args.no_cpu:
         rec, (ids, e_o, s_o) = cpu_baseline(system, gamma)
+        progress("oracle baseline done")
         e_g = hp.Plan.endpoints_to_numpy(e)[ids]
         par = compare_paths(e_g, status[ids], e_o, s_o)
         rec["parity"] = {"paths": int(len(ids)), "converged_flag_differences": int(len(par.flips)),
@@ -437,14 +453,20 @@ def main():
 
     if not args.no_extra:
         out["cyclic8"] = batched_vs_plain(ctx, "cyclic8")
+        progress("cyclic-8 batched and plain done")
         out["double_double_cyclic8"] = dd_run(ctx, out["cyclic8"]["batched_ms"])
+        progress("double-double cyclic-8 done")
         out["dense5"] = batched_vs_plain(ctx, "dense5", steps=20)
+        progress("dense n = 5 done")
         out["batch256"] = batch_run(ctx)
+        progress("256-system batch done")
         out["continuation_cyclic8"] = continuation_run(ctx)
+        progress("continuation done")
 
     if args.serving_requests > 0:
         out["serving"] = serving_run(ctx, args.serving_requests,
                                      int(args.serving_budget_gib * (1 << 30)))
+        progress("serving done")
 
     print(json.dumps(out), flush=True)
     ctx.close()

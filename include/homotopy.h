@@ -229,11 +229,13 @@ void hp_plan_destroy(hp_plan *plan);
 int hp_plan_set_variant(hp_plan *plan, int32_t variant);
 
 /* Writes and compiles the kernel specialised to f (variant 300 + n) for
- * gfx950 without loading it, so it needs no device; *code_bytes = size of
- * the code object.  The code object is kept for the process (and written to
- * the directory $HP_JIT_CACHE names, when set, where later processes find
- * it), so plans for systems with f's support skip the compilation: a caller
- * can compile ahead of the first solve.  HP_E_UNSUPPORTED_N when f cannot have one (n > 10, or more
+ * gfx950 without loading it, so it needs no device, in its two forms: the
+ * plans' and the server's (which suspends and resumes paths);
+ * *code_bytes = size of the plans' code object.  The code objects are kept
+ * for the process (and written to the directory $HP_JIT_CACHE names, when
+ * set, where later processes find them), so plans and servers for systems
+ * with f's support skip the compilation: a caller can compile ahead of the
+ * first solve.  HP_E_UNSUPPORTED_N when f cannot have one (n > 10, or more
  * than 1024 factors in all), HP_E_DEVICE when compilation fails (compiler log
  * in hp_last_error), HP_E_INVALID_ARG for a malformed system. */
 int hp_spec_compile(const hp_system *f, int64_t *code_bytes);
@@ -366,24 +368,57 @@ int hp_cascade(hp_context *ctx, const hp_system *e, int32_t k, const hp_c64 *gam
  * own stream), in the manner of the paper's pipeline in which tracking of
  * the paths of one piece of work starts while other pieces are still being
  * produced (Section 2.2, Figure 1: a producer stage feeding tracking
- * threads).  The server allocates an output arena of at most
- * hbm_budget_bytes: path slots of HP_MAX_N endpoint coordinates + status +
- * stats (236 B each).  Requests (one system each, all its total-degree
- * paths) are admitted in arrival order while their slot regions fit;  a
- * request larger than the free room gets a region of at least 4096 slots
- * and runs chunk by chunk.  Each round of work packs the next chunk of every
+ * threads), with the paths tracked independently of one another (Section 1),
+ * which is what lets a path stop and resume between launches.  The server
+ * allocates an arena of at most hbm_budget_bytes: path slots of HP_MAX_N
+ * endpoint coordinates + status + stats (236 B each).  Requests (one system
+ * each, all its total-degree paths) are admitted in arrival order while
+ * their slot regions fit (at most 262,144 slots each; a request with more
+ * paths, or one larger than the free room, which gets at least 4096 slots,
+ * reuses the slots of its finished paths).
+ * The work goes in epochs.  Each epoch packs a queue of paths of every
  * admitted request (same tolerances) into one multi-system persistent
  * launch per kernel family (the kernel specialised to a support, shared by
- * the requests of that support; the dense kernel; the group kernels), so
+ * the requests of that support; the dense kernels; the group kernels), so
  * that requests that arrive while others run share the following launches
- * and each request runs on the kernel it would get alone.  HP_E_BUDGET if
- * the budget holds fewer than 4096 slots. */
+ * and each request runs on the kernel it would get alone.  On the
+ * specialised and dense kernels each wavefront stops after a budget of
+ * steps per epoch: its paths in flight are suspended in their slots (the
+ * accepted point, t, the step size and the counters) and resume from there
+ * in a later epoch, bit for bit as if never stopped.  The budget of each
+ * family adapts so that its epoch's kernel time is about the slice time
+ * (hp_server_set_slice), which bounds how long a new request waits before
+ * its paths start.  The group kernels run their queue to the end.
+ * HP_E_BUDGET if the budget holds fewer than 4096 slots. */
 int hp_server_create(hp_context *ctx, size_t hbm_budget_bytes, hp_server **out);
+/* Time slicing of the specialised and dense kernel families: slice_ms is the
+ * target kernel time of an epoch (default 20 ms), fixed_steps > 0 replaces
+ * the adaptive budget by that many steps per wavefront and epoch, and
+ * slice_ms = fixed_steps = 0 runs every queue to the end.  Results do not
+ * depend on these settings.  Takes effect from the next epoch; HP_E_INVALID_ARG
+ * for a negative or non-finite value. */
+int hp_server_set_slice(hp_server *srv, double slice_ms, int32_t fixed_steps);
+typedef struct hp_server_info {
+  int64_t epochs;        /* epochs run so far                                */
+  int64_t carried;       /* queue entries left unfinished at the end of an
+                            epoch (suspended or not started), summed          */
+  double epoch_ms_max;   /* longest epoch, wall time from queue build to the
+                            end of the harvest                               */
+  double epoch_ms_mean;
+  double slice_ms;       /* settings of hp_server_set_slice                  */
+  int32_t fixed_steps;
+  int32_t budget_min;    /* smallest and largest adaptive step budget of the
+                            families seen (0: none yet)                      */
+  int32_t budget_max;
+  int32_t pad;
+  uint64_t peak_bytes;   /* as hp_server_peak_bytes                          */
+} hp_server_info;
+int hp_server_info_get(hp_server *srv, hp_server_info *out);
 /* Queues a request; the system is copied.  *req_id receives its id.  A
- * sparse system with n <= 10 runs on the kernel specialised to its support,
- * which this call compiles (seconds) the first time that support is seen in
- * the process unless hp_spec_compile did so ahead; the calling thread's
- * current HIP device becomes the server's. */
+ * sparse system with n <= 10 runs on the kernel specialised to its support;
+ * the first time that support is seen in the process the server compiles it
+ * (seconds) on its compile thread, not in this call, and the request waits
+ * for it; the calling thread's current HIP device becomes the server's. */
 int hp_server_submit(hp_server *srv, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
                      int64_t *req_id);
 /* *done = 1 once every path of the request has finished (non-blocking). */
@@ -393,11 +428,11 @@ int hp_server_poll(hp_server *srv, int64_t req_id, int32_t *done);
  * *latency_ms (nullable) receives completion time minus submission time. */
 int hp_server_wait(hp_server *srv, int64_t req_id, hp_c64 *endpoints, int32_t *status,
                    hp_path_stats *stats, double *latency_ms);
-/* Stops the worker; requests not yet finished end as failed.  No other
- * thread may be inside a call on srv (hp_server_wait included) while it
- * runs. */
 /* Peak bytes of arena slots held by admitted requests so far (<= budget). */
 int hp_server_peak_bytes(hp_server *srv, size_t *out);
+/* Stops the worker and the compile thread; requests not yet finished end as
+ * failed.  No other thread may be inside a call on srv (hp_server_wait
+ * included) while it runs. */
 void hp_server_destroy(hp_server *srv);
 
 #ifdef __cplusplus

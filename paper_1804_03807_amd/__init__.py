@@ -412,6 +412,16 @@ class Server:
         check(self._L.hp_server_peak_bytes(self.handle, ctypes.byref(v)))
         return int(v.value)
 
+    def set_slice(self, slice_ms: float, fixed_steps: int = 0) -> None:
+        """Epoch kernel-time target (ms) of the sliced kernel families, or a
+        fixed step budget per wavefront and epoch; 0, 0 runs queues to the end."""
+        check(self._L.hp_server_set_slice(self.handle, float(slice_ms), int(fixed_steps)))
+
+    def info(self) -> dict:
+        v = _lib.HpServerInfo()
+        check(self._L.hp_server_info_get(self.handle, ctypes.byref(v)))
+        return {k: getattr(v, k) for k, _ in v._fields_ if k != "pad"}
+
     def close(self):
         if self.handle:
             self._L.hp_server_destroy(self.handle)

@@ -27,6 +27,7 @@ EXPORTED = [
     "hp_server_wait", "hp_server_peak_bytes", "hp_server_destroy", "hp_spec_compile",
     "hp_find_duplicates_device", "hp_plan_solve_device", "hp_find_duplicates_device_static",
     "hp_membership_test", "hp_cascade", "hp_track_paths_dd", "hp_default_tolerances_dd",
+    "hp_server_set_slice", "hp_server_info_get",
 ]
 
 
@@ -45,6 +46,14 @@ class HpTolerances(ctypes.Structure):
                 ("h_init", ctypes.c_double), ("h_min", ctypes.c_double),
                 ("h_max", ctypes.c_double), ("max_steps", ctypes.c_int32),
                 ("max_newton", ctypes.c_int32), ("max_newton_final", ctypes.c_int32)]
+
+
+class HpServerInfo(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int64), ("carried", ctypes.c_int64),
+                ("epoch_ms_max", ctypes.c_double), ("epoch_ms_mean", ctypes.c_double),
+                ("slice_ms", ctypes.c_double), ("fixed_steps", ctypes.c_int32),
+                ("budget_min", ctypes.c_int32), ("budget_max", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("peak_bytes", ctypes.c_uint64)]
 
 
 class HpCascadeStage(ctypes.Structure):
@@ -133,6 +142,8 @@ def load():
             "hp_server_wait": (ctypes.c_int, [vp, i64, vp, vp, vp, P(ctypes.c_double)]),
             "hp_server_peak_bytes": (ctypes.c_int, [vp, P(ctypes.c_size_t)]),
             "hp_server_destroy": (None, [vp]),
+            "hp_server_set_slice": (ctypes.c_int, [vp, ctypes.c_double, i32]),
+            "hp_server_info_get": (ctypes.c_int, [vp, P(HpServerInfo)]),
             "hp_spec_compile": (ctypes.c_int, [P(HpSystem), P(i64)]),
         }
         for name, (res, args) in sig.items():

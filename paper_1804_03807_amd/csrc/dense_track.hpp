@@ -20,7 +20,7 @@
 // the end of Section 2.1 for independent paths).
 //
 // Kernels: k_dense (dense.hip) tracks every system of a launch with
-// n <= kDenseMaxN, dispatching per system on n; k_dense11 and k_dense12
+// n <= kDenseMaxN, dispatching per system on n; k_dense_n<11> and k_dense_n<12>
 // (dense11.hip, dense12.hip: translation units of their own, so that the
 // largest instantiations compile in parallel) track systems of exactly that
 // n.
@@ -161,10 +161,64 @@ struct Dense : LaneTrack<Dense<N>, N, RkLds<N>> {
   }
 };
 
-template <int N>
-__device__ __forceinline__ void dense_drain(const KArgs &a, int s, lds_char *rk) {
+// true when the launch's step budget stopped the wavefront (Sliced)
+template <int N, bool Sliced>
+__device__ __forceinline__ bool dense_drain(const KArgs &a, int s, lds_char *rk, int &wave_steps) {
   Dense<N> tr(a, rk);
-  lane_drain(a, tr, s);
+  return lane_drain<Sliced>(a, tr, s, wave_steps);
+}
+
+// Persistent kernel over every system of the launch (n <= kDenseMaxN, mixed
+// n in one launch): a wavefront drains the systems' refill queues one after
+// another and runs the tracker instantiated for each system's n
+// (wave-uniform).  Sliced: the serving form (suspend and resume, see
+// lane_drain).
+template <bool Sliced>
+__global__ void __launch_bounds__(64) k_dense(KArgs a) {
+  __shared__ __align__(16) char rk[RkLds<kDenseMaxN>::kBytes];
+  lds_char *lds = (lds_char *)rk;
+  const int first_sys = blockIdx.x % a.n_systems;
+  int wave_steps = 0;
+  for (int v = 0; v < a.n_systems; ++v) {
+    const int s = (first_sys + v) % a.n_systems;
+    bool stop = false;
+    switch (as_const(a.sys)[s].n) {
+      case 1: stop = dense_drain<1, Sliced>(a, s, lds, wave_steps); break;
+      case 2: stop = dense_drain<2, Sliced>(a, s, lds, wave_steps); break;
+      case 3: stop = dense_drain<3, Sliced>(a, s, lds, wave_steps); break;
+      case 4: stop = dense_drain<4, Sliced>(a, s, lds, wave_steps); break;
+      case 5: stop = dense_drain<5, Sliced>(a, s, lds, wave_steps); break;
+      case 6: stop = dense_drain<6, Sliced>(a, s, lds, wave_steps); break;
+      case 7: stop = dense_drain<7, Sliced>(a, s, lds, wave_steps); break;
+      case 8: stop = dense_drain<8, Sliced>(a, s, lds, wave_steps); break;
+      case 9: stop = dense_drain<9, Sliced>(a, s, lds, wave_steps); break;
+      case 10: stop = dense_drain<10, Sliced>(a, s, lds, wave_steps); break;
+      default: break;  // the host admits n <= kDenseMaxN only
+    }
+    if (stop) return;  // the step budget is spent
+  }
+}
+
+// The same for systems of exactly n = N (11, 12), one instantiation per
+// translation unit so that they compile side by side.
+template <int N, bool Sliced>
+__global__ void __launch_bounds__(64) k_dense_n(KArgs a) {
+  __shared__ __align__(16) char rk[RkLds<N>::kBytes];
+  const int first_sys = blockIdx.x % a.n_systems;
+  int wave_steps = 0;
+  for (int v = 0; v < a.n_systems; ++v)
+    if (dense_drain<N, Sliced>(a, (first_sys + v) % a.n_systems, (lds_char *)rk, wave_steps)) return;
+}
+
+// Launch and occupancy of one instantiation (hipError_t values).
+template <class K>
+int dense_launch(K kernel, const KArgs &a, int groups, void *stream) {
+  hipLaunchKernelGGL(kernel, dim3(groups), dim3(64), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+template <class K>
+int dense_per_cu(K kernel, int *out) {
+  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(out, kernel, 64, 0);
 }
 
 }  // namespace hp

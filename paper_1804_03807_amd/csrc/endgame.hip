@@ -125,10 +125,13 @@ __global__ void __launch_bounds__(64) k_endgame(KArgs a, const int2 *blk) {
   }
   cptr<DevSys> sp = as_const(a.sys) + s;
   if (q >= sp->n_paths) return;
-  const long long o = sp->out_path_base + q;
+  // output slot of queue index q (serving keeps paths in slots of an arena)
+  const long long *slots = (const long long *)sp->slots;
+  const long long so = slots ? slots[q] : q;
+  const long long o = sp->out_path_base + so;
   const int st0 = a.status[o];
   if (st0 != HP_CONVERGED && st0 != HP_FAILED_NEWTON_T1) return;
-  double2 *xe = a.endpoints + sp->out_x_base + q * N;
+  double2 *xe = a.endpoints + sp->out_x_base + so * N;
   cd x[N];
   bool finite = true;
   sfor<0, N>([&](auto ii) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <climits>
@@ -480,7 +481,8 @@ bool kv_decode(int code, Kv &k) {
 }
 
 // Dense kernel for the systems of P: 400 (k_dense) when every n <= kDenseMaxN,
-// 400 + n (k_dense11, k_dense12) when they all have that one larger n, else 0.
+// 400 + n (k_dense_n<11>, k_dense_n<12>) when they all have that one larger n,
+// else 0.
 int dense_code_for(const Packed &P) {
   if (!P.dense_ok) return 0;
   if (P.nl <= hp::kDenseMaxN) return kDenseCode;
@@ -732,16 +734,23 @@ size_t kv_lds(const Kv &k, const Packed &P) {
 // the systems of P.  Group kernels stage small term tables in LDS unless
 // that lowers the number of resident workgroups.
 int kv_occupancy(hp_context *ctx, const Kv &k, const Packed &P, size_t *lds, int *per_cu,
-                 int *stage) {
+                 int *stage, bool sliced = false) {
   *stage = 0;
   if (k.spec) {
     *lds = 0;
     HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k.sm->persistent, hp::kLanes, 0));
   } else if (k.dense) {
     *lds = 0;
-    if (k.code == kDenseCode) HIP_TRY((hipError_t)hp_dense_per_cu(per_cu));
-    else if (k.nmax == 11) HIP_TRY((hipError_t)hp_dense11_per_cu(per_cu));
-    else HIP_TRY((hipError_t)hp_dense12_per_cu(per_cu));
+    if (sliced) {
+      if (k.code == kDenseCode) HIP_TRY((hipError_t)hp_dense_sliced_per_cu(per_cu));
+      else HIP_TRY((hipError_t)hp_dense_wide_sliced_per_cu(k.nmax, per_cu));
+    } else if (k.code == kDenseCode) {
+      HIP_TRY((hipError_t)hp_dense_per_cu(per_cu));
+    } else if (k.nmax == 11) {
+      HIP_TRY((hipError_t)hp_dense11_per_cu(per_cu));
+    } else {
+      HIP_TRY((hipError_t)hp_dense12_per_cu(per_cu));
+    }
   } else if (k.lanes) {
     *lds = kv_lds(k, P);
     int rc = check_lds(ctx, *lds);
@@ -792,11 +801,16 @@ int launch_endgame(const DevTables &dev, const Packed &P, const KArgs &a, int64_
 }
 
 // Persistent launch over the systems in `dev` (already uploaded), followed
-// by the end game of its paths.
+// by the end game of its paths.  step_budget >= 0 selects the serving form
+// of the specialised (the module must be one) and dense kernels, with that
+// many steps per wavefront (0: no limit); -1 the plain form.
 int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv &k,
                       const hp_tolerances &tol, int64_t total_paths, hp_c64 *endpoints,
                       int32_t *status, hp_path_stats *stats, hipStream_t s, int *groups_out,
-                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, hipEvent_t em = nullptr) {
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, hipEvent_t em = nullptr,
+                      int32_t step_budget = -1) {
+  const bool sliced = step_budget >= 0;
+  if (sliced && !k.spec && !k.dense) return fail(HP_E_INVALID_ARG, "no serving form of this kernel");
   if (!e0) {  // the context's events: e0 .. em the tracking kernel, em .. e1 the end game
     e0 = ctx->ev0;
     e1 = ctx->ev1;
@@ -807,7 +821,7 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
     return fail(HP_E_INVALID_ARG, "kernel variant does not match the systems' n");
   size_t lds = 0;
   int per_cu = 0, stage = 0;
-  int rc = kv_occupancy(ctx, k, P, &lds, &per_cu, &stage);
+  int rc = kv_occupancy(ctx, k, P, &lds, &per_cu, &stage, sliced);
   if (rc) return rc;
   // enough wavefronts to hold every path once, at most a full device
   const int64_t per_wave = (k.lanes || k.spec || k.dense) ? k.pw : hp::kLanes / std::max(1, P.nl);
@@ -828,12 +842,16 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
   a.tol = dev_tol(tol);
   a.stage = stage;
   a.dcoef = dev.dcoef.as<double2>();
+  a.step_budget = sliced ? step_budget : 0;
   HIP_TRY(hipMemsetAsync(dev.qhead.p, 0, P.sys.size() * sizeof(unsigned long long), s));
   HIP_TRY(hipEventRecord(e0, s));
   if (k.spec) {
     void *params[] = {&a};
     HIP_TRY(hipModuleLaunchKernel(k.sm->persistent, (unsigned)groups, 1, 1, hp::kLanes, 1, 1, 0, s,
                                   params, nullptr));
+  } else if (k.dense && sliced) {
+    if (k.code == kDenseCode) HIP_TRY((hipError_t)hp_launch_dense_sliced(a, (int)groups, s));
+    else HIP_TRY((hipError_t)hp_launch_dense_wide_sliced(k.nmax, a, (int)groups, s));
   } else if (k.dense) {
     if (k.code == kDenseCode) HIP_TRY((hipError_t)hp_launch_dense(a, (int)groups, s));
     else if (k.nmax == 11) HIP_TRY((hipError_t)hp_launch_dense11(a, (int)groups, s));
@@ -1109,10 +1127,12 @@ int hp_spec_compile(const hp_system *f, int64_t *code_bytes) {
   const DevSys &d = P.sys[0];
   if (!hp::spec_eligible(f->n, P.terms.data(), d.n_terms))
     return fail(HP_E_UNSUPPORTED_N, "system too large for a specialised kernel");
-  std::vector<char> code;
+  std::vector<char> code, serving;
   std::string log;
   rc = hp::spec_compile(hp::spec_source(f->n, d.deg, P.terms.data(), d.n_terms), code, log);
   if (rc) return fail(HP_E_DEVICE, "specialised kernel: " + log);
+  rc = hp::spec_compile(hp::spec_source(f->n, d.deg, P.terms.data(), d.n_terms, true), serving, log);
+  if (rc) return fail(HP_E_DEVICE, "specialised kernel (serving form): " + log);
   *code_bytes = (int64_t)code.size();
   return HP_OK;
 }
@@ -1910,23 +1930,40 @@ int hp_cascade(hp_context *ctx, const hp_system *e, int32_t k, const hp_c64 *gam
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Serving: continuous batching over the persistent tracker
+// Serving: continuous batching over the persistent tracker, in time slices
 // ---------------------------------------------------------------------------
 //
-// A worker thread owns a stream and an output arena in HBM of at most the
-// budget.  Requests are admitted in arrival order while their regions (path
-// slots of the arena) fit; a request whose outputs exceed the free room gets
-// a region for one chunk of its paths and runs chunk by chunk.
-// Every epoch packs the next chunk of each admitted request into one
-// multi-system persistent launch (one refill queue per chunk), so requests
-// that arrive while others run join at the next epoch and share launches.
-// After an epoch the finished chunks are copied to host memory; a request
-// whose last chunk finished is complete.
+// A worker thread owns a stream and an arena of path slots in HBM of at most
+// the budget.  Requests are admitted in arrival order while their regions
+// (slots of the arena, at most kEpochPaths per request) fit; a request with
+// more paths than its region reuses the slots of finished paths.
+// The work goes in epochs.  Every epoch packs, for each admitted request, a
+// queue of its paths (those suspended in the previous epoch first, then
+// paths not started yet, each holding a slot) into one multi-system
+// persistent launch per kernel family.  On the one-path-per-lane families
+// every wavefront stops after a budget of steps: its paths in flight are
+// suspended to their slots (accepted point, t, h, counters) and resume from
+// there in the next epoch, so an epoch's kernel time is bounded and a new
+// request waits at most about one slice before its paths start.  The
+// budget of each family is adapted so that its epochs take about the slice
+// time.  After the launches a harvest kernel compacts the finished paths of
+// the queues, which are copied to the requests' host results; their slots
+// go back to the requests' free lists.
+// Kernels specialised to a first-seen support are compiled on a thread of
+// their own, off the submitting thread; the request joins the queue once its
+// kernel is ready.
 
 namespace {
 
-constexpr int64_t kEpochPaths = 1 << 18;  // paths per epoch over all requests
+constexpr int64_t kEpochPaths = 1 << 18;  // queue entries per epoch over all requests
 constexpr int64_t kMinChunk = 4096;
+constexpr int32_t kInitialBudget = 64;  // steps per wavefront in a family's first slice
+constexpr int32_t kMinBudget = 4, kMaxBudget = 1 << 20;
+constexpr double kDefaultSliceMs = 20.0;
+
+struct Entry {
+  int64_t pid, slot;  // path id, slot in the request's region
+};
 
 struct Request {
   int64_t id = 0;
@@ -1943,14 +1980,29 @@ struct Request {
   std::vector<int32_t> status;
   std::vector<hp_path_stats> stats;
   // progress
-  int64_t next_path = 0;  // first path not yet handed to an epoch
+  int64_t next_path = 0;  // first path id not yet given a slot
   int64_t done_paths = 0;
-  // arena region (resident path outputs of one chunk)
+  std::vector<Entry> live;          // paths holding a slot, not finished (queue order)
+  std::vector<int64_t> free_slots;  // slots of the region holding no path
+  // arena region
   int64_t region_paths = 0;  // capacity in paths
   int64_t region_off = -1;   // offset in paths into the arena
   bool admitted = false, done = false, failed = false;
+  std::string error;
   int dense_code = 0;  // runs on this dense kernel (as it would alone), 0: not dense
   const hp::SpecModule *sm = nullptr;  // runs on the kernel specialised to its support
+  std::string spec_src;                // that kernel's source, until it is compiled
+  // this epoch's queue: entries qoff .. qoff + qlen - 1 of the epoch arrays,
+  // the first qtaken of them from live
+  int64_t qoff = 0, qlen = 0, qtaken = 0;
+
+  // family key: (300, module) for a specialised kernel, (dense code,
+  // nullptr) for a dense kernel, (0, nullptr) for the group kernels
+  std::pair<int, const void *> family() const {
+    return sm ? std::make_pair(300, (const void *)sm) : std::make_pair(dense_code, (const void *)nullptr);
+  }
+  // the group kernels run their queue to the end (no slot mapping, no suspension)
+  bool sliceable() const { return sm || dense_code; }
 };
 
 }  // namespace
@@ -1963,22 +2015,32 @@ struct hp_server {
   hp_context *ctx = nullptr;
   size_t budget = 0, resident = 0, peak = 0;
   hipStream_t stream = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipStream_t fam_stream[kFamilyStreams] = {};
-  hipEvent_t fam_ev[kFamilyStreams][2] = {};
+  std::vector<std::array<hipEvent_t, 2>> fam_ev;  // per family of an epoch
+  std::vector<std::unique_ptr<DevTables>> fam_dev;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::deque<std::shared_ptr<Request>> pending;
+  std::condition_variable cv_work, cv_done, cv_compile;
+  std::deque<std::shared_ptr<Request>> pending, to_compile;
   std::vector<std::shared_ptr<Request>> active;
   std::map<int64_t, std::shared_ptr<Request>> all;
   int64_t next_id = 1;
   bool stop = false;
   std::string error;
-  std::thread worker;
+  std::thread worker, compiler;
+  // slicing (under mu): slice time, fixed step budget (> 0 overrides the
+  // adaptive one), adaptive budget per family
+  double slice_ms = kDefaultSliceMs;
+  int32_t fixed_steps = 0;
+  std::map<std::pair<int, const void *>, int32_t> fam_budget;
+  // counters (under mu)
+  int64_t epochs = 0, carried = 0;
+  double epoch_ms_sum = 0.0, epoch_ms_max = 0.0;
   // arena: paths are slots of (endpoints up to HP_MAX_N, status, stats)
   DevBuf a_ends, a_status, a_stats;
   int64_t arena_paths = 0;
   std::vector<std::pair<int64_t, int64_t>> free_list;  // (offset, length) in paths
+  // epoch queues and harvest records
+  DevBuf q_ids, q_slots, c_path, c_xoff, c_n, r_entry, r_status, r_x, r_stats, r_count;
 
   int64_t largest_free() const {
     int64_t m = 0;
@@ -2016,13 +2078,13 @@ namespace {
 size_t slot_bytes() { return (size_t)HP_MAX_N * sizeof(hp_c64) + sizeof(int32_t) + sizeof(hp_path_stats); }
 
 // Admits pending requests in arrival order while the arena has room (called
-// with mu held).  A request gets a region for all of its paths if one is
-// free, else (when it is larger than the free room) a region of at least
-// kMinChunk paths that it fills chunk by chunk.
+// with mu held).  A request gets a region for all of its paths (at most
+// kEpochPaths) if one is free, else, when it is larger than the free room,
+// a region of at least kMinChunk paths whose slots its paths reuse.
 void admit(hp_server *S) {
   while (!S->pending.empty()) {
     auto &R = S->pending.front();
-    int64_t want = std::min<int64_t>(R->info.paths, S->arena_paths);
+    int64_t want = std::min(std::min<int64_t>(R->info.paths, S->arena_paths), kEpochPaths);
     const int64_t room = S->largest_free();
     if (room < want) {
       if (room < std::min<int64_t>(want, kMinChunk)) break;
@@ -2032,6 +2094,8 @@ void admit(hp_server *S) {
     if (off < 0) break;
     R->region_paths = want;
     R->region_off = off;
+    R->free_slots.resize((size_t)want);
+    for (int64_t k = 0; k < want; ++k) R->free_slots[(size_t)k] = want - 1 - k;  // pops 0, 1, ...
     R->admitted = true;
     S->resident += (size_t)want * slot_bytes();
     S->peak = std::max(S->peak, S->resident);
@@ -2040,37 +2104,95 @@ void admit(hp_server *S) {
   }
 }
 
+template <class T>
+int upload_vec(DevBuf &d, const std::vector<T> &h, hipStream_t s) {
+  int rc = d.alloc(std::max<size_t>(1, h.size()) * sizeof(T));
+  if (rc) return rc;
+  if (!h.empty()) HIP_TRY(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return HP_OK;
+}
+
 int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
   hp_context *ctx = S->ctx;
-  // chunk sizes: share the epoch among the admitted requests
+  double slice_ms;
+  int32_t fixed_steps;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    slice_ms = S->slice_ms;
+    fixed_steps = S->fixed_steps;
+  }
+  const bool sliced = fixed_steps > 0 || slice_ms > 0.0;
+  const double t_epoch = now_ms();
   // one launch has one tolerance set: take the requests that share the
   // oldest active request's tolerances; the others wait for a later epoch
   const hp_tolerances tol = batch[0]->tol;
   size_t same = 0;
   for (auto &R : batch) same += std::memcmp(&R->tol, &tol, sizeof(tol)) == 0;
   const int64_t share = std::max<int64_t>(kMinChunk, kEpochPaths / (int64_t)same);
-  // one launch per kernel family, each request on the family it runs on
-  // alone (its specialised kernel, the dense kernel or the group kernels),
-  // so that its result does not depend on the other requests of the mix
-  // family key: (300, module) for a specialised kernel, (dense code,
-  // nullptr) for a dense kernel, (0, nullptr) for the group kernels
+
+  // ---- queues: suspended and waiting paths first, then new paths ----
+  std::vector<int64_t> h_ids, h_slots, h_path, h_xoff;
+  std::vector<int32_t> h_n, h_owner;
+  for (size_t i = 0; i < batch.size(); ++i) {
+    Request &R = *batch[i];
+    R.qoff = (int64_t)h_ids.size();
+    R.qlen = R.qtaken = 0;
+    if (std::memcmp(&R.tol, &tol, sizeof(tol)) != 0) continue;
+    const int n = R.info.n;
+    auto push = [&](int64_t pid, int64_t slot) {
+      h_ids.push_back(pid);
+      h_slots.push_back(slot);
+      h_path.push_back(R.region_off + slot);
+      h_xoff.push_back(R.region_off * HP_MAX_N + slot * n);
+      h_n.push_back(n);
+      h_owner.push_back((int32_t)i);
+    };
+    if (!R.sliceable()) {
+      // group kernels: the next chunk of path ids in slots 0, 1, ...
+      const int64_t c = std::min(std::min(R.info.paths - R.next_path, R.region_paths), share);
+      for (int64_t k = 0; k < c; ++k) push(R.next_path + k, k);
+      R.next_path += c;
+    } else {
+      const int64_t take = std::min<int64_t>((int64_t)R.live.size(), share);
+      for (int64_t k = 0; k < take; ++k) push(R.live[(size_t)k].pid, R.live[(size_t)k].slot);
+      R.live.erase(R.live.begin(), R.live.begin() + take);
+      R.qtaken = take;
+      while ((int64_t)h_ids.size() - R.qoff < share && R.next_path < R.info.paths &&
+             !R.free_slots.empty()) {
+        push(R.next_path++, R.free_slots.back());
+        R.free_slots.pop_back();
+      }
+    }
+    R.qlen = (int64_t)h_ids.size() - R.qoff;
+  }
+  const int64_t E = (int64_t)h_ids.size();
+  if (E == 0) return HP_OK;
+  if (E > INT32_MAX) return fail(HP_E_INVALID_ARG, "epoch queue too long");
+  int rc;
+  if ((rc = upload_vec(S->q_ids, h_ids, S->stream))) return rc;
+  if ((rc = upload_vec(S->q_slots, h_slots, S->stream))) return rc;
+  if ((rc = upload_vec(S->c_path, h_path, S->stream))) return rc;
+  if ((rc = upload_vec(S->c_xoff, h_xoff, S->stream))) return rc;
+  if ((rc = upload_vec(S->c_n, h_n, S->stream))) return rc;
+  HIP_TRY(hipStreamSynchronize(S->stream));
+
+  // ---- one launch per kernel family, each request on the family it runs
+  // on alone, so that its result does not depend on the other requests ----
   std::map<std::pair<int, const void *>, size_t> fam_of;
   std::vector<Packed> P;
   std::vector<int64_t> total;
   std::vector<Kv> fam_kv;
-  std::vector<int64_t> chunk(batch.size(), 0);
+  std::vector<std::pair<int, const void *>> fam_key;
   for (size_t i = 0; i < batch.size(); ++i) {
     Request &R = *batch[i];
-    if (std::memcmp(&R.tol, &tol, sizeof(tol)) != 0) continue;
-    chunk[i] = std::min(std::min(R.info.paths - R.next_path, R.region_paths), share);
-    const std::pair<int, const void *> key =
-        R.sm ? std::make_pair(300, (const void *)R.sm)
-             : std::make_pair(R.dense_code, (const void *)nullptr);
+    if (R.qlen == 0) continue;
+    const auto key = R.family();
     auto it = fam_of.find(key);
     if (it == fam_of.end()) {
       it = fam_of.emplace(key, P.size()).first;
       P.emplace_back();
       total.push_back(0);
+      fam_key.push_back(key);
       Kv kv;
       if (R.sm) {
         kv_decode(300 + R.info.n, kv);
@@ -2081,47 +2203,140 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
       fam_kv.push_back(kv);  // group family: chosen from its systems below
     }
     const size_t f = it->second;
-    // chunk outputs go to the request's arena region; slots are HP_MAX_N wide
-    pack_append(P[f], &R.sys, R.info, R.gamma, chunk[i], R.region_off, R.region_off * HP_MAX_N,
-                nullptr);
-    P[f].sys.back().id_base = R.next_path;
-    // endpoints of a chunk are packed with stride n inside its region
-    total[f] += chunk[i];
+    // queue entries go to the request's arena region: path slots from
+    // region_off, endpoint slots of n coordinates from region_off * HP_MAX_N
+    if (R.sliceable()) {
+      pack_append(P[f], &R.sys, R.info, R.gamma, R.qlen, R.region_off, R.region_off * HP_MAX_N,
+                  S->q_ids.as<int64_t>() + R.qoff);
+      P[f].sys.back().slots = S->q_slots.as<int64_t>() + R.qoff;
+    } else {
+      pack_append(P[f], &R.sys, R.info, R.gamma, R.qlen, R.region_off, R.region_off * HP_MAX_N,
+                  nullptr);
+      P[f].sys.back().id_base = h_ids[(size_t)R.qoff];
+    }
+    total[f] += R.qlen;
+  }
+  // step budget per family: -1 for the group kernels (no serving form), 0
+  // (no limit) when slicing is off
+  std::vector<int32_t> fam_steps(P.size(), 0);
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (size_t f = 0; f < P.size(); ++f) {
+      if (fam_key[f].first == 0) fam_steps[f] = -1;
+      if (fam_key[f].first == 0 || !sliced) continue;
+      if (fixed_steps > 0) {
+        fam_steps[f] = fixed_steps;
+      } else {
+        auto b = S->fam_budget.find(fam_key[f]);
+        fam_steps[f] = b == S->fam_budget.end() ? kInitialBudget : b->second;
+      }
+    }
+  }
+  while (S->fam_dev.size() < P.size()) S->fam_dev.emplace_back(new DevTables());
+  while (S->fam_ev.size() < P.size()) {
+    std::array<hipEvent_t, 2> ev{};
+    HIP_TRY(hipEventCreate(&ev[0]));
+    HIP_TRY(hipEventCreate(&ev[1]));
+    S->fam_ev.push_back(ev);
   }
   // the families run side by side (their requests' arena regions are
   // disjoint), each on one of the family streams
-  std::vector<DevTables> dev(P.size());
-  int rc = HP_OK;
-  for (size_t f = 0, used = 0; f < P.size() && rc == HP_OK; ++f) {
-    if (P[f].sys.empty()) continue;
-    const int q = (int)(used++ % kFamilyStreams);
+  for (size_t f = 0; f < P.size() && rc == HP_OK; ++f) {
+    const hipStream_t fs = S->fam_stream[f % kFamilyStreams];
     Kv kv = fam_kv[f];
     if (!kv.spec && !kv.dense) kv_decode(nmax_for(P[f].nl), kv);  // group kernels
-    rc = dev[f].upload(P[f], S->fam_stream[q]);
+    rc = S->fam_dev[f]->upload(P[f], fs);
     if (rc == HP_OK)
-      rc = launch_persistent(ctx, dev[f], P[f], kv, tol, total[f], S->a_ends.as<hp_c64>(),
-                             S->a_status.as<int32_t>(), S->a_stats.as<hp_path_stats>(),
-                             S->fam_stream[q], nullptr, S->fam_ev[q][0], S->fam_ev[q][1]);
+      rc = launch_persistent(ctx, *S->fam_dev[f], P[f], kv, tol, total[f], S->a_ends.as<hp_c64>(),
+                             S->a_status.as<int32_t>(), S->a_stats.as<hp_path_stats>(), fs,
+                             nullptr, S->fam_ev[f][0], S->fam_ev[f][1], nullptr, fam_steps[f]);
   }
-  // every launched family ends before its tables are freed or read back
+  // every launched family ends before the harvest reads the arena
   for (int q = 0; q < kFamilyStreams; ++q) HIP_TRY(hipStreamSynchronize(S->fam_stream[q]));
   if (rc) return rc;
-  // copy finished chunks to the requests' host results
+  std::vector<float> fam_ms(P.size(), 0.0f);
+  for (size_t f = 0; f < P.size(); ++f)
+    HIP_TRY(hipEventElapsedTime(&fam_ms[f], S->fam_ev[f][0], S->fam_ev[f][1]));
+
+  // ---- harvest: finished paths to the host results, slots freed ----
+  if ((rc = S->r_entry.alloc((size_t)E * sizeof(int32_t)))) return rc;
+  if ((rc = S->r_status.alloc((size_t)E * sizeof(int32_t)))) return rc;
+  if ((rc = S->r_x.alloc((size_t)E * HP_MAX_N * sizeof(hp_c64)))) return rc;
+  if ((rc = S->r_stats.alloc((size_t)E * sizeof(hp_path_stats)))) return rc;
+  if ((rc = S->r_count.alloc(sizeof(unsigned)))) return rc;
+  HIP_TRY(hipMemsetAsync(S->r_count.p, 0, sizeof(unsigned), S->stream));
+  hp::CollectArgs ca;
+  ca.m = E;
+  ca.path_slot = (const long long *)S->c_path.as<int64_t>();
+  ca.x_off = (const long long *)S->c_xoff.as<int64_t>();
+  ca.n = S->c_n.as<int32_t>();
+  ca.status = S->a_status.as<int32_t>();
+  ca.endpoints = (const double2 *)S->a_ends.as<hp_c64>();
+  ca.stats = S->a_stats.as<hp_path_stats>();
+  ca.rec_entry = S->r_entry.as<int32_t>();
+  ca.rec_status = S->r_status.as<int32_t>();
+  ca.rec_x = (double2 *)S->r_x.as<hp_c64>();
+  ca.rec_stats = S->r_stats.as<hp_path_stats>();
+  ca.count = S->r_count.as<unsigned>();
+  HIP_TRY((hipError_t)hp_launch_collect(ca, S->stream));
+  unsigned cnt = 0;
+  HIP_TRY(hipMemcpyAsync(&cnt, S->r_count.p, sizeof(unsigned), hipMemcpyDeviceToHost, S->stream));
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  if ((int64_t)cnt > E) return fail(HP_E_DEVICE, "harvest count out of range");
+  std::vector<int32_t> r_entry(cnt), r_status(cnt);
+  std::vector<hp_c64> r_x((size_t)cnt * HP_MAX_N);
+  std::vector<hp_path_stats> r_stats(cnt);
+  if (cnt) {
+    HIP_TRY(hipMemcpyAsync(r_entry.data(), S->r_entry.p, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, S->stream));
+    HIP_TRY(hipMemcpyAsync(r_status.data(), S->r_status.p, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, S->stream));
+    HIP_TRY(hipMemcpyAsync(r_x.data(), S->r_x.p, r_x.size() * sizeof(hp_c64), hipMemcpyDeviceToHost, S->stream));
+    HIP_TRY(hipMemcpyAsync(r_stats.data(), S->r_stats.p, cnt * sizeof(hp_path_stats), hipMemcpyDeviceToHost, S->stream));
+    HIP_TRY(hipStreamSynchronize(S->stream));
+  }
+  std::vector<uint8_t> finished((size_t)E, 0);
+  for (unsigned r = 0; r < cnt; ++r) {
+    const int64_t k = r_entry[r];
+    if (k < 0 || k >= E || finished[(size_t)k]) return fail(HP_E_DEVICE, "harvest record out of range");
+    finished[(size_t)k] = 1;
+    Request &R = *batch[(size_t)h_owner[(size_t)k]];
+    const int64_t pid = h_ids[(size_t)k], n = R.info.n;
+    std::memcpy(R.ends.data() + pid * n, r_x.data() + (size_t)r * HP_MAX_N, (size_t)n * sizeof(hp_c64));
+    R.status[(size_t)pid] = r_status[r];
+    R.stats[(size_t)pid] = r_stats[r];
+    R.done_paths += 1;
+    if (R.sliceable()) R.free_slots.push_back(h_slots[(size_t)k]);
+  }
+  // unfinished queue entries keep their slots and go first next epoch
+  int64_t carried = 0;
+  std::vector<bool> fam_open(P.size(), false);
   for (size_t i = 0; i < batch.size(); ++i) {
     Request &R = *batch[i];
-    const int64_t c = chunk[i], p0 = R.next_path, n = R.info.n;
-    if (c == 0) continue;
-    HIP_TRY(hipMemcpyAsync(R.ends.data() + p0 * n, S->a_ends.as<hp_c64>() + R.region_off * HP_MAX_N,
-                           (size_t)c * n * sizeof(hp_c64), hipMemcpyDeviceToHost, S->stream));
-    HIP_TRY(hipMemcpyAsync(R.status.data() + p0, S->a_status.as<int32_t>() + R.region_off,
-                           (size_t)c * sizeof(int32_t), hipMemcpyDeviceToHost, S->stream));
-    HIP_TRY(hipMemcpyAsync(R.stats.data() + p0, S->a_stats.as<hp_path_stats>() + R.region_off,
-                           (size_t)c * sizeof(hp_path_stats), hipMemcpyDeviceToHost, S->stream));
+    if (R.qlen == 0) continue;
+    std::vector<Entry> keep;
+    for (int64_t k = R.qoff; k < R.qoff + R.qlen; ++k)
+      if (!finished[(size_t)k]) keep.push_back({h_ids[(size_t)k], h_slots[(size_t)k]});
+    if (!keep.empty() && !R.sliceable()) return fail(HP_E_DEVICE, "a group-kernel path did not finish");
+    carried += (int64_t)keep.size();
+    if (!keep.empty()) fam_open[fam_of[R.family()]] = true;
+    keep.insert(keep.end(), R.live.begin(), R.live.end());
+    R.live.swap(keep);
   }
-  HIP_TRY(hipStreamSynchronize(S->stream));
-  for (size_t i = 0; i < batch.size(); ++i) {
-    batch[i]->next_path += chunk[i];
-    batch[i]->done_paths += chunk[i];
+  const double ms = now_ms() - t_epoch;
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->epochs += 1;
+  S->carried += carried;
+  S->epoch_ms_sum += ms;
+  S->epoch_ms_max = std::max(S->epoch_ms_max, ms);
+  // adapt each sliced family's step budget toward the slice time
+  if (fixed_steps <= 0 && slice_ms > 0.0) {
+    for (size_t f = 0; f < P.size(); ++f) {
+      if (fam_steps[f] <= 0) continue;
+      int32_t b = fam_steps[f];
+      const double km = std::max(0.01, (double)fam_ms[f]);
+      if (km > 1.25 * slice_ms) b = std::max(kMinBudget, (int32_t)(b * (slice_ms / km)));
+      else if (km < 0.5 * slice_ms && fam_open[f]) b = std::min<int64_t>(kMaxBudget, 2 * (int64_t)b);
+      S->fam_budget[fam_key[f]] = b;
+    }
   }
   return HP_OK;
 }
@@ -2134,8 +2349,9 @@ void worker_main(hp_server *S) {
       std::unique_lock<std::mutex> lk(S->mu);
       S->cv_work.wait(lk, [&] { return S->stop || !S->pending.empty() || !S->active.empty(); });
       if (S->stop) {
-        // requests still queued or running end as failed, so waiters return
+        // requests still queued, compiling or running end as failed, so waiters return
         for (auto &R : S->pending) R->done = R->failed = true;
+        for (auto &R : S->to_compile) R->done = R->failed = true;
         for (auto &R : S->active) R->done = R->failed = true;
         S->error = "server destroyed before the request finished";
         S->cv_done.notify_all();
@@ -2152,19 +2368,61 @@ void worker_main(hp_server *S) {
     for (auto &R : S->active) {
       if (rc != HP_OK) {
         R->failed = true;
-        S->error = g_err;
+        R->error = g_err;
       }
       if (rc != HP_OK || R->done_paths >= R->info.paths) {
         R->done = true;
         R->t_done = now;
+        // a freed region's slots hold no path: status kUnstarted throughout
+        // (the harvest marks the slots of finished paths; this covers a
+        // failed epoch)
+        (void)hp_launch_fill_i32(S->a_status.as<int32_t>() + R->region_off, R->region_paths,
+                                 hp::kUnstarted, S->stream);
+        (void)hipStreamSynchronize(S->stream);
         S->resident -= (size_t)R->region_paths * slot_bytes();
         S->free_region(R->region_off, R->region_paths);
+        R->live.clear();
+        R->free_slots.clear();
+        R->free_slots.shrink_to_fit();
       } else {
         keep.push_back(R);
       }
     }
     S->active.swap(keep);
     S->cv_done.notify_all();
+  }
+}
+
+// Compiles the kernels specialised to first-seen supports, one request at a
+// time; a request joins the pending queue when its kernel is loaded.
+void compiler_main(hp_server *S) {
+  (void)hipSetDevice(S->ctx->device);
+  for (;;) {
+    std::shared_ptr<Request> R;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_compile.wait(lk, [&] { return S->stop || !S->to_compile.empty(); });
+      if (S->stop) return;
+      R = S->to_compile.front();
+    }
+    std::string log;
+    const hp::SpecModule *sm = nullptr;
+    const int rc = hp::spec_get(S->ctx->device, R->spec_src, &sm, log);
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) return;  // the worker has failed every queued request
+    S->to_compile.pop_front();
+    if (rc) {
+      R->done = R->failed = true;
+      R->error = "specialised kernel: " + std::string(hipGetErrorString((hipError_t)rc)) +
+                 (log.empty() ? "" : "\n" + log);
+      S->cv_done.notify_all();
+    } else {
+      R->sm = sm;
+      R->spec_src.clear();
+      R->spec_src.shrink_to_fit();
+      S->pending.push_back(R);
+      S->cv_work.notify_one();
+    }
   }
 }
 
@@ -2189,17 +2447,49 @@ int hp_server_create(hp_context *ctx, size_t hbm_budget_bytes, hp_server **out) 
   if ((rc = S->a_stats.alloc((size_t)S->arena_paths * sizeof(hp_path_stats)))) return rc;
   S->free_list.push_back({0, S->arena_paths});
   HIP_TRY(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
-  HIP_TRY(hipEventCreate(&S->ev0));
-  HIP_TRY(hipEventCreate(&S->ev1));
-  for (int f = 0; f < kFamilyStreams; ++f) {
+  for (int f = 0; f < kFamilyStreams; ++f)
     HIP_TRY(hipStreamCreateWithFlags(&S->fam_stream[f], hipStreamNonBlocking));
-    HIP_TRY(hipEventCreate(&S->fam_ev[f][0]));
-    HIP_TRY(hipEventCreate(&S->fam_ev[f][1]));
-  }
+  // no slot holds a path yet
+  HIP_TRY((hipError_t)hp_launch_fill_i32(S->a_status.as<int32_t>(), S->arena_paths, hp::kUnstarted,
+                                         S->stream));
+  HIP_TRY(hipStreamSynchronize(S->stream));
   hp_server *raw = S.get();
   S->worker = std::thread(worker_main, raw);
+  S->compiler = std::thread(compiler_main, raw);
   context_adopt(ctx);
   *out = S.release();
+  return HP_OK;
+}
+
+int hp_server_set_slice(hp_server *S, double slice_ms, int32_t fixed_steps) {
+  if (!S) return fail(HP_E_INVALID_ARG, "NULL server");
+  if (!(slice_ms >= 0.0) || !std::isfinite(slice_ms) || fixed_steps < 0)
+    return fail(HP_E_INVALID_ARG, "slice_ms must be finite and >= 0, fixed_steps >= 0");
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->slice_ms = slice_ms;
+  S->fixed_steps = fixed_steps;
+  S->fam_budget.clear();
+  return HP_OK;
+}
+
+int hp_server_info_get(hp_server *S, hp_server_info *out) {
+  if (!S || !out) return fail(HP_E_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  std::memset(out, 0, sizeof(*out));
+  out->epochs = S->epochs;
+  out->carried = S->carried;
+  out->epoch_ms_max = S->epoch_ms_max;
+  out->epoch_ms_mean = S->epochs ? S->epoch_ms_sum / (double)S->epochs : 0.0;
+  out->slice_ms = S->slice_ms;
+  out->fixed_steps = S->fixed_steps;
+  int32_t bmin = 0, bmax = 0;
+  for (auto &b : S->fam_budget) {
+    bmin = bmin ? std::min(bmin, b.second) : b.second;
+    bmax = std::max(bmax, b.second);
+  }
+  out->budget_min = bmin;
+  out->budget_max = bmax;
+  out->peak_bytes = S->peak;
   return HP_OK;
 }
 
@@ -2222,17 +2512,12 @@ int hp_server_submit(hp_server *S, const hp_system *f, hp_c64 gamma, const hp_to
     if (kv.nmax < n) return fail(HP_E_UNSUPPORTED_N, "no kernel variant for n");
     if ((rc = check_lds(S->ctx, kv_lds(kv, one)))) return rc;
     R->dense_code = kv.dense ? kv.code : 0;
-    // systems a specialised kernel serves run on it (compiled here the
-    // first time their support is seen, then shared by every request of
-    // that support)
+    // systems a specialised kernel serves run on it (compiled on the
+    // server's compile thread the first time their support is seen, then
+    // shared by every request of that support)
     const DevSys &d = one.sys[0];
-    if (!R->dense_code && hp::spec_eligible(n, one.terms.data(), d.n_terms)) {
-      std::string log;
-      HIP_TRY(hipSetDevice(S->ctx->device));
-      rc = hp::spec_get(S->ctx->device, hp::spec_source(n, d.deg, one.terms.data(), d.n_terms),
-                        &R->sm, log);
-      if (rc) return fail(HP_E_DEVICE, "specialised kernel: " + log);
-    }
+    if (!R->dense_code && hp::spec_eligible(n, one.terms.data(), d.n_terms))
+      R->spec_src = hp::spec_source(n, d.deg, one.terms.data(), d.n_terms, true);
   }
   R->eq_ptr.assign(f->eq_ptr, f->eq_ptr + n + 1);
   R->coeff.assign(f->coeff, f->coeff + f->n_terms);
@@ -2248,9 +2533,14 @@ int hp_server_submit(hp_server *S, const hp_system *f, hp_c64 gamma, const hp_to
   std::lock_guard<std::mutex> lk(S->mu);
   R->id = S->next_id++;
   S->all[R->id] = R;
-  S->pending.push_back(R);
+  if (R->spec_src.empty()) {
+    S->pending.push_back(R);
+    S->cv_work.notify_one();
+  } else {
+    S->to_compile.push_back(R);
+    S->cv_compile.notify_one();
+  }
   *req_id = R->id;
-  S->cv_work.notify_one();
   return HP_OK;
 }
 
@@ -2274,7 +2564,7 @@ int hp_server_wait(hp_server *S, int64_t req_id, hp_c64 *endpoints, int32_t *sta
     R = it->second;
     S->cv_done.wait(lk, [&] { return R->done; });
     S->all.erase(it);
-    if (R->failed) return fail(HP_E_DEVICE, "request failed: " + S->error);
+    if (R->failed) return fail(HP_E_DEVICE, "request failed: " + (R->error.empty() ? S->error : R->error));
   }
   if (endpoints) std::memcpy(endpoints, R->ends.data(), R->ends.size() * sizeof(hp_c64));
   if (status) std::memcpy(status, R->status.data(), R->status.size() * sizeof(int32_t));
@@ -2296,18 +2586,19 @@ void hp_server_destroy(hp_server *S) {
     std::lock_guard<std::mutex> lk(S->mu);
     S->stop = true;
     S->cv_work.notify_all();
+    S->cv_compile.notify_all();
   }
   if (S->worker.joinable()) S->worker.join();
+  if (S->compiler.joinable()) S->compiler.join();
   (void)hipSetDevice(S->ctx->device);
   if (S->stream) (void)hipStreamSynchronize(S->stream);
-  for (int f = 0; f < kFamilyStreams; ++f) {
+  for (int f = 0; f < kFamilyStreams; ++f)
     if (S->fam_stream[f]) (void)hipStreamSynchronize(S->fam_stream[f]);
-    for (int e = 0; e < 2; ++e)
-      if (S->fam_ev[f][e]) (void)hipEventDestroy(S->fam_ev[f][e]);
+  for (auto &ev : S->fam_ev)
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  for (int f = 0; f < kFamilyStreams; ++f)
     if (S->fam_stream[f]) (void)hipStreamDestroy(S->fam_stream[f]);
-  }
-  if (S->ev0) (void)hipEventDestroy(S->ev0);
-  if (S->ev1) (void)hipEventDestroy(S->ev1);
   if (S->stream) (void)hipStreamDestroy(S->stream);
   hp_context *ctx = S->ctx;
   delete S;

@@ -51,6 +51,8 @@ struct alignas(16) DevSys {
   int64_t out_x_base;          // first endpoint (hp_c64) index of this system
   const int64_t *ids;          // queue index -> path id (nullptr: id_base + index)
   int64_t id_base;
+  const int64_t *slots;        // queue index -> output slot (nullptr: the index);
+                               // a slot holds a suspended path's state (serving)
   // general start system g (g_n_terms == 0: total degree, g_i = x_i^{d_i} - 1)
   int32_t g_term_base;         // first term of g
   int32_t g_n_terms;
@@ -77,7 +79,7 @@ struct alignas(16) DevSys {
 // (a <= b <= c), each block present up to the equation's degree, loops with
 // a outermost (missing monomials hold zero).
 constexpr int kDenseMaxN = 10;      // k_dense: any n up to this in one launch
-constexpr int kDenseWideMaxN = 12;  // k_dense11, k_dense12: one exact n per launch
+constexpr int kDenseWideMaxN = 12;  // k_dense_n<11>, k_dense_n<12>: one exact n per launch
 constexpr int kDenseMaxDeg = 3;
 
 struct DevTol {
@@ -112,7 +114,16 @@ struct KArgs {
   PlainState ps;         // plain mode only
   const double2 *dcoef;  // dense coefficient tables (dense kernel)
   double2 *endpoints_lo; // low parts of the endpoints (double-double tracker)
+  int32_t step_budget;   // serving kernels: steps per wavefront in this launch (0: until
+                         // the queues are drained); past it, paths in flight are
+                         // suspended to their slots
 };
+
+// Status codes of a slot that holds a suspended path (serving) or a path not
+// started yet; a finished path's status is its hp_status (>= 0).
+constexpr int32_t kSuspendedTrack = -2;
+constexpr int32_t kSuspendedFinal = -3;
+constexpr int32_t kUnstarted = -4;
 
 enum Mode : int32_t { M_IDLE = 0, M_TRACK = 1, M_FINAL = 2 };
 
@@ -135,6 +146,25 @@ struct DupArgs {
   unsigned long long *pair_count;  // pairs found (may exceed max_pairs)
   void *temp;                      // radix sort workspace
   size_t temp_bytes;
+};
+
+// Arguments of the serving harvest (serve.hip): entry k of the launch's
+// queues owns arena path slot path_slot[k] (status, stats) and endpoint
+// coordinates x_off[k] .. x_off[k] + n[k] - 1; finished entries become
+// records 0 .. *count - 1.
+struct CollectArgs {
+  long long m;
+  const long long *path_slot;
+  const long long *x_off;
+  const int32_t *n;
+  int32_t *status;           // arena
+  const double2 *endpoints;  // arena
+  const hp_path_stats *stats;
+  int32_t *rec_entry;        // [m]
+  int32_t *rec_status;       // [m]
+  double2 *rec_x;            // [m][HP_MAX_N]
+  hp_path_stats *rec_stats;  // [m]
+  unsigned *count;
 };
 
 // Kernel variants compiled into the library: the register arrays hold up to
@@ -201,7 +231,7 @@ inline size_t lanes_lds_bytes(int n, int pw, int emax) {
 }  // namespace hp
 
 // Kernel launchers (tracker.hip, lanes.hip, dense.hip, dense11.hip, dense12.hip,
-// endgame.hip, dedup.hip, dedup_static.hip, ddtrack.hip).  Return a hipError_t
+// dense_sliced.hip, dense_wide_sliced.hip, endgame.hip, dedup.hip, dedup_static.hip, ddtrack.hip, serve.hip).  Return a hipError_t
 // value.
 extern "C++" {
 // general: the systems use a general start system or explicit start points
@@ -221,6 +251,12 @@ int hp_launch_dense11(const hp::KArgs &a, int groups, void *stream);
 int hp_dense11_per_cu(int *out);
 int hp_launch_dense12(const hp::KArgs &a, int groups, void *stream);
 int hp_dense12_per_cu(int *out);
+// Serving forms of the dense kernels (dense_sliced.hip, dense_wide_sliced.hip;
+// n = 11 or 12 for the wide one).
+int hp_launch_dense_sliced(const hp::KArgs &a, int groups, void *stream);
+int hp_dense_sliced_per_cu(int *out);
+int hp_launch_dense_wide_sliced(int n, const hp::KArgs &a, int groups, void *stream);
+int hp_dense_wide_sliced_per_cu(int n, int *out);
 // Duplicate scan (dedup.hip): projection and compaction of the converged
 // endpoints, radix sort of m keys, window scan over the m sorted keys; and
 // the scatter of re-tracked results into the full outputs.
@@ -244,6 +280,9 @@ int hp_launch_scatter(const long long *ids, long long m, int n, const double2 *e
 // per path; resident workgroups per CU of its n instantiation.
 int hp_launch_ddtrack(int n, const hp::KArgs &a, int groups, void *stream);
 int hp_ddtrack_per_cu(int n, int *out);
+// Serving harvest of finished paths, and a fill of m int32 values (serve.hip).
+int hp_launch_collect(const hp::CollectArgs &a, void *stream);
+int hp_launch_fill_i32(int32_t *p, long long m, int32_t v, void *stream);
 // End game of the paths of systems with n unknowns: blk[b] = (system, first
 // queue index) of block b (64 paths each), or blk == nullptr for one system
 // (system 0, block b from queue index 64 b).

@@ -80,7 +80,7 @@ bool spec_eligible(int n, const DevTerm *terms, int n_terms) {
 // adds s d_i x_i^{d_i-1} on the diagonal; the right-hand side is chosen by
 // emode.  A Jacobian entry or value is assigned at its first contribution
 // and accumulated with fused multiply-adds afterwards.
-std::string spec_source(int n, const int32_t *deg, const DevTerm *terms, int n_terms) {
+std::string spec_source(int n, const int32_t *deg, const DevTerm *terms, int n_terms, bool sliced) {
   std::vector<GenTerm> T;
   T.reserve(n_terms);
   std::vector<int> emax(n, 1);  // powers the terms use (computed up front)
@@ -186,10 +186,13 @@ std::string spec_source(int n, const int32_t *deg, const DevTerm *terms, int n_t
     << "constexpr int kRkBytes = hp::RkLds<hp::gen::Sys::N>::kBytes;\n\n"
     << "extern \"C\" __global__ void __launch_bounds__(64) hp_spec_persistent(hp::KArgs a) {\n"
     << "  __shared__ __attribute__((aligned(16))) char rk[kRkBytes];\n"
-    << "  SpecT tr(a, (hp::lds_char *)rk);\n  hp::lane_persistent(a, tr);\n}\n\n"
-    << "extern \"C\" __global__ void __launch_bounds__(64) hp_spec_plain(hp::KArgs a) {\n"
-    << "  __shared__ __attribute__((aligned(16))) char rk[kRkBytes];\n"
-    << "  SpecT tr(a, (hp::lds_char *)rk);\n  hp::lane_plain<SpecT, 64>(a, tr);\n}\n";
+    << "  SpecT tr(a, (hp::lds_char *)rk);\n  hp::lane_persistent<" << (sliced ? "true" : "false")
+    << ">(a, tr);\n}\n";
+  // the serving form (sliced) has no plain kernel
+  if (!sliced)
+    o << "\nextern \"C\" __global__ void __launch_bounds__(64) hp_spec_plain(hp::KArgs a) {\n"
+      << "  __shared__ __attribute__((aligned(16))) char rk[kRkBytes];\n"
+      << "  SpecT tr(a, (hp::lds_char *)rk);\n  hp::lane_plain<SpecT, 64>(a, tr);\n}\n";
   return o.str();
 }
 
@@ -359,7 +362,9 @@ int spec_get(int device, const std::string &src, const SpecModule **out, std::st
   std::unique_ptr<SpecModule> m(new SpecModule());
   hipError_t e = hipModuleLoadData(&m->mod, code.data());
   if (e == hipSuccess) e = hipModuleGetFunction(&m->persistent, m->mod, "hp_spec_persistent");
-  if (e == hipSuccess) e = hipModuleGetFunction(&m->plain, m->mod, "hp_spec_plain");
+  // a serving (sliced) module has no plain kernel
+  if (e == hipSuccess && src.find("hp_spec_plain") != std::string::npos)
+    e = hipModuleGetFunction(&m->plain, m->mod, "hp_spec_plain");
   if (e != hipSuccess) {
     if (m->mod) (void)hipModuleUnload(m->mod);
     return (int)e;

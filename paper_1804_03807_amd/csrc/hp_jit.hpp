@@ -25,7 +25,10 @@ bool spec_eligible(int n, const DevTerm *terms, int n_terms);
 // HIP source of the specialised kernels hp_spec_persistent and hp_spec_plain
 // for a system of n unknowns, start-system degrees deg[0..n-1] and terms in
 // packed order (sorted by factor count; the coefficients stay run-time data).
-std::string spec_source(int n, const int32_t *deg, const DevTerm *terms, int n_terms);
+// sliced: the serving form, whose persistent kernel suspends and resumes
+// paths (lane_drain) and which has no plain kernel
+std::string spec_source(int n, const int32_t *deg, const DevTerm *terms, int n_terms,
+                        bool sliced = false);
 
 // Code object of spec source for gfx950 (no device needed): from this
 // process's cache, else from the directory $HP_JIT_CACHE names (when set),

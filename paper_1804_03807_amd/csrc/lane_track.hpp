@@ -132,11 +132,66 @@ struct LaneTrack {
     id_base = sp->id_base;
   }
 
+  // output slot of queue index q
+  __device__ __forceinline__ long long slot_of(long long q) const {
+    const long long *sl = (const long long *)sp->slots;
+    return sl ? sl[q] : q;
+  }
+
+  // A path suspended at the end of an earlier launch resumes from its slot:
+  // accepted point, t, h and counters as suspend() left them.
+  __device__ __forceinline__ bool resume(long long q) {
+    const long long o = out_path_base + slot_of(q);
+    const int st = a.status[o];
+    if (st != kSuspendedTrack && st != kSuspendedFinal) return false;
+    const double2 *e = a.endpoints + out_x_base + slot_of(q) * n;
+#pragma unroll
+    for (int i = 0; i < N; ++i) rk.set_x0(i, {e[i].x, e[i].y});
+    const hp_path_stats *s = a.stats + o;
+    steps = s->steps;
+    rejections = s->rejections;
+    newton_its = s->newton_iters;
+    evals = s->evals;
+    solves = s->solves;
+    accepts = s->pad;
+    t = s->t_final;
+    h = s->residual;
+    mode = (st == kSuspendedFinal) ? M_FINAL : M_TRACK;
+    return true;
+  }
+
+  // The step budget of the launch is spent: the path's state goes to its
+  // slot (endpoint = accepted point; stats hold t, h, counters).
+  __device__ __forceinline__ void suspend() {
+    const long long so = slot_of(qidx);
+    double2 *e = a.endpoints + out_x_base + so * n;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const cd x = rk.x0(i);
+      e[i] = make_double2(x.re, x.im);
+    }
+    hp_path_stats *s = a.stats + out_path_base + so;
+    s->steps = steps;
+    s->rejections = rejections;
+    s->newton_iters = newton_its;
+    s->evals = evals;
+    s->solves = solves;
+    s->pad = accepts;
+    s->t_final = t;
+    s->residual = h;
+    a.status[out_path_base + so] = (mode == M_FINAL) ? kSuspendedFinal : kSuspendedTrack;
+  }
+
   // ------------------------------------------------------------ start path
   // Path id -> start point of the total-degree start system: digit i of the
   // id in the mixed radix (d_0, d_1, ...) picks the root of unity of x_i.
+  // Sliced: the launch may find suspended paths in its queue (serving).
+  template <bool Sliced>
   __device__ __forceinline__ void start_path(long long q) {
     qidx = q;
+    if constexpr (Sliced) {
+      if (resume(q)) return;
+    }
     const long long pid = ids ? ids[q] : id_base + q;
     cptr<double> roots = as_const((const double *)a.roots) + 2 * sp->root_base;
 #pragma unroll
@@ -303,14 +358,18 @@ struct LaneTrack {
     fin_res = res;
   }
 
+  // Sliced: queue indices map to slots (serving)
+  template <bool Sliced = false>
   __device__ __forceinline__ void write_out(int fs, double res) {
-    double2 *e = a.endpoints + out_x_base + qidx * n;
+    long long so = qidx;
+    if constexpr (Sliced) so = slot_of(qidx);
+    double2 *e = a.endpoints + out_x_base + so * n;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       const cd x = rk.x0(i);
       e[i] = make_double2(x.re, x.im);
     }
-    const long long o = out_path_base + qidx;
+    const long long o = out_path_base + so;
     a.status[o] = fs;
     if (a.stats) {
       hp_path_stats *s = a.stats + o;
@@ -334,12 +393,25 @@ struct LaneTrack {
 // mbcnt), in place of the work crew's guarded next-job pointer (Section 1).
 // ------------------------------------------------------------------------
 // Drains system s's queue: tracks its paths until the queue is empty and
-// this wavefront's lanes are idle.
-template <class T>
-__device__ __forceinline__ void lane_drain(const KArgs &a, T &tr, int s) {
+// this wavefront's lanes are idle.  Sliced (serving): queue entries may be
+// paths suspended by an earlier launch, which resume from their slots, and
+// once the wavefront has taken a.step_budget > 0 steps in this launch
+// (counted in wave_steps across the systems it visits) its paths in flight
+// are suspended to their slots and it returns true.
+template <bool Sliced, class T>
+__device__ __forceinline__ bool lane_drain(const KArgs &a, T &tr, int s, int &wave_steps) {
   tr.load_system(s);
   bool exhausted = false;
   for (;;) {
+    if constexpr (Sliced) {
+      if (a.step_budget > 0 && wave_steps >= a.step_budget) {
+        if (tr.slot && tr.mode != M_IDLE) {
+          tr.suspend();
+          tr.mode = M_IDLE;
+        }
+        return true;
+      }
+    }
     // ---- refill idle lanes: one atomic per wavefront ----
     const bool idle = tr.slot && tr.mode == M_IDLE;
     const uint64_t m = ballot(idle);
@@ -353,7 +425,7 @@ __device__ __forceinline__ void lane_drain(const KArgs &a, T &tr, int s) {
                                                       __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
       if (idle) {
         const long long q = (long long)qb + rank;
-        if (q < tr.npaths) tr.start_path(q);
+        if (q < tr.npaths) tr.template start_path<Sliced>(q);
       }
       if ((long long)(qb + cnt) >= tr.npaths) exhausted = true;
     }
@@ -367,17 +439,21 @@ __device__ __forceinline__ void lane_drain(const KArgs &a, T &tr, int s) {
       double res;
       tr.step(fs, res);
       if (fs >= 0) {
-        tr.write_out(fs, res);
+        tr.template write_out<Sliced>(fs, res);
         tr.mode = M_IDLE;
       }
     }
+    if constexpr (Sliced) ++wave_steps;
   }
+  return false;
 }
 
-template <class T>
+template <bool Sliced = false, class T>
 __device__ __forceinline__ void lane_persistent(const KArgs &a, T &tr) {
   const int first_sys = blockIdx.x % a.n_systems;
-  for (int v = 0; v < a.n_systems; ++v) lane_drain(a, tr, (first_sys + v) % a.n_systems);
+  int wave_steps = 0;
+  for (int v = 0; v < a.n_systems; ++v)
+    if (lane_drain<Sliced>(a, tr, (first_sys + v) % a.n_systems, wave_steps)) return;
 }
 
 // ------------------------------------------------------------------------

@@ -159,3 +159,89 @@ def test_mix_matches_oracle_sample(ctx):
             assert_parity(e[sample], st[sample], e_o, s_o, s.name, s, sample, log)
     finally:
         srv.close()
+
+
+def test_sliced_equals_unsliced_bitwise(ctx):
+    """With a budget of 4 steps per wavefront and epoch, paths of the
+    specialised and dense kernel families are suspended to their slots and
+    resumed in later epochs many times over; every request still ends bit for
+    bit (endpoints, statuses, every counter) as when each queue runs to the
+    end."""
+    import paper_1804_03807_amd as hp
+    reqs = small_requests(10, 6000)
+    log("requests", [(r, s.name, s.bezout()) for r, s, _ in reqs])
+    ref = {}
+    srv = hp.Server(ctx, 1 << 30)
+    try:
+        srv.set_slice(0.0, 0)
+        for r, s, g in reqs:
+            ref[r] = srv.wait(srv.submit(s, g), stats=True)
+        assert srv.info()["carried"] == 0
+    finally:
+        srv.close()
+    srv = hp.Server(ctx, 1 << 30)
+    try:
+        srv.set_slice(0.0, 4)
+        ids = [(r, srv.submit(s, g)) for r, s, g in reqs]
+        for r, q in ids:
+            e, st, sts, _ = srv.wait(q, stats=True)
+            e0, st0, sts0, _ = ref[r]
+            assert np.array_equal(st, st0), f"request {r}: statuses differ"
+            assert np.array_equal(e.view(np.float64), e0.view(np.float64)), f"request {r}: endpoints"
+            for k in ("steps", "rejections", "newton_iters", "evals", "solves", "t_final",
+                      "residual"):
+                assert np.array_equal(sts[k], sts0[k]), f"request {r}: stats {k}"
+        info = srv.info()
+        log("sliced server", info)
+        assert info["fixed_steps"] == 4 and info["epochs"] > 10 and info["carried"] > 0
+    finally:
+        srv.close()
+
+
+def test_adaptive_slice_bounds_epochs(ctx):
+    """The adaptive step budget keeps epochs near the slice time: with a 5 ms
+    slice, a cyclic-8 request (40,320 paths) runs over many epochs, and a
+    small request submitted behind it finishes long before it."""
+    import paper_1804_03807_amd as hp
+    wl = W.cyclic8()
+    sys8, g8 = wl.systems[0], complex(wl.gammas[0])
+    (r1, s1, g1), = small_requests(1, 1000)
+    ref1 = served_alone(ctx, s1, g1)
+    srv = hp.Server(ctx, 1 << 30)
+    try:
+        srv.set_slice(5.0, 0)
+        q8 = srv.submit(sys8, g8)
+        time.sleep(0.05)
+        q1 = srv.submit(s1, g1)
+        e, st, sts, lat1 = srv.wait(q1, stats=True)
+        assert_same((e, st, sts), ref1, "small request behind cyclic-8")
+        _, st8, _, lat8 = srv.wait(q8, stats=True)
+        info = srv.info()
+        log(f"latency small {lat1:.1f} ms, cyclic-8 {lat8:.1f} ms; {info}")
+        assert (st8 == 0).sum() > 0
+        assert info["epochs"] > 5 and info["budget_max"] > 0
+        assert lat1 < lat8
+    finally:
+        srv.close()
+
+
+def test_submit_does_not_compile(ctx):
+    """A request on a support not seen before returns from submit at once;
+    its specialised kernel compiles on the server's own thread."""
+    import paper_1804_03807_amd as hp
+    rng = np.random.default_rng(20261203)
+    s = W.embed(W.cyclic_system(5, rng), 1, rng, name="embedded_cyclic5")
+    g = complex(W.unit_circle(rng))
+    srv = hp.Server(ctx, 1 << 30)
+    try:
+        t0 = time.perf_counter()
+        q = srv.submit(s, g)
+        t_submit = time.perf_counter() - t0
+        e, st, sts, lat = srv.wait(q, stats=True)
+        log(f"submit {t_submit * 1e3:.1f} ms, request latency {lat:.0f} ms")
+        assert t_submit < 0.5
+        sample = W.stride_sample(s.bezout(), 48)
+        e_o, s_o, _ = oracle.track_paths(s, g, path_ids=sample, n_threads=NTHREADS)
+        assert_parity(e[sample], st[sample], e_o, s_o, s.name, s, sample, log)
+    finally:
+        srv.close()
