@@ -248,6 +248,7 @@ def serving_run(ctx, n_requests, budget_bytes, calib=200, load=0.8):
             except hp.HomotopyError:
                 pass  # too large for a specialised kernel: group kernels
     compile_ms = (time.perf_counter() - t0) * 1e3
+    progress(f"serving: {len(seen)} supports compiled ahead ({compile_ms:.0f} ms)")
 
     def run(sub, arrivals):
         srv = hp.Server(ctx, budget_bytes)
@@ -256,19 +257,27 @@ def serving_run(ctx, n_requests, budget_bytes, calib=200, load=0.8):
         t0 = time.perf_counter()
 
         def producer():
+            t_last = time.perf_counter()
             for i, ((s, g), ta) in enumerate(zip(sub, arrivals)):
                 while time.perf_counter() - t0 < ta:
                     time.sleep(0.0002)
                 ids[i] = srv.submit(s, g)
+                if time.perf_counter() - t_last > 10.0:
+                    t_last = time.perf_counter()
+                    progress(f"serving: {i + 1}/{len(sub)} requests submitted")
 
         th = threading.Thread(target=producer)
         th.start()
         th.join()
         lat, conv = [], 0
-        for q in ids:
+        t_last = time.perf_counter()
+        for i, q in enumerate(ids):
             _, st, _, ms = srv.wait(q)
             lat.append(ms)
             conv += int((st == 0).sum())
+            if time.perf_counter() - t_last > 10.0:
+                t_last = time.perf_counter()
+                progress(f"serving: {i + 1}/{len(ids)} requests done")
         makespan = time.perf_counter() - t0
         peak = srv.peak_bytes()
         info = srv.info()

@@ -128,7 +128,24 @@ typedef struct {
   int32_t max_n;      /* compiled size bound n_max of the variant used        */
   int32_t groups;     /* workgroups (one wavefront each) launched             */
   int32_t variant;    /* kernel variant code (see hp_plan_set_variant)        */
+  int32_t lanes_per_path; /* 1 (one path per lane) or n (group kernels)      */
+  int32_t waves_per_simd; /* cap on resident wavefronts per SIMD (0: none)   */
 } hp_timing;
+
+/* A launch configuration chosen by the autotuner (hp_plan_tuning,
+ * hp_tune_batch): the kernel variant (which fixes the lanes per path),
+ * paths per wavefront and the cap on resident wavefronts per SIMD, with the
+ * kernel time of the choice and of the untuned default on the sample. */
+typedef struct {
+  int32_t variant;
+  int32_t lanes_per_path;
+  int32_t paths_per_wave;
+  int32_t waves_per_simd; /* 0: as many as fit                               */
+  double ms;              /* sample kernel time of the choice (0 if cached)  */
+  double ms_default;      /* sample kernel time of the default shape         */
+  int32_t candidates;     /* configurations timed                           */
+  int32_t cached;         /* 1: taken from the tuning cache, nothing timed   */
+} hp_tune_choice;
 
 typedef struct hp_context hp_context;
 typedef struct hp_plan hp_plan;
@@ -227,6 +244,21 @@ void hp_plan_destroy(hp_plan *plan);
  * hp_plan_create times every candidate on a sample of the plan's paths and
  * caches the choice per system shape (file named by $HP_TUNE_CACHE). */
 int hp_plan_set_variant(hp_plan *plan, int32_t variant);
+/* Launch shape of the plan's variant: paths_per_wave (1..64; 0: all 64) for
+ * the specialised and dense kernels (other variants take 0 only), and a cap
+ * on the resident wavefronts per SIMD (0: as many as fit).  Paths are
+ * tracked independently (Section 1), so a path's result does not depend on
+ * the shape.  HP_E_INVALID_ARG for values out of range. */
+int hp_plan_set_launch(hp_plan *plan, int32_t paths_per_wave, int32_t waves_per_simd);
+/* The autotuner's record for a plan created with tune != 0 (zeros
+ * otherwise).  The tuner times every compiled variant that fits the
+ * system (group kernels: n lanes per path; lane, specialised and dense
+ * kernels: one), for the specialised and dense kernels with 64 and 32 paths
+ * per wavefront, each with every binding cap on the wavefronts per SIMD, on
+ * a sample of the plan's paths (2 resident rounds), and caches the fastest
+ * by device and system shape (n, terms, largest exponent and factor count)
+ * in memory and in the file $HP_TUNE_CACHE names. */
+int hp_plan_tuning(const hp_plan *plan, hp_tune_choice *out);
 
 /* Writes and compiles the kernel specialised to f (variant 300 + n) for
  * gfx950 without loading it, so it needs no device, in its two forms: the
@@ -264,6 +296,14 @@ int hp_batch_layout(const hp_system *fs, int32_t n_systems, int64_t *path_offset
 int hp_track_batch(hp_context *ctx, const hp_system *fs, int32_t n_systems,
                    const hp_c64 *gammas, const hp_tolerances *tol, hp_c64 *endpoints,
                    int32_t *status, hp_path_stats *stats);
+/* Autotunes the launch of a batch (the variants that run every system of
+ * it: the dense kernels, the group kernels; the launch shapes as for
+ * hp_plan_tuning) on a sample of each system's paths and caches the
+ * choice by device and batch shape (number of systems, range of n, terms,
+ * largest exponent and factor count, dense or not); hp_track_batch calls on
+ * batches of that shape launch with it.  Arguments as for hp_track_batch. */
+int hp_tune_batch(hp_context *ctx, const hp_system *fs, int32_t n_systems, const hp_c64 *gammas,
+                  const hp_tolerances *tol, hp_tune_choice *out);
 
 /* Endpoint post-pass (host): pairs (a, b), a < b, of CONVERGED endpoints with
  * ||x_a - x_b||_inf <= rel * max(1, ||x_a||_inf), found by sorting on a random
@@ -392,7 +432,7 @@ int hp_cascade(hp_context *ctx, const hp_system *e, int32_t k, const hp_c64 *gam
  * HP_E_BUDGET if the budget holds fewer than 4096 slots. */
 int hp_server_create(hp_context *ctx, size_t hbm_budget_bytes, hp_server **out);
 /* Time slicing of the specialised and dense kernel families: slice_ms is the
- * target kernel time of an epoch (default 20 ms), fixed_steps > 0 replaces
+ * target kernel time of an epoch (default 50 ms), fixed_steps > 0 replaces
  * the adaptive budget by that many steps per wavefront and epoch, and
  * slice_ms = fixed_steps = 0 runs every queue to the end.  Results do not
  * depend on these settings.  Takes effect from the next epoch; HP_E_INVALID_ARG

@@ -223,6 +223,18 @@ class Context:
             out.append((e, st[p0:p1], sts[p0:p1] if stats else None))
         return out
 
+    def tune_batch(self, systems, gammas, tol=None) -> dict:
+        """Autotunes the launch of batches shaped like this one (hp_tune_batch);
+        later track_batch calls on such batches use the choice."""
+        views = [_SysView(s) for s in systems]
+        arr = (HpSystem * len(views))(*[x.c for x in views])
+        g = np.ascontiguousarray(np.asarray(gammas, dtype=np.complex128))
+        tol = tol or default_tolerances()
+        c = _lib.HpTuneChoice()
+        check(self._L.hp_tune_batch(self.handle, arr, len(views), _ptr(g), ctypes.byref(tol),
+                                    ctypes.byref(c)))
+        return {k: getattr(c, k) for k, _ in c._fields_}
+
     def solve(self, system, gamma, tol=None):
         """All paths (batched), then the duplicate-endpoint re-track pass.
         Returns (endpoints, status, stats, remaining duplicate pairs)."""
@@ -332,6 +344,16 @@ class Plan:
     def set_variant(self, variant: int):
         """Kernel variant code (see hp_plan_set_variant in homotopy.h)."""
         check(self._L.hp_plan_set_variant(self.handle, int(variant)))
+
+    def set_launch(self, paths_per_wave: int = 0, waves_per_simd: int = 0):
+        """Launch shape of the plan's variant (hp_plan_set_launch)."""
+        check(self._L.hp_plan_set_launch(self.handle, int(paths_per_wave), int(waves_per_simd)))
+
+    def tuning(self) -> dict:
+        """The autotuner's record (hp_plan_tuning; zeros when not tuned)."""
+        c = _lib.HpTuneChoice()
+        check(self._L.hp_plan_tuning(self.handle, ctypes.byref(c)))
+        return {k: getattr(c, k) for k, _ in c._fields_}
 
     def outputs(self, n_paths, stats=True, device="cuda"):
         """Device tensors (endpoints as float64 [P, n, 2], status, stats bytes)."""

@@ -27,7 +27,8 @@ EXPORTED = [
     "hp_server_wait", "hp_server_peak_bytes", "hp_server_destroy", "hp_spec_compile",
     "hp_find_duplicates_device", "hp_plan_solve_device", "hp_find_duplicates_device_static",
     "hp_membership_test", "hp_cascade", "hp_track_paths_dd", "hp_default_tolerances_dd",
-    "hp_server_set_slice", "hp_server_info_get",
+    "hp_server_set_slice", "hp_server_info_get", "hp_plan_set_launch", "hp_plan_tuning",
+    "hp_tune_batch",
 ]
 
 
@@ -66,7 +67,15 @@ class HpTiming(ctypes.Structure):
     _fields_ = [("kernel_ms", ctypes.c_double), ("endgame_ms", ctypes.c_double),
                 ("post_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("launches", ctypes.c_int64), ("paths_per_wave", ctypes.c_int32),
-                ("max_n", ctypes.c_int32), ("groups", ctypes.c_int32), ("variant", ctypes.c_int32)]
+                ("max_n", ctypes.c_int32), ("groups", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("lanes_per_path", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32)]
+
+
+class HpTuneChoice(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("lanes_per_path", ctypes.c_int32),
+                ("paths_per_wave", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
+                ("ms", ctypes.c_double), ("ms_default", ctypes.c_double),
+                ("candidates", ctypes.c_int32), ("cached", ctypes.c_int32)]
 
 
 STATS_DTYPE = np.dtype([("steps", np.int32), ("rejections", np.int32),
@@ -143,6 +152,9 @@ def load():
             "hp_server_peak_bytes": (ctypes.c_int, [vp, P(ctypes.c_size_t)]),
             "hp_server_destroy": (None, [vp]),
             "hp_server_set_slice": (ctypes.c_int, [vp, ctypes.c_double, i32]),
+            "hp_plan_set_launch": (ctypes.c_int, [vp, i32, i32]),
+            "hp_plan_tuning": (ctypes.c_int, [vp, P(HpTuneChoice)]),
+            "hp_tune_batch": (ctypes.c_int, [vp, vp, i32, vp, P(HpTolerances), P(HpTuneChoice)]),
             "hp_server_info_get": (ctypes.c_int, [vp, P(HpServerInfo)]),
             "hp_spec_compile": (ctypes.c_int, [P(HpSystem), P(i64)]),
         }

@@ -367,6 +367,31 @@ void pack_append(Packed &P, const hp_system *f, const SysInfo &info, hp_c64 gamm
 }
 
 // Device copy of a Packed image.
+// Pinned host memory (hipHostMalloc), grow-only like DevBuf.
+struct HostBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  HostBuf() = default;
+  HostBuf(const HostBuf &) = delete;
+  HostBuf &operator=(const HostBuf &) = delete;
+  ~HostBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  int alloc(size_t b) {
+    if (b <= bytes && p) return HP_OK;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    hipError_t e = hipHostMalloc(&p, std::max<size_t>(b, 64), hipHostMallocDefault);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return fail(HP_E_OOM, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    }
+    bytes = std::max<size_t>(b, 64);
+    return HP_OK;
+  }
+};
+
 struct DevTables {
   DevBuf tcoef, tmeta, kp, roots, sys, qhead, dcoef, egblk;
   // end-game blocks of a multi-system launch, grouped by n: the blocks of
@@ -445,6 +470,10 @@ struct Kv {
   int nmax = 0;
   int pw = 0;  // lane kernels: paths per wavefront
   const hp::SpecModule *sm = nullptr;  // spec: the loaded module
+  // launch shape (tuning choices): paths per wavefront of a specialised or
+  // dense kernel (0: 64), resident wavefronts per SIMD the launch is capped
+  // at (0: as many as fit)
+  int lp = 0, wps = 0;
 };
 
 constexpr int kDenseCode = 400;
@@ -518,41 +547,70 @@ std::vector<int> kv_candidates(int n, int emax, size_t max_lds) {
 // measured workloads, which stay autotuner candidates).
 int kv_default(int n) { return nmax_for(n); }
 
+// A tuned launch: kernel variant code, paths per wavefront (lp) and
+// wavefronts per SIMD (wps) as in Kv.
+struct TuneVal {
+  int code = 0, lp = 0, wps = 0;
+};
+
 std::mutex g_tune_mu;
-std::map<std::string, int> g_tune_mem;
+std::map<std::string, TuneVal> g_tune_mem;
 
 std::string tune_path() {
   const char *p = std::getenv("HP_TUNE_CACHE");
   return p ? std::string(p) : std::string();
 }
 
-std::string tune_key(const SysInfo &info, int n_terms) {
+// Cache key of one system's shape: device (gfx950 and its compute units), n,
+// terms, largest exponent and largest factor count of a term.
+std::string tune_key(int cus, const SysInfo &info, int n_terms) {
   std::ostringstream o;
-  o << "gfx950:n" << info.n << ":t" << n_terms << ":e" << info.emax << ":k" << info.kmax;
+  o << "gfx950:cu" << cus << ":n" << info.n << ":t" << n_terms << ":e" << info.emax << ":k"
+    << info.kmax;
   return o.str();
 }
 
-int tune_lookup(const std::string &key) {
-  std::lock_guard<std::mutex> g(g_tune_mu);
-  auto it = g_tune_mem.find(key);
-  if (it != g_tune_mem.end()) return it->second;
-  std::string path = tune_path();
-  if (path.empty()) return 0;
-  std::ifstream in(path);
-  std::string k;
-  int w;
-  while (in >> k >> w) g_tune_mem[k] = w;
-  it = g_tune_mem.find(key);
-  return it == g_tune_mem.end() ? 0 : it->second;
+// Cache key of a batch: the number of systems, their range of n, all their
+// terms, the largest exponent and factor count, and whether every system
+// has a dense table.
+std::string tune_key_batch(int cus, const Packed &P, int64_t total_terms) {
+  std::ostringstream o;
+  o << "gfx950:cu" << cus << ":batch:s" << P.sys.size() << ":n" << P.nmin << "-" << P.nl << ":t"
+    << total_terms << ":e" << P.emax << ":k" << P.kmax << ":d" << (P.dense_ok ? 1 : 0);
+  return o.str();
 }
 
-void tune_store(const std::string &key, int nmax) {
+// Lines "key code [lp wps]" of the cache file; later lines win.
+bool tune_lookup(const std::string &key, TuneVal &out) {
   std::lock_guard<std::mutex> g(g_tune_mu);
-  g_tune_mem[key] = nmax;
+  auto it = g_tune_mem.find(key);
+  if (it == g_tune_mem.end()) {
+    std::string path = tune_path();
+    if (path.empty()) return false;
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string k;
+      TuneVal v;
+      if (!(ls >> k >> v.code)) continue;
+      if (!(ls >> v.lp >> v.wps)) v.lp = v.wps = 0;
+      g_tune_mem[k] = v;
+    }
+    it = g_tune_mem.find(key);
+    if (it == g_tune_mem.end()) return false;
+  }
+  out = it->second;
+  return true;
+}
+
+void tune_store(const std::string &key, const TuneVal &v) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune_mem[key] = v;
   std::string path = tune_path();
   if (path.empty()) return;
   std::ofstream out(path, std::ios::app);
-  out << key << " " << nmax << "\n";
+  out << key << " " << v.code << " " << v.lp << " " << v.wps << "\n";
 }
 
 }  // namespace
@@ -639,7 +697,8 @@ struct hp_plan {
   DevTables dev;
   hp_tolerances tol{};
   hp_c64 gamma{};
-  Kv kv;  // kernel variant
+  Kv kv;  // kernel variant and launch shape
+  hp_tune_choice tune{};  // the autotuner's record (zero: not tuned)
   bool spec_default = false;  // default variant: the specialised kernel where it applies
   DevBuf start_dev;  // explicit start points [n_start][n] (general plans)
   // plain-mode state
@@ -733,6 +792,21 @@ size_t kv_lds(const Kv &k, const Packed &P) {
 // LDS bytes, resident workgroups per CU and term staging of variant k for
 // the systems of P.  Group kernels stage small term tables in LDS unless
 // that lowers the number of resident workgroups.
+// Paths a wavefront of variant k holds (systems of up to nl unknowns).
+int kv_paths_per_wave(const Kv &k, int nl) {
+  if ((k.spec || k.dense) && k.lp > 0) return k.lp;
+  return (k.lanes || k.spec || k.dense) ? k.pw : hp::kLanes / std::max(1, nl);
+}
+
+// The launch shape of variant k in the timing record.
+void timing_shape(hp_timing &t, const Kv &k, int nl) {
+  t.paths_per_wave = kv_paths_per_wave(k, nl);
+  t.lanes_per_path = (k.lanes || k.spec || k.dense) ? 1 : nl;
+  t.waves_per_simd = k.wps;
+  t.max_n = k.nmax;
+  t.variant = k.code;
+}
+
 int kv_occupancy(hp_context *ctx, const Kv &k, const Packed &P, size_t *lds, int *per_cu,
                  int *stage, bool sliced = false) {
   *stage = 0;
@@ -823,10 +897,13 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
   int per_cu = 0, stage = 0;
   int rc = kv_occupancy(ctx, k, P, &lds, &per_cu, &stage, sliced);
   if (rc) return rc;
-  // enough wavefronts to hold every path once, at most a full device
-  const int64_t per_wave = (k.lanes || k.spec || k.dense) ? k.pw : hp::kLanes / std::max(1, P.nl);
+  // enough wavefronts to hold every path once, at most a full device (or
+  // the tuned number of wavefronts per SIMD: 4 SIMDs per CU)
+  const int lp = (k.spec || k.dense) ? k.lp : 0;
+  const int64_t per_wave = lp ? lp : kv_paths_per_wave(k, P.nl);
   const int64_t want = (total_paths + per_wave - 1) / per_wave;
-  const int64_t groups = std::min<int64_t>((int64_t)ctx->cus * per_cu, std::max<int64_t>(1, want));
+  const int cap = k.wps > 0 ? std::min(per_cu, 4 * k.wps) : per_cu;
+  const int64_t groups = std::min<int64_t>((int64_t)ctx->cus * cap, std::max<int64_t>(1, want));
   KArgs a;
   std::memset(&a, 0, sizeof(a));
   a.sys = dev.sys.as<DevSys>();
@@ -843,6 +920,7 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
   a.stage = stage;
   a.dcoef = dev.dcoef.as<double2>();
   a.step_budget = sliced ? step_budget : 0;
+  a.lane_paths = lp;
   HIP_TRY(hipMemsetAsync(dev.qhead.p, 0, P.sys.size() * sizeof(unsigned long long), s));
   HIP_TRY(hipEventRecord(e0, s));
   if (k.spec) {
@@ -992,49 +1070,136 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
   return HP_OK;
 }
 
-int autotune(hp_plan *plan) {
-  const std::string key = tune_key(plan->info, plan->n_terms);
-  const int cached = tune_lookup(key);
-  if (cached && plan_variant(plan, cached) == HP_OK) return HP_OK;
-  hp_context *ctx = plan->ctx;
-  // sample: a few resident rounds of the widest variant
-  const int64_t sample = std::min<int64_t>(plan->info.paths, (int64_t)ctx->cus * 4 * 64 * 2);
-  DevBuf e, st;
-  int rc;
-  if ((rc = e.alloc((size_t)sample * plan->info.n * sizeof(hp_c64)))) return rc;
-  if ((rc = st.alloc((size_t)sample * sizeof(int32_t)))) return rc;
-  double best = 1e300;
-  Kv best_k = plan->kv;
-  std::vector<int> cands = kv_candidates(plan->info.n, plan->P.emax, ctx->max_lds);
-  if (plan_spec_eligible(plan)) cands.insert(cands.begin(), 300 + plan->info.n);
-  if (!plan->P.general)
-    if (const int dc = dense_code_for(plan->P)) cands.push_back(dc);
-  for (int code : cands) {
-    Kv k;
-    if (!kv_decode(code, k) || check_lds(ctx, kv_lds(k, plan->P)) != HP_OK) continue;
-    if (k.lanes && plan->P.general) continue;
-    if (k.spec && (rc = spec_prepare(plan, k))) return rc;
-    double tms = 0.0;
-    for (int rep = 0; rep < 2; ++rep) {  // the second repetition counts
-      DevSys d = plan->P.sys[0];
-      d.n_paths = sample;
-      d.ids = nullptr;
-      HIP_TRY(hipMemcpyAsync(plan->dev.sys.p, &d, sizeof(d), hipMemcpyHostToDevice, ctx->stream));
-      rc = launch_persistent(ctx, plan->dev, plan->P, k, plan->tol, sample, e.as<hp_c64>(),
-                             st.as<int32_t>(), nullptr, ctx->stream, nullptr);
-      if (rc) return rc;
-      HIP_TRY(hipStreamSynchronize(ctx->stream));
-      float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-      tms = ms;
+// Launch shapes of variant k to time: paths per wavefront 64 or 32 for the
+// specialised and dense kernels, and every cap on the wavefronts per SIMD
+// that binds (below the occupancy of the variant).
+std::vector<Kv> tune_shapes(hp_context *ctx, const Kv &k, const Packed &P) {
+  std::vector<Kv> out;
+  size_t lds = 0;
+  int per_cu = 0, stage = 0;
+  if (kv_occupancy(ctx, k, P, &lds, &per_cu, &stage) != HP_OK) return out;
+  const int max_wps = (per_cu + 3) / 4;
+  for (int lp : (k.spec || k.dense) ? std::vector<int>{0, 32} : std::vector<int>{0})
+    for (int wps = 0; wps < max_wps; ++wps) {
+      Kv v = k;
+      v.lp = lp;
+      v.wps = wps;
+      out.push_back(v);
     }
-    if (tms < best) {
-      best = tms;
+  return out;
+}
+
+// Times candidate launch shapes with run(k) (the kernel milliseconds of one
+// launch over the sample the caller set up; the second of two runs counts)
+// and returns the fastest; default_ms: the time of `def`'s shape.
+template <class Run>
+int tune_pick(const std::vector<Kv> &cands, const Kv &def, Run run, Kv &best_k, hp_tune_choice &c) {
+  double best = 1e300;
+  c.ms_default = -1.0;
+  c.candidates = 0;
+  for (const Kv &k : cands) {
+    float ms = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {
+      const int rc = run(k, ms);
+      if (rc) return rc;
+    }
+    ++c.candidates;
+    if (k.code == def.code && k.lp == def.lp && k.wps == def.wps) c.ms_default = ms;
+    if (ms < best) {
+      best = ms;
       best_k = k;
     }
   }
+  c.ms = best;
+  return HP_OK;
+}
+
+// Packs a batch (offsets from hp_batch_layout); total_terms: all terms.
+int pack_batch(const hp_system *fs, int32_t n_systems, const hp_c64 *gammas,
+               std::vector<int64_t> &po, std::vector<int64_t> &xo, Packed &P, int64_t &total_terms) {
+  int rc = hp_batch_layout(fs, n_systems, po.data(), xo.data());
+  if (rc) return rc;
+  total_terms = 0;
+  for (int s = 0; s < n_systems; ++s) {
+    SysInfo info;
+    check_system(&fs[s], info);
+    pack_append(P, &fs[s], info, gammas[s], info.paths, po[s], xo[s], nullptr);
+    total_terms += fs[s].n_terms;
+  }
+  return HP_OK;
+}
+
+// Variant `code` runs every system of the batch P (dense or group kernels).
+bool batch_variant_ok(hp_context *ctx, const Packed &P, int code, Kv &k) {
+  if (!kv_decode(code, k) || k.lanes || k.spec) return false;
+  if (k.dense) return dense_fits(k, P);
+  return k.nmax >= P.nl && check_lds(ctx, P.lds(k.nmax, false)) == HP_OK;
+}
+
+void choice_from_kv(hp_tune_choice &c, const Kv &k, int nl) {
+  hp_timing t{};
+  timing_shape(t, k, nl);
+  c.variant = k.code;
+  c.paths_per_wave = t.paths_per_wave;
+  c.lanes_per_path = t.lanes_per_path;
+  c.waves_per_simd = k.wps;
+}
+
+// Checks a cached or forced launch shape against variant k.
+bool shape_ok(const Kv &k, int lp, int wps) {
+  return wps >= 0 && wps <= 64 && (lp == 0 || ((k.spec || k.dense) && lp >= 1 && lp <= hp::kLanes));
+}
+
+int autotune(hp_plan *plan) {
+  hp_context *ctx = plan->ctx;
+  const std::string key = tune_key(ctx->cus, plan->info, plan->n_terms);
+  plan->tune = hp_tune_choice{};
+  TuneVal cv;
+  if (tune_lookup(key, cv) && plan_variant(plan, cv.code) == HP_OK && shape_ok(plan->kv, cv.lp, cv.wps)) {
+    plan->kv.lp = cv.lp;
+    plan->kv.wps = cv.wps;
+    choice_from_kv(plan->tune, plan->kv, plan->info.n);
+    plan->tune.cached = 1;
+    return HP_OK;
+  }
+  int rc;
+  if ((rc = plan_variant(plan, 0))) return rc;
+  const Kv def = plan->kv;
+  // sample: a few resident rounds of the widest variant
+  const int64_t sample = std::min<int64_t>(plan->info.paths, (int64_t)ctx->cus * 4 * 64 * 2);
+  DevBuf e, st;
+  if ((rc = e.alloc((size_t)sample * plan->info.n * sizeof(hp_c64)))) return rc;
+  if ((rc = st.alloc((size_t)sample * sizeof(int32_t)))) return rc;
+  std::vector<int> codes = kv_candidates(plan->info.n, plan->P.emax, ctx->max_lds);
+  if (plan_spec_eligible(plan)) codes.insert(codes.begin(), 300 + plan->info.n);
+  if (!plan->P.general)
+    if (const int dc = dense_code_for(plan->P)) codes.push_back(dc);
+  std::vector<Kv> cands;
+  for (int code : codes) {
+    Kv k;
+    if (!kv_decode(code, k) || check_lds(ctx, kv_lds(k, plan->P)) != HP_OK) continue;
+    if (k.lanes && plan->P.general) continue;
+    if (k.dense && !dense_fits(k, plan->P)) continue;
+    if (k.spec && (rc = spec_prepare(plan, k))) return rc;
+    for (const Kv &v : tune_shapes(ctx, k, plan->P)) cands.push_back(v);
+  }
+  DevSys d = plan->P.sys[0];
+  d.n_paths = sample;
+  d.ids = nullptr;
+  HIP_TRY(hipMemcpyAsync(plan->dev.sys.p, &d, sizeof(d), hipMemcpyHostToDevice, ctx->stream));
+  Kv best_k = def;
+  rc = tune_pick(cands, def, [&](const Kv &k, float &ms) {
+    int r = launch_persistent(ctx, plan->dev, plan->P, k, plan->tol, sample, e.as<hp_c64>(),
+                              st.as<int32_t>(), nullptr, ctx->stream, nullptr);
+    if (r) return r;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    return HP_OK;
+  }, best_k, plan->tune);
+  if (rc) return rc;
   plan->kv = best_k;
-  tune_store(key, best_k.code);
+  choice_from_kv(plan->tune, best_k, plan->info.n);
+  tune_store(key, TuneVal{best_k.code, best_k.lp, best_k.wps});
   return HP_OK;
 }
 
@@ -1142,6 +1307,22 @@ int hp_plan_set_variant(hp_plan *plan, int32_t variant) {
   return plan_variant(plan, variant);
 }
 
+int hp_plan_set_launch(hp_plan *plan, int32_t paths_per_wave, int32_t waves_per_simd) {
+  if (!plan) return fail(HP_E_INVALID_ARG, "plan is NULL");
+  if (!shape_ok(plan->kv, paths_per_wave, waves_per_simd))
+    return fail(HP_E_INVALID_ARG, "paths_per_wave must be 0 (or 1..64 on a specialised or dense "
+                                  "kernel), waves_per_simd 0..64");
+  plan->kv.lp = paths_per_wave == hp::kLanes ? 0 : paths_per_wave;
+  plan->kv.wps = waves_per_simd;
+  return HP_OK;
+}
+
+int hp_plan_tuning(const hp_plan *plan, hp_tune_choice *out) {
+  if (!plan || !out) return fail(HP_E_INVALID_ARG, "NULL argument");
+  *out = plan->tune;
+  return HP_OK;
+}
+
 int hp_plan_track_device(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endpoints,
                          int32_t *status, hp_path_stats *stats, int32_t mode, void *stream) {
   if (!plan) return fail(HP_E_INVALID_ARG, "plan is NULL");
@@ -1155,10 +1336,7 @@ int hp_plan_track_device(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_
   hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
   const double t0 = now_ms();
   ctx->last = hp_timing{};
-  ctx->last.paths_per_wave = (plan->kv.lanes || plan->kv.spec || plan->kv.dense) ? plan->kv.pw
-                                                                                 : hp::kLanes / plan->info.n;
-  ctx->last.max_n = plan->kv.nmax;
-  ctx->last.variant = plan->kv.code;
+  timing_shape(ctx->last, plan->kv, plan->info.n);
   if (n_paths == 0) return HP_OK;
   int rc;
   if (mode == HP_PLAIN) {
@@ -1302,6 +1480,7 @@ int hp_track_paths_dd(hp_context *ctx, const hp_system *f, const hp_c64 *start, 
   ctx->last.launches = 1;
   ctx->last.groups = (int32_t)groups;
   ctx->last.paths_per_wave = (int32_t)per_wave;
+  ctx->last.lanes_per_path = n;
   ctx->last.max_n = n;
   ctx->last.variant = 500 + n;
   ctx->last.total_ms = now_ms() - t0;
@@ -1337,14 +1516,20 @@ int hp_track_batch(hp_context *ctx, const hp_system *fs, int32_t n_systems, cons
   const double t0 = now_ms();
   HIP_TRY(hipSetDevice(ctx->device));
   std::vector<int64_t> po(n_systems + 1), xo(n_systems + 1);
-  if ((rc = hp_batch_layout(fs, n_systems, po.data(), xo.data()))) return rc;
   Packed P;
-  for (int s = 0; s < n_systems; ++s) {
-    SysInfo info;
-    check_system(&fs[s], info);
-    pack_append(P, &fs[s], info, gammas[s], info.paths, po[s], xo[s], nullptr);
+  int64_t total_terms = 0;
+  if ((rc = pack_batch(fs, n_systems, gammas, po, xo, P, total_terms))) return rc;
+  // the tuned launch of batches of this shape, if any (hp_tune_batch)
+  Kv kv = kv_pick(P);
+  TuneVal cv;
+  if (tune_lookup(tune_key_batch(ctx->cus, P, total_terms), cv)) {
+    Kv k;
+    if (batch_variant_ok(ctx, P, cv.code, k) && shape_ok(k, cv.lp, cv.wps)) {
+      k.lp = cv.lp;
+      k.wps = cv.wps;
+      kv = k;
+    }
   }
-  const Kv kv = kv_pick(P);
   DevTables dev;
   if ((rc = dev.upload(P, ctx->stream))) return rc;
   DevBuf e, st, sts;
@@ -1371,10 +1556,61 @@ int hp_track_batch(hp_context *ctx, const hp_system *fs, int32_t n_systems, cons
   ctx->last.kernel_ms = ms;
   ctx->last.launches = 1;
   ctx->last.groups = groups;
-  ctx->last.paths_per_wave = (kv.lanes || kv.dense) ? kv.pw : hp::kLanes / P.nl;
-  ctx->last.max_n = kv.nmax;
-  ctx->last.variant = kv.code;
+  timing_shape(ctx->last, kv, P.nl);
   ctx->last.total_ms = now_ms() - t0;
+  return HP_OK;
+}
+
+int hp_tune_batch(hp_context *ctx, const hp_system *fs, int32_t n_systems, const hp_c64 *gammas,
+                  const hp_tolerances *tol, hp_tune_choice *out) {
+  if (!ctx || !fs || n_systems < 1 || !gammas || !out)
+    return fail(HP_E_INVALID_ARG, "bad batch arguments");
+  *out = hp_tune_choice{};
+  int rc = check_tol(tol);
+  if (rc) return rc;
+  hp_tolerances T;
+  if (tol) T = *tol;
+  else hp_default_tolerances(&T);
+  HIP_TRY(hipSetDevice(ctx->device));
+  std::vector<int64_t> po(n_systems + 1), xo(n_systems + 1);
+  Packed P;
+  int64_t total_terms = 0;
+  if ((rc = pack_batch(fs, n_systems, gammas, po, xo, P, total_terms))) return rc;
+  const Kv def = kv_pick(P);
+  std::vector<Kv> cands;
+  std::vector<int> codes;
+  if (const int dc = dense_code_for(P)) codes.push_back(dc);
+  for (int v : hp::kNmaxVariants) codes.push_back(v);
+  for (int code : codes) {
+    Kv k;
+    if (!batch_variant_ok(ctx, P, code, k)) continue;
+    for (const Kv &v : tune_shapes(ctx, k, P)) cands.push_back(v);
+  }
+  // sample: every system's first paths, a share of about two resident rounds
+  const int64_t total = po[n_systems];
+  const int64_t want = std::min<int64_t>(total, (int64_t)ctx->cus * 4 * 64 * 2);
+  int64_t sample = 0;
+  for (DevSys &d : P.sys) {
+    d.n_paths = std::max<int64_t>(1, (d.n_paths * want + total - 1) / total);
+    sample += d.n_paths;
+  }
+  DevTables dev;
+  if ((rc = dev.upload(P, ctx->stream))) return rc;
+  DevBuf e, st;
+  if ((rc = e.alloc((size_t)std::max<int64_t>(1, xo[n_systems]) * sizeof(hp_c64)))) return rc;
+  if ((rc = st.alloc((size_t)std::max<int64_t>(1, total) * sizeof(int32_t)))) return rc;
+  Kv best = def;
+  rc = tune_pick(cands, def, [&](const Kv &k, float &ms) {
+    int r = launch_persistent(ctx, dev, P, k, T, sample, e.as<hp_c64>(), st.as<int32_t>(), nullptr,
+                              ctx->stream, nullptr);
+    if (r) return r;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    return HP_OK;
+  }, best, *out);
+  if (rc) return rc;
+  choice_from_kv(*out, best, P.nl);
+  tune_store(tune_key_batch(ctx->cus, P, total_terms), TuneVal{best.code, best.lp, best.wps});
   return HP_OK;
 }
 
@@ -1769,9 +2005,7 @@ int hp_membership_test(hp_context *ctx, const hp_system *e, int32_t n_hyper, con
   ctx->last.endgame_ms = eg;
   ctx->last.launches = 1;
   ctx->last.groups = groups;
-  ctx->last.paths_per_wave = hp::kLanes / n;
-  ctx->last.max_n = kv.nmax;
-  ctx->last.variant = kv.code;
+  timing_shape(ctx->last, kv, n);
   ctx->last.total_ms = now_ms() - t0;
   return HP_OK;
 }
@@ -1957,9 +2191,9 @@ namespace {
 
 constexpr int64_t kEpochPaths = 1 << 18;  // queue entries per epoch over all requests
 constexpr int64_t kMinChunk = 4096;
-constexpr int32_t kInitialBudget = 64;  // steps per wavefront in a family's first slice
+constexpr int32_t kInitialBudget = 16;  // steps per wavefront in a family's first slice
 constexpr int32_t kMinBudget = 4, kMaxBudget = 1 << 20;
-constexpr double kDefaultSliceMs = 20.0;
+constexpr double kDefaultSliceMs = 50.0;
 
 struct Entry {
   int64_t pid, slot;  // path id, slot in the request's region
@@ -2039,8 +2273,12 @@ struct hp_server {
   DevBuf a_ends, a_status, a_stats;
   int64_t arena_paths = 0;
   std::vector<std::pair<int64_t, int64_t>> free_list;  // (offset, length) in paths
-  // epoch queues and harvest records
-  DevBuf q_ids, q_slots, c_path, c_xoff, c_n, r_entry, r_status, r_x, r_stats, r_count;
+  // epoch queues and harvest records: one block each, on the device and
+  // pinned on the host (queue: ids, slots, path slots, endpoint offsets
+  // (int64 each), n (int32); records: entry, status (int32 each), stats,
+  // endpoints (HP_MAX_N each)), and the record count
+  DevBuf q_dev, r_dev, r_count;
+  HostBuf q_host, r_host;
 
   int64_t largest_free() const {
     int64_t m = 0;
@@ -2104,14 +2342,6 @@ void admit(hp_server *S) {
   }
 }
 
-template <class T>
-int upload_vec(DevBuf &d, const std::vector<T> &h, hipStream_t s) {
-  int rc = d.alloc(std::max<size_t>(1, h.size()) * sizeof(T));
-  if (rc) return rc;
-  if (!h.empty()) HIP_TRY(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
-  return HP_OK;
-}
-
 int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
   hp_context *ctx = S->ctx;
   double slice_ms;
@@ -2131,21 +2361,32 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
   const int64_t share = std::max<int64_t>(kMinChunk, kEpochPaths / (int64_t)same);
 
   // ---- queues: suspended and waiting paths first, then new paths ----
-  std::vector<int64_t> h_ids, h_slots, h_path, h_xoff;
-  std::vector<int32_t> h_n, h_owner;
+  int64_t cap = 0;  // entries this epoch at most
+  for (auto &R : batch)
+    if (std::memcmp(&R->tol, &tol, sizeof(tol)) == 0) cap += share;
+  const size_t qstride = (size_t)cap;
+  int rc;
+  if ((rc = S->q_host.alloc(qstride * (4 * sizeof(int64_t) + sizeof(int32_t))))) return rc;
+  int64_t *h_ids = (int64_t *)S->q_host.p, *h_slots = h_ids + qstride, *h_path = h_slots + qstride,
+          *h_xoff = h_path + qstride;
+  int32_t *h_n = (int32_t *)(h_xoff + qstride);
+  std::vector<int32_t> h_owner;
+  h_owner.reserve((size_t)cap);
+  int64_t E = 0;
   for (size_t i = 0; i < batch.size(); ++i) {
     Request &R = *batch[i];
-    R.qoff = (int64_t)h_ids.size();
+    R.qoff = E;
     R.qlen = R.qtaken = 0;
     if (std::memcmp(&R.tol, &tol, sizeof(tol)) != 0) continue;
     const int n = R.info.n;
     auto push = [&](int64_t pid, int64_t slot) {
-      h_ids.push_back(pid);
-      h_slots.push_back(slot);
-      h_path.push_back(R.region_off + slot);
-      h_xoff.push_back(R.region_off * HP_MAX_N + slot * n);
-      h_n.push_back(n);
+      h_ids[E] = pid;
+      h_slots[E] = slot;
+      h_path[E] = R.region_off + slot;
+      h_xoff[E] = R.region_off * HP_MAX_N + slot * n;
+      h_n[E] = n;
       h_owner.push_back((int32_t)i);
+      ++E;
     };
     if (!R.sliceable()) {
       // group kernels: the next chunk of path ids in slots 0, 1, ...
@@ -2157,24 +2398,23 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
       for (int64_t k = 0; k < take; ++k) push(R.live[(size_t)k].pid, R.live[(size_t)k].slot);
       R.live.erase(R.live.begin(), R.live.begin() + take);
       R.qtaken = take;
-      while ((int64_t)h_ids.size() - R.qoff < share && R.next_path < R.info.paths &&
-             !R.free_slots.empty()) {
+      while (E - R.qoff < share && R.next_path < R.info.paths && !R.free_slots.empty()) {
         push(R.next_path++, R.free_slots.back());
         R.free_slots.pop_back();
       }
     }
-    R.qlen = (int64_t)h_ids.size() - R.qoff;
+    R.qlen = E - R.qoff;
   }
-  const int64_t E = (int64_t)h_ids.size();
   if (E == 0) return HP_OK;
   if (E > INT32_MAX) return fail(HP_E_INVALID_ARG, "epoch queue too long");
-  int rc;
-  if ((rc = upload_vec(S->q_ids, h_ids, S->stream))) return rc;
-  if ((rc = upload_vec(S->q_slots, h_slots, S->stream))) return rc;
-  if ((rc = upload_vec(S->c_path, h_path, S->stream))) return rc;
-  if ((rc = upload_vec(S->c_xoff, h_xoff, S->stream))) return rc;
-  if ((rc = upload_vec(S->c_n, h_n, S->stream))) return rc;
+  // device copy of the queue block (same layout, stride qstride)
+  if ((rc = S->q_dev.alloc(S->q_host.bytes))) return rc;
+  HIP_TRY(hipMemcpyAsync(S->q_dev.p, S->q_host.p, qstride * (4 * sizeof(int64_t) + sizeof(int32_t)),
+                         hipMemcpyHostToDevice, S->stream));
   HIP_TRY(hipStreamSynchronize(S->stream));
+  int64_t *d_ids = S->q_dev.as<int64_t>(), *d_slots = d_ids + qstride, *d_path = d_slots + qstride,
+          *d_xoff = d_path + qstride;
+  int32_t *d_n = (int32_t *)(d_xoff + qstride);
 
   // ---- one launch per kernel family, each request on the family it runs
   // on alone, so that its result does not depend on the other requests ----
@@ -2200,6 +2440,14 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
       } else if (R.dense_code) {
         kv_decode(R.dense_code, kv);
       }
+      // the launch shape tuned for the family's first system, when the
+      // tuner chose this family's kernel for it (hp_plan_create with tuning)
+      TuneVal cv;
+      if ((R.sm || R.dense_code) && tune_lookup(tune_key(ctx->cus, R.info, R.sys.n_terms), cv) &&
+          cv.code == kv.code && shape_ok(kv, cv.lp, cv.wps)) {
+        kv.lp = cv.lp;
+        kv.wps = cv.wps;
+      }
       fam_kv.push_back(kv);  // group family: chosen from its systems below
     }
     const size_t f = it->second;
@@ -2207,12 +2455,12 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
     // region_off, endpoint slots of n coordinates from region_off * HP_MAX_N
     if (R.sliceable()) {
       pack_append(P[f], &R.sys, R.info, R.gamma, R.qlen, R.region_off, R.region_off * HP_MAX_N,
-                  S->q_ids.as<int64_t>() + R.qoff);
-      P[f].sys.back().slots = S->q_slots.as<int64_t>() + R.qoff;
+                  d_ids + R.qoff);
+      P[f].sys.back().slots = d_slots + R.qoff;
     } else {
       pack_append(P[f], &R.sys, R.info, R.gamma, R.qlen, R.region_off, R.region_off * HP_MAX_N,
                   nullptr);
-      P[f].sys.back().id_base = h_ids[(size_t)R.qoff];
+      P[f].sys.back().id_base = h_ids[R.qoff];
     }
     total[f] += R.qlen;
   }
@@ -2259,52 +2507,56 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
     HIP_TRY(hipEventElapsedTime(&fam_ms[f], S->fam_ev[f][0], S->fam_ev[f][1]));
 
   // ---- harvest: finished paths to the host results, slots freed ----
-  if ((rc = S->r_entry.alloc((size_t)E * sizeof(int32_t)))) return rc;
-  if ((rc = S->r_status.alloc((size_t)E * sizeof(int32_t)))) return rc;
-  if ((rc = S->r_x.alloc((size_t)E * HP_MAX_N * sizeof(hp_c64)))) return rc;
-  if ((rc = S->r_stats.alloc((size_t)E * sizeof(hp_path_stats)))) return rc;
+  const size_t rstride = (size_t)E;
+  const size_t rbytes = rstride * (2 * sizeof(int32_t) + sizeof(hp_path_stats) + HP_MAX_N * sizeof(hp_c64));
+  if ((rc = S->r_dev.alloc(rbytes))) return rc;
+  if ((rc = S->r_host.alloc(rbytes))) return rc;
   if ((rc = S->r_count.alloc(sizeof(unsigned)))) return rc;
+  // record block: x first (16-byte aligned), then stats, entry, status
+  hp_c64 *dr_x = S->r_dev.as<hp_c64>();
+  hp_path_stats *dr_stats = (hp_path_stats *)(dr_x + rstride * HP_MAX_N);
+  int32_t *dr_entry = (int32_t *)(dr_stats + rstride), *dr_status = dr_entry + rstride;
+  hp_c64 *hr_x = (hp_c64 *)S->r_host.p;
+  hp_path_stats *hr_stats = (hp_path_stats *)(hr_x + rstride * HP_MAX_N);
+  int32_t *hr_entry = (int32_t *)(hr_stats + rstride), *hr_status = hr_entry + rstride;
   HIP_TRY(hipMemsetAsync(S->r_count.p, 0, sizeof(unsigned), S->stream));
   hp::CollectArgs ca;
   ca.m = E;
-  ca.path_slot = (const long long *)S->c_path.as<int64_t>();
-  ca.x_off = (const long long *)S->c_xoff.as<int64_t>();
-  ca.n = S->c_n.as<int32_t>();
+  ca.path_slot = (const long long *)d_path;
+  ca.x_off = (const long long *)d_xoff;
+  ca.n = d_n;
   ca.status = S->a_status.as<int32_t>();
   ca.endpoints = (const double2 *)S->a_ends.as<hp_c64>();
   ca.stats = S->a_stats.as<hp_path_stats>();
-  ca.rec_entry = S->r_entry.as<int32_t>();
-  ca.rec_status = S->r_status.as<int32_t>();
-  ca.rec_x = (double2 *)S->r_x.as<hp_c64>();
-  ca.rec_stats = S->r_stats.as<hp_path_stats>();
+  ca.rec_entry = dr_entry;
+  ca.rec_status = dr_status;
+  ca.rec_x = (double2 *)dr_x;
+  ca.rec_stats = dr_stats;
   ca.count = S->r_count.as<unsigned>();
   HIP_TRY((hipError_t)hp_launch_collect(ca, S->stream));
   unsigned cnt = 0;
   HIP_TRY(hipMemcpyAsync(&cnt, S->r_count.p, sizeof(unsigned), hipMemcpyDeviceToHost, S->stream));
   HIP_TRY(hipStreamSynchronize(S->stream));
   if ((int64_t)cnt > E) return fail(HP_E_DEVICE, "harvest count out of range");
-  std::vector<int32_t> r_entry(cnt), r_status(cnt);
-  std::vector<hp_c64> r_x((size_t)cnt * HP_MAX_N);
-  std::vector<hp_path_stats> r_stats(cnt);
   if (cnt) {
-    HIP_TRY(hipMemcpyAsync(r_entry.data(), S->r_entry.p, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, S->stream));
-    HIP_TRY(hipMemcpyAsync(r_status.data(), S->r_status.p, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, S->stream));
-    HIP_TRY(hipMemcpyAsync(r_x.data(), S->r_x.p, r_x.size() * sizeof(hp_c64), hipMemcpyDeviceToHost, S->stream));
-    HIP_TRY(hipMemcpyAsync(r_stats.data(), S->r_stats.p, cnt * sizeof(hp_path_stats), hipMemcpyDeviceToHost, S->stream));
+    HIP_TRY(hipMemcpyAsync(hr_entry, dr_entry, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, S->stream));
+    HIP_TRY(hipMemcpyAsync(hr_status, dr_status, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, S->stream));
+    HIP_TRY(hipMemcpyAsync(hr_x, dr_x, (size_t)cnt * HP_MAX_N * sizeof(hp_c64), hipMemcpyDeviceToHost, S->stream));
+    HIP_TRY(hipMemcpyAsync(hr_stats, dr_stats, cnt * sizeof(hp_path_stats), hipMemcpyDeviceToHost, S->stream));
     HIP_TRY(hipStreamSynchronize(S->stream));
   }
   std::vector<uint8_t> finished((size_t)E, 0);
   for (unsigned r = 0; r < cnt; ++r) {
-    const int64_t k = r_entry[r];
+    const int64_t k = hr_entry[r];
     if (k < 0 || k >= E || finished[(size_t)k]) return fail(HP_E_DEVICE, "harvest record out of range");
     finished[(size_t)k] = 1;
     Request &R = *batch[(size_t)h_owner[(size_t)k]];
-    const int64_t pid = h_ids[(size_t)k], n = R.info.n;
-    std::memcpy(R.ends.data() + pid * n, r_x.data() + (size_t)r * HP_MAX_N, (size_t)n * sizeof(hp_c64));
-    R.status[(size_t)pid] = r_status[r];
-    R.stats[(size_t)pid] = r_stats[r];
+    const int64_t pid = h_ids[k], n = R.info.n;
+    std::memcpy(R.ends.data() + pid * n, hr_x + (size_t)r * HP_MAX_N, (size_t)n * sizeof(hp_c64));
+    R.status[(size_t)pid] = hr_status[r];
+    R.stats[(size_t)pid] = hr_stats[r];
     R.done_paths += 1;
-    if (R.sliceable()) R.free_slots.push_back(h_slots[(size_t)k]);
+    if (R.sliceable()) R.free_slots.push_back(h_slots[k]);
   }
   // unfinished queue entries keep their slots and go first next epoch
   int64_t carried = 0;
@@ -2314,7 +2566,7 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
     if (R.qlen == 0) continue;
     std::vector<Entry> keep;
     for (int64_t k = R.qoff; k < R.qoff + R.qlen; ++k)
-      if (!finished[(size_t)k]) keep.push_back({h_ids[(size_t)k], h_slots[(size_t)k]});
+      if (!finished[(size_t)k]) keep.push_back({h_ids[k], h_slots[k]});
     if (!keep.empty() && !R.sliceable()) return fail(HP_E_DEVICE, "a group-kernel path did not finish");
     carried += (int64_t)keep.size();
     if (!keep.empty()) fam_open[fam_of[R.family()]] = true;

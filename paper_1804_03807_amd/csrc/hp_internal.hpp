@@ -117,7 +117,15 @@ struct KArgs {
   int32_t step_budget;   // serving kernels: steps per wavefront in this launch (0: until
                          // the queues are drained); past it, paths in flight are
                          // suspended to their slots
+  int32_t lane_paths;    // specialised and dense kernels: lanes 0 .. lane_paths - 1 of a
+                         // wavefront hold paths (0: all 64), a tuning choice
 };
+
+// Lanes of a wavefront that take paths from the refill queue in the
+// one-path-per-lane kernels whose paths per wavefront are a launch argument.
+__device__ __forceinline__ bool lane_holds_path(const KArgs &a) {
+  return (int)(threadIdx.x & 63) < (a.lane_paths > 0 ? a.lane_paths : kLanes);
+}
 
 // Status codes of a slot that holds a suspended path (serving) or a path not
 // started yet; a finished path's status is its hp_status (>= 0).

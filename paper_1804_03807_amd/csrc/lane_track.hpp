@@ -412,8 +412,9 @@ __device__ __forceinline__ bool lane_drain(const KArgs &a, T &tr, int s, int &wa
         return true;
       }
     }
-    // ---- refill idle lanes: one atomic per wavefront ----
-    const bool idle = tr.slot && tr.mode == M_IDLE;
+    // ---- refill idle lanes: one atomic per wavefront (lanes past the
+    // launch's paths per wavefront stay idle) ----
+    const bool idle = tr.slot && tr.mode == M_IDLE && lane_holds_path(a);
     const uint64_t m = ballot(idle);
     if (m != 0 && !exhausted) {
       const unsigned cnt = __popcll(m);

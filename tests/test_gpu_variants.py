@@ -145,12 +145,19 @@ def test_autotune_chooses_a_valid_variant(ctx, tmp_path, monkeypatch):
     e, st, sts = plan.outputs(P)
     plan.track_device(e, st, sts)
     torch.cuda.synchronize()
-    code = ctx.last_timing()["variant"]
-    log(f"autotuned variant {code}")
+    t = ctx.last_timing()
+    code = t["variant"]
+    choice = plan.tuning()
+    log(f"autotuned variant {code}, choice {choice}")
     assert code in GROUP + LANES + SPEC + DENSE
     assert code < 100 or code % 100 == s.n
-    text = cache.read_text().split()
-    assert len(text) == 2 and int(text[1]) == code
+    assert choice["variant"] == code and choice["cached"] == 0 and choice["candidates"] >= 4
+    assert choice["paths_per_wave"] == t["paths_per_wave"]
+    assert choice["waves_per_simd"] == t["waves_per_simd"]
+    assert choice["lanes_per_path"] == t["lanes_per_path"] == (s.n if code < 100 else 1)
+    assert 0 < choice["ms"] <= choice["ms_default"]
+    text = cache.read_text().split()  # key, variant, paths per wavefront (0: 64), waves per SIMD
+    assert len(text) == 4 and int(text[1]) == code and int(text[3]) == choice["waves_per_simd"]
     e_o, s_o, _ = oracle_ref("cyclic6", s, g)
     assert_parity(hp.Plan.endpoints_to_numpy(e), st.cpu().numpy(), e_o, s_o, "autotuned", s)
     plan.close()
@@ -159,7 +166,71 @@ def test_autotune_chooses_a_valid_variant(ctx, tmp_path, monkeypatch):
     plan2.track_device(e2, st2)
     torch.cuda.synchronize()
     assert ctx.last_timing()["variant"] == code
+    assert plan2.tuning()["cached"] == 1
     plan2.close()
+
+
+@pytest.mark.parametrize("name", ["cyclic6", "dense8_d2", "dense11_d2"])
+def test_launch_shape_keeps_results(ctx, name):
+    """The autotuner's launch shapes (32 of 64 lanes holding paths, a cap of
+    one wavefront per SIMD) leave every path's result bit for bit as it is:
+    paths are tracked independently."""
+    import torch
+    import paper_1804_03807_amd as hp
+    s, g = CASES[name]()
+    P = s.bezout()
+    plan = ctx.plan(s, g)
+    if name != "cyclic6":
+        plan.set_variant(400 if s.n <= 10 else 400 + s.n)
+    ref = None
+    for lp, wps in [(0, 0), (32, 0), (0, 1), (48, 1), (32, 2)]:
+        plan.set_launch(lp, wps)
+        e, st, sts = plan.outputs(P)
+        plan.track_device(e, st, sts)
+        torch.cuda.synchronize()
+        t = ctx.last_timing()
+        assert t["paths_per_wave"] == (lp or 64) and t["waves_per_simd"] == wps
+        out = (hp.Plan.endpoints_to_numpy(e), st.cpu().numpy(), sts.cpu().numpy().tobytes())
+        if ref is None:
+            ref = out
+            continue
+        assert np.array_equal(out[0].view(np.float64), ref[0].view(np.float64)), (lp, wps)
+        assert np.array_equal(out[1], ref[1]) and out[2] == ref[2], (lp, wps)
+    with pytest.raises(hp.HomotopyError):
+        plan.set_launch(65, 0)
+    with pytest.raises(hp.HomotopyError):
+        plan.set_launch(0, -1)
+    plan.set_variant(GROUP[1] if s.n <= 8 else GROUP[-1])
+    with pytest.raises(hp.HomotopyError):
+        plan.set_launch(32, 0)  # group kernels: paths per wavefront fixed by n
+    plan.close()
+
+
+def test_tune_batch(ctx, tmp_path, monkeypatch):
+    """hp_tune_batch times the variants that run a whole batch with every
+    launch shape and caches the fastest; hp_track_batch on that batch then
+    launches with it, and its results match the untuned launch's."""
+    monkeypatch.setenv("HP_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    rng = np.random.default_rng(606)
+    systems = [W.dense_system(int(n), [2] * int(n), rng) for n in rng.integers(3, 8, size=24)]
+    gammas = W.unit_circle(rng, len(systems))
+    ref = ctx.track_batch(systems, gammas)
+    t_ref = ctx.last_timing()
+    choice = ctx.tune_batch(systems, gammas)
+    log(f"untuned variant {t_ref['variant']}; batch choice {choice}")
+    assert choice["candidates"] >= 4 and choice["cached"] == 0
+    assert choice["variant"] in GROUP + [400]
+    out = ctx.track_batch(systems, gammas)
+    t = ctx.last_timing()
+    assert t["variant"] == choice["variant"]
+    assert t["paths_per_wave"] == choice["paths_per_wave"]
+    assert t["waves_per_simd"] == choice["waves_per_simd"]
+    same_kernel = choice["variant"] == t_ref["variant"]
+    for k, (s, (e, st, _), (e0, st0, _)) in enumerate(zip(systems, out, ref)):
+        if same_kernel:
+            assert np.array_equal(e.view(np.float64), e0.view(np.float64)) and np.array_equal(st, st0)
+        else:
+            assert_parity(e, st, e0, st0, f"batch system {k}", s)
 
 
 @pytest.mark.parametrize("name", ["cyclic6", "dense8_d2"])

@@ -26,8 +26,8 @@ dense systems.
 from __future__ import annotations
 
 import dataclasses
+import functools
 import hashlib
-import itertools
 import math
 
 import numpy as np
@@ -93,15 +93,29 @@ def _assemble(n, eq_terms, name):
     return s
 
 
+def _compositions(n: int, deg: int):
+    """Exponent vectors of n entries summing to deg, in descending
+    lexicographic order."""
+    if n == 1:
+        return [(deg,)]
+    out = []
+    for a0 in range(deg, -1, -1):
+        out.extend((a0,) + rest for rest in _compositions(n - 1, deg - a0))
+    return out
+
+
+@functools.lru_cache(maxsize=None)
+def _graded_lex(n: int, d: int):
+    out = []
+    for deg in range(d + 1):
+        out.extend(_compositions(n, deg))
+    return tuple(out)
+
+
 def graded_lex_monomials(n: int, d: int):
     """All exponent vectors of total degree <= d, degree ascending, then
     descending lexicographic order within a degree."""
-    out = []
-    for deg in range(d + 1):
-        level = [a for a in itertools.product(range(deg, -1, -1), repeat=n) if sum(a) == deg]
-        level.sort(reverse=True)
-        out.extend(level)
-    return out
+    return list(_graded_lex(n, d))
 
 
 def dense_system(n: int, degrees, rng: np.random.Generator, name="dense") -> PolySystem:
