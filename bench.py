@@ -47,17 +47,19 @@ METRIC = "paths/sec at endpoint residual<=1e-10, batched vs plain; p50/p99 solve
 COUNTER_PROFILE = {
     "workload": "cyclic10",
     "variant": 310,
+    "paths_per_wave": 64,
+    "waves_per_simd": 0,
     "sources_sha256": {
         "spec_track.hpp": "bb636574221bdf00805a21bbf4a783b4222c9c83e6ae6b0d1ef22211410816f1",
-        "lane_track.hpp": "d88e396d1469da3c3c901e2aaa6170c2cb2c893162686c6fafd3989921cf3ff4",
+        "lane_track.hpp": "c57862aba823120a48aa71a8ff47f4c77eda4a170bfb88596b82c0c4e7babd38",
         "hp_device.hpp": "f785014ca74114e45d5b32364f08af0b41660996c35cbf08085ef6fbc53b0a3e",
-        "hp_internal.hpp": "e8034b6ecb25a95b6f5974700c46bb6f261e0e981ce138c2fe7f3e48902fc286",
-        "hp_jit.cpp": "161eb0b1682f3e9c2e6298568b857aa590840c85fd0c98555fde715ce4f31b59",
+        "hp_internal.hpp": "9f69f93541a55dda1e17bd1303e1af9e3dddc1f89f2df00bc5aea0cd074c1fa9",
+        "hp_jit.cpp": "539cda6476e6db04fa0235bf354936b966f41021c8148fa51ee4e63b68b82d6d",
         "reg_lu.hpp": "488a287cfdfca4d8c1b616ad7aa2ae6bd41dfae4f8f485f55d55bd2819711eb2",
     },
-    "fetch_kib": 37142961.6875, "fetch_scale": 262144 / 131088.6875,
-    "write_kib": 1223088794.21875, "write_scale": 262144 / 262144,
-    "fma_f64": 232873573265, "mul_f64": 89306916092, "add_f64": 14735514329,
+    "fetch_kib": 74601094.875, "fetch_scale": 262144 / 131088.3125,
+    "write_kib": 1382728859.34375, "write_scale": 262144 / 262144,
+    "fma_f64": 232874150898, "mul_f64": 89306967666, "add_f64": 14735539864,
 }
 COUNTER_SOURCES = ["spec_track.hpp", "lane_track.hpp", "hp_device.hpp", "hp_internal.hpp",
                    "hp_jit.cpp", "reg_lu.hpp"]
@@ -86,11 +88,13 @@ def sources_digest():
 
 
 def counter_profile(workload, variant):
-    """The counter figures when the kernel sources, workload and variant are
-    the profiled ones, else None."""
+    """The counter figures when the kernel sources, workload and launch
+    (variant, paths per wavefront, wavefronts per SIMD) are the profiled
+    ones, else None."""
     C = COUNTER_PROFILE
-    if (workload != C["workload"] or variant != C["variant"] or not C["sources_sha256"]
-            or C["fetch_kib"] is None or sources_digest() != C["sources_sha256"]):
+    if (workload != C["workload"] or variant != (C["variant"], C["paths_per_wave"], C["waves_per_simd"])
+            or not C["sources_sha256"] or C["fetch_kib"] is None
+            or sources_digest() != C["sources_sha256"]):
         return None
     return C
 
@@ -212,6 +216,9 @@ def batch_run(ctx, n_systems=256):
     wl = W.dense_batch(n_systems, seed=3)
     gam = [complex(g) for g in wl.gammas]
     ctx.track_batch(wl.systems, gam, stats=False)  # warm-up (code load, tables)
+    t_untuned = ctx.last_timing()
+    # autotune the launch of this batch shape; the timed call launches with it
+    choice = ctx.tune_batch(wl.systems, gam)
     t0 = time.perf_counter()
     res = ctx.track_batch(wl.systems, gam, stats=True)
     dt = time.perf_counter() - t0
@@ -223,6 +230,10 @@ def batch_run(ctx, n_systems=256):
             "kernel_ms": tm["kernel_ms"], "endgame_ms": tm["endgame_ms"],
             "paths_per_s": wl.total_paths / ((tm["kernel_ms"] + tm["endgame_ms"]) * 1e-3),
             "end_to_end_ms": dt * 1e3, "kernel_variant": tm["variant"],
+            "launch": {"paths_per_wave": tm["paths_per_wave"], "lanes_per_path": tm["lanes_per_path"],
+                       "waves_per_simd": tm["waves_per_simd"]},
+            "tuning": {**choice, "untuned_variant": t_untuned["variant"],
+                       "untuned_kernel_ms": t_untuned["kernel_ms"]},
             "achieved_tflops": tfs, "frac_of_fp64_peak": tfs / FP64_PEAK_TFLOPS}
 
 
@@ -380,7 +391,9 @@ def main():
     P = system.bezout()
     ctx = hp.Context(0)
     t0 = time.perf_counter()
-    plan = ctx.plan(system, gamma)  # writes and compiles the specialised kernel
+    # writes and compiles the specialised kernel, then autotunes the launch
+    # (variant, paths per wavefront, wavefronts per SIMD) on a sample
+    plan = ctx.plan(system, gamma, tune=not args.variant)
     plan_ms = (time.perf_counter() - t0) * 1e3
     progress(f"plan for {args.workload} ready ({plan_ms:.0f} ms)")
     if args.variant:
@@ -399,7 +412,8 @@ def main():
     flop = flops.run_flops(system, stats)
     kmean = float(np.mean(kms))
     achieved = flop / (kmean * 1e-3) / 1e12
-    prof = counter_profile(args.workload, timing["variant"])
+    prof = counter_profile(args.workload, (timing["variant"], timing["paths_per_wave"],
+                                           timing["waves_per_simd"]))
     traffic = counter_tf = None
     if prof:
         traffic = (prof["fetch_kib"] * 1024 * prof["fetch_scale"]
@@ -424,7 +438,10 @@ def main():
                    "mode": "batched (persistent, device refill queue), end game, device dedup",
                    "kernel_variant": {"max_n": timing["max_n"],
                                       "paths_per_wave": timing["paths_per_wave"],
+                                      "lanes_per_path": timing["lanes_per_path"],
+                                      "waves_per_simd": timing["waves_per_simd"],
                                       "code": timing["variant"], "groups": timing["groups"]},
+                   "tuning": plan.tuning(),
                    "plan_create_ms": plan_ms},
         "converged": int(conv.sum()),
         "not_converged": int((~conv).sum()),
