@@ -283,6 +283,11 @@ def serving_run(ctx, n_requests, budget_bytes, calib=200, load=0.8):
         lat, conv = [], 0
         t_last = time.perf_counter()
         for i, q in enumerate(ids):
+            while not srv.poll(q):  # poll, so that progress lines keep coming
+                time.sleep(0.002)
+                if time.perf_counter() - t_last > 10.0:
+                    t_last = time.perf_counter()
+                    progress(f"serving: {i}/{len(ids)} requests done")
             _, st, _, ms = srv.wait(q)
             lat.append(ms)
             conv += int((st == 0).sum())

@@ -416,19 +416,21 @@ int hp_cascade(hp_context *ctx, const hp_system *e, int32_t k, const hp_c64 *gam
  * their slot regions fit (at most 262,144 slots each; a request with more
  * paths, or one larger than the free room, which gets at least 4096 slots,
  * reuses the slots of its finished paths).
- * The work goes in epochs.  Each epoch packs a queue of paths of every
- * admitted request (same tolerances) into one multi-system persistent
- * launch per kernel family (the kernel specialised to a support, shared by
- * the requests of that support; the dense kernels; the group kernels), so
- * that requests that arrive while others run share the following launches
- * and each request runs on the kernel it would get alone.  On the
- * specialised and dense kernels each wavefront stops after a budget of
- * steps per epoch: its paths in flight are suspended in their slots (the
+ * The work goes in epochs.  Each epoch packs a queue of paths of the
+ * admitted requests (same tolerances), in admission order up to 524,288
+ * paths, into one multi-system persistent launch per kernel family (the
+ * kernel specialised to a support, shared by the requests of that support;
+ * the dense kernels; the group kernels), so that requests that arrive while
+ * others run share the following launches, the oldest requests finish
+ * first under load, and each request runs on the kernel it would get alone.
+ * On the specialised and dense kernels each wavefront stops after a budget
+ * of steps per epoch: its paths in flight are suspended in their slots (the
  * accepted point, t, the step size and the counters) and resume from there
  * in a later epoch, bit for bit as if never stopped.  The budget of each
  * family adapts so that its epoch's kernel time is about the slice time
  * (hp_server_set_slice), which bounds how long a new request waits before
- * its paths start.  The group kernels run their queue to the end.
+ * its paths start when the epochs have room for them.  The group kernels
+ * run their queue to the end.
  * HP_E_BUDGET if the budget holds fewer than 4096 slots. */
 int hp_server_create(hp_context *ctx, size_t hbm_budget_bytes, hp_server **out);
 /* Time slicing of the specialised and dense kernel families: slice_ms is the

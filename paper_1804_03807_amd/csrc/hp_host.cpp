@@ -2171,16 +2171,17 @@ int hp_cascade(hp_context *ctx, const hp_system *e, int32_t k, const hp_c64 *gam
 // the budget.  Requests are admitted in arrival order while their regions
 // (slots of the arena, at most kEpochPaths per request) fit; a request with
 // more paths than its region reuses the slots of finished paths.
-// The work goes in epochs.  Every epoch packs, for each admitted request, a
-// queue of its paths (those suspended in the previous epoch first, then
-// paths not started yet, each holding a slot) into one multi-system
-// persistent launch per kernel family.  On the one-path-per-lane families
-// every wavefront stops after a budget of steps: its paths in flight are
-// suspended to their slots (accepted point, t, h, counters) and resume from
-// there in the next epoch, so an epoch's kernel time is bounded and a new
-// request waits at most about one slice before its paths start.  The
-// budget of each family is adapted so that its epochs take about the slice
-// time.  After the launches a harvest kernel compacts the finished paths of
+// The work goes in epochs.  Every epoch packs, for the admitted requests in
+// admission order until kEpochEntries entries are taken, a queue of each
+// one's paths (those suspended in the previous epoch first, then paths not
+// started yet, each holding a slot) into one multi-system persistent launch
+// per kernel family.  On the one-path-per-lane families every wavefront
+// stops after a budget of steps: its paths in flight are suspended to their
+// slots (accepted point, t, h, counters) and resume from there in a later
+// epoch, so an epoch's kernel time is bounded and a new request whose
+// entries fit the next epoch starts within about one slice, while under
+// load the oldest requests finish first.  The budget of each family is
+// adapted so that its epochs take about the slice time.  After the launches a harvest kernel compacts the finished paths of
 // the queues, which are copied to the requests' host results; their slots
 // go back to the requests' free lists.
 // Kernels specialised to a first-seen support are compiled on a thread of
@@ -2189,7 +2190,8 @@ int hp_cascade(hp_context *ctx, const hp_system *e, int32_t k, const hp_c64 *gam
 
 namespace {
 
-constexpr int64_t kEpochPaths = 1 << 18;  // queue entries per epoch over all requests
+constexpr int64_t kEpochPaths = 1 << 18;    // slots of a request's region at most
+constexpr int64_t kEpochEntries = 1 << 19;  // queue entries of an epoch over all requests
 constexpr int64_t kMinChunk = 4096;
 constexpr int32_t kInitialBudget = 16;  // steps per wavefront in a family's first slice
 constexpr int32_t kMinBudget = 4, kMaxBudget = 1 << 20;
@@ -2356,28 +2358,25 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
   // one launch has one tolerance set: take the requests that share the
   // oldest active request's tolerances; the others wait for a later epoch
   const hp_tolerances tol = batch[0]->tol;
-  size_t same = 0;
-  for (auto &R : batch) same += std::memcmp(&R->tol, &tol, sizeof(tol)) == 0;
-  const int64_t share = std::max<int64_t>(kMinChunk, kEpochPaths / (int64_t)same);
 
-  // ---- queues: suspended and waiting paths first, then new paths ----
-  int64_t cap = 0;  // entries this epoch at most
-  for (auto &R : batch)
-    if (std::memcmp(&R->tol, &tol, sizeof(tol)) == 0) cap += share;
-  const size_t qstride = (size_t)cap;
+  // ---- queues, filled in admission order up to kEpochEntries entries (so
+  // the oldest requests finish first and an epoch's host work is bounded):
+  // a request's suspended and waiting paths first, then new paths ----
+  const size_t qstride = (size_t)kEpochEntries;
   int rc;
   if ((rc = S->q_host.alloc(qstride * (4 * sizeof(int64_t) + sizeof(int32_t))))) return rc;
   int64_t *h_ids = (int64_t *)S->q_host.p, *h_slots = h_ids + qstride, *h_path = h_slots + qstride,
           *h_xoff = h_path + qstride;
   int32_t *h_n = (int32_t *)(h_xoff + qstride);
   std::vector<int32_t> h_owner;
-  h_owner.reserve((size_t)cap);
+  h_owner.reserve((size_t)kEpochEntries);
   int64_t E = 0;
   for (size_t i = 0; i < batch.size(); ++i) {
     Request &R = *batch[i];
     R.qoff = E;
     R.qlen = R.qtaken = 0;
-    if (std::memcmp(&R.tol, &tol, sizeof(tol)) != 0) continue;
+    if (std::memcmp(&R.tol, &tol, sizeof(tol)) != 0 || E >= kEpochEntries) continue;
+    const int64_t share = kEpochEntries - E;  // entries left for this request and the next
     const int n = R.info.n;
     auto push = [&](int64_t pid, int64_t slot) {
       h_ids[E] = pid;
@@ -2407,10 +2406,14 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
   }
   if (E == 0) return HP_OK;
   if (E > INT32_MAX) return fail(HP_E_INVALID_ARG, "epoch queue too long");
-  // device copy of the queue block (same layout, stride qstride)
+  // device copy of the queue block (same layout, stride qstride; the first
+  // E entries of each array)
   if ((rc = S->q_dev.alloc(S->q_host.bytes))) return rc;
-  HIP_TRY(hipMemcpyAsync(S->q_dev.p, S->q_host.p, qstride * (4 * sizeof(int64_t) + sizeof(int32_t)),
-                         hipMemcpyHostToDevice, S->stream));
+  for (int a = 0; a < 5; ++a) {
+    const size_t off = (size_t)a * qstride * sizeof(int64_t), w = a < 4 ? sizeof(int64_t) : sizeof(int32_t);
+    HIP_TRY(hipMemcpyAsync((char *)S->q_dev.p + off, (const char *)S->q_host.p + off, (size_t)E * w,
+                           hipMemcpyHostToDevice, S->stream));
+  }
   HIP_TRY(hipStreamSynchronize(S->stream));
   int64_t *d_ids = S->q_dev.as<int64_t>(), *d_slots = d_ids + qstride, *d_path = d_slots + qstride,
           *d_xoff = d_path + qstride;
