@@ -13,8 +13,9 @@ re-tracking of duplicate pairs, all on the device.
 Also measured (sub-keys, outside the timed region): cyclic-8 (40,320 paths)
 batched vs plain, the dense n = 5 system (32 paths) batched vs plain, 256 dense
 systems in one launch, coefficient-parameter continuation between two
-cyclic-8 systems (2,560 paths), the double-double tracker on cyclic-8, and
-the serving loop on 1,000 requests.
+cyclic-8 systems (2,560 paths) and between two cyclic-10 systems (the
+headline's finite roots), the double-double tracker on cyclic-8, and the
+serving loop on 1,000 requests.
 
 Prints one JSON line.
 """
@@ -163,10 +164,47 @@ def batched_vs_plain(ctx, name, steps=3):
             "achieved_tflops": achieved, "frac_of_fp64_peak": achieved / FP64_PEAK_TFLOPS}
 
 
-def continuation_run(ctx):
-    """Coefficient-parameter continuation on the cyclic-8 supports: the 2,560
-    finite roots of one random-coefficient system (the cyclic-8 workload,
-    solved first) moved to those of another system on the same supports."""
+def continuation_run(ctx, name, source, start, target):
+    """Coefficient-parameter continuation: the finite roots `start` of the
+    system `source` moved to those of `target` (same supports), on the
+    specialised kernel's coefficient-parameter form (a plan with a start
+    system, hp_plan_create_general) and on the group kernels (hp_track_paths
+    with g and start, the one-shot call), both timed after a warm-up."""
+    import torch
+    import paper_1804_03807_amd as hp
+    gam = complex(np.exp(1.3j))
+    P = len(start)
+    t0 = time.perf_counter()
+    plan = ctx.plan(target, gam, g=source, start=start)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    e, st, sts = plan.outputs(P)
+    plan.track_device(e, st, sts)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.track_device(e, st, sts)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tm = ctx.last_timing()
+    conv = int((st == 0).sum().item())
+    ctx.track_paths(target, gam, start=start, g=source)  # warm-up
+    t0 = time.perf_counter()
+    _, sg, _ = ctx.track_paths(target, gam, start=start, g=source)
+    dtg = time.perf_counter() - t0
+    tg = ctx.last_timing()
+    plan.close()
+    return {"workload": name, "paths": int(P), "converged": conv,
+            "specialised": {"kernel_variant": tm["variant"], "kernel_ms": tm["kernel_ms"],
+                            "endgame_ms": tm["endgame_ms"], "device_call_ms": dt * 1e3,
+                            "paths_per_s": P / dt, "plan_create_ms": plan_ms},
+            "group": {"kernel_variant": tg["variant"], "kernel_ms": tg["kernel_ms"],
+                      "endgame_ms": tg["endgame_ms"], "end_to_end_ms": dtg * 1e3,
+                      "paths_per_s": P / dtg, "converged": int((sg == 0).sum())},
+            "specialised_over_group_kernel": tg["kernel_ms"] / tm["kernel_ms"]}
+
+
+def continuation_cyclic8(ctx):
+    """The 2,560 finite roots of the cyclic-8 workload's system moved to
+    another random system on the cyclic-8 supports."""
     import torch
     import paper_1804_03807_amd as hp
     import workloads as W
@@ -178,16 +216,7 @@ def continuation_run(ctx):
     torch.cuda.synchronize()
     start = hp.Plan.endpoints_to_numpy(e)[st.cpu().numpy() == 0]
     plan.close()
-    gam = complex(np.exp(1.3j))
-    ctx.track_paths(sb, gam, start=start, g=sa)  # warm-up
-    t0 = time.perf_counter()
-    ee, ss, _ = ctx.track_paths(sb, gam, start=start, g=sa)
-    dt = time.perf_counter() - t0
-    tm = ctx.last_timing()
-    return {"paths": int(len(start)), "converged": int((ss == 0).sum()),
-            "kernel_ms": tm["kernel_ms"], "endgame_ms": tm["endgame_ms"],
-            "end_to_end_ms": dt * 1e3, "paths_per_s": len(start) / dt,
-            "kernel_variant": tm["variant"]}
+    return continuation_run(ctx, "cyclic8 supports, seed 2 -> seed 12", sa, start, sb)
 
 
 def dd_run(ctx, double_ms):
@@ -478,6 +507,8 @@ def main():
         out["cpu_baseline"] = rec
         if not par.ok:
             out["value_invalid"] = "GPU endpoints differ from the oracle on the sampled paths"
+    # the headline's finite roots: start points of the cyclic-10 continuation
+    start10 = (hp.Plan.endpoints_to_numpy(e)[conv] if args.workload == "cyclic10" else None)
     del e, st, sts
     plan.close()
     torch.cuda.empty_cache()
@@ -491,8 +522,14 @@ def main():
         progress("dense n = 5 done")
         out["batch256"] = batch_run(ctx)
         progress("256-system batch done")
-        out["continuation_cyclic8"] = continuation_run(ctx)
-        progress("continuation done")
+        out["continuation_cyclic8"] = continuation_cyclic8(ctx)
+        progress("continuation cyclic-8 done")
+        if start10 is not None:
+            import workloads as W
+            out["continuation_cyclic10"] = continuation_run(
+                ctx, "cyclic10 supports, seed 5 -> seed 15 (the headline's converged endpoints)",
+                system, start10, W.cyclic_workload(10, 15).systems[0])
+            progress("continuation cyclic-10 done")
 
     if args.serving_requests > 0:
         out["serving"] = serving_run(ctx, args.serving_requests,

@@ -219,6 +219,21 @@ void hp_default_tolerances_dd(hp_tolerances *tol);
  * compilation are HP_E_DEVICE with the compiler log in hp_last_error. */
 int hp_plan_create(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
                    int32_t tune, hp_plan **out);
+/* A plan for gamma (1 - t) g + t f with explicit start points (host array
+ * [n_start][n], copied; path id k starts at row k; g as for hp_track_paths,
+ * NULL for the total-degree start system).  When g has f's support term by
+ * term (the same equations with the same monomials in the same order, other
+ * coefficients: the coefficient-parameter continuation of Section 2.1, the
+ * "contin" stage of Section 5.4 Table 5) and n <= 10, the default variant is
+ * the specialised kernel in its coefficient-parameter form: one sweep over
+ * the monomials with the blended coefficients gamma (1 - t) cg + t cf gives
+ * J and H, and the coefficients gamma cg - cf give -H_t.  Otherwise, and for
+ * every other g, the group kernels.  tune != 0 runs the autotuner as for
+ * hp_plan_create.  HP_E_INVALID_ARG for a missing start array or a g of
+ * another n. */
+int hp_plan_create_general(hp_context *ctx, const hp_system *f, const hp_system *g,
+                           const hp_c64 *start, int64_t n_start, hp_c64 gamma,
+                           const hp_tolerances *tol, int32_t tune, hp_plan **out);
 void hp_plan_destroy(hp_plan *plan);
 /* Forces the kernel variant.  Three kernel families:
  *   n_max = 4, 8, 10, 12   group kernels: n lanes of a wavefront per path
@@ -231,7 +246,8 @@ void hp_plan_destroy(hp_plan *plan);
  *                          LDS, for systems whose power table is large);
  *   300 + n (n = 1..10)    the kernel specialised to the plan's system (one
  *                          path per lane, [J | rhs] in registers, compiled at
- *                          run time; total-degree start system only);
+ *                          run time; total-degree start system, or a start
+ *                          system on f's support: hp_plan_create_general);
  *   400, 411, 412          dense kernels for equations of total degree <= 3
  *                          (400: any n <= 10; 411, 412: n = 11, 12), one path
  *                          per lane, batched mode only (a plain call of a
@@ -271,6 +287,10 @@ int hp_plan_tuning(const hp_plan *plan, hp_tune_choice *out);
  * than 1024 factors in all), HP_E_DEVICE when compilation fails (compiler log
  * in hp_last_error), HP_E_INVALID_ARG for a malformed system. */
 int hp_spec_compile(const hp_system *f, int64_t *code_bytes);
+/* One form of that kernel: 0 the plans', 1 the server's, 2 the
+ * coefficient-parameter form of hp_plan_create_general (which depends on
+ * f's support only).  Same errors; HP_E_INVALID_ARG for another form. */
+int hp_spec_compile_form(const hp_system *f, int32_t form, int64_t *code_bytes);
 
 /* Device-memory call: tracks the paths whose ids are ids[0..n_paths-1]
  * (device int64 array; NULL means ids 0..n_paths-1).  Outputs are device

@@ -80,11 +80,17 @@ def path_count(system) -> int:
     return int(load().hp_path_count(ctypes.byref(_SysView(system).c)))
 
 
-def spec_compile(system) -> int:
+def spec_compile(system, form=None) -> int:
     """Writes and compiles (hiprtc, gfx950) the kernel specialised to the
-    system's support without a device; returns the code object's size."""
+    system's support without a device; returns the code object's size.
+    form None: the plans' and the server's forms; 0, 1, 2: the plans', the
+    server's or the coefficient-parameter form alone."""
     out = ctypes.c_int64(0)
-    check(load().hp_spec_compile(ctypes.byref(_SysView(system).c), ctypes.byref(out)))
+    if form is None:
+        check(load().hp_spec_compile(ctypes.byref(_SysView(system).c), ctypes.byref(out)))
+    else:
+        check(load().hp_spec_compile_form(ctypes.byref(_SysView(system).c), int(form),
+                                          ctypes.byref(out)))
     return int(out.value)
 
 
@@ -286,8 +292,8 @@ class Context:
         recs = [{f: getattr(s, f) for f, _ in HpCascadeStage._fields_ if f != "pad"} for s in stages]
         return recs, wit[:c], dims[:c]
 
-    def plan(self, system, gamma, tol=None, tune=False):
-        return Plan(self, system, gamma, tol, tune)
+    def plan(self, system, gamma, tol=None, tune=False, g=None, start=None):
+        return Plan(self, system, gamma, tol, tune, g=g, start=start)
 
     def find_duplicates_device(self, endpoints, status, rel=1e-6, max_pairs=1 << 16, stream=None):
         """Duplicate scan of device tensors (endpoints float64 [P, n, 2] or
@@ -318,17 +324,30 @@ class Context:
 class Plan:
     """A system resident on the device; tracks paths into torch tensors."""
 
-    def __init__(self, ctx: Context, system, gamma, tol=None, tune=False):
+    def __init__(self, ctx: Context, system, gamma, tol=None, tune=False, g=None, start=None):
+        """start (complex [P, n]): a general plan (hp_plan_create_general) whose
+        path k starts at start[k], from the start system g (None: total degree)."""
         self.ctx = ctx
         self._L = ctx._L
         self._view = _SysView(system)
         self.n = self._view.n
-        self.paths = path_count(system)
         self.tol = tol or default_tolerances()
         h = ctypes.c_void_p()
         self.handle = None
-        check(self._L.hp_plan_create(ctx.handle, ctypes.byref(self._view.c), _c64(gamma),
-                                     ctypes.byref(self.tol), int(bool(tune)), ctypes.byref(h)))
+        if start is None:
+            if g is not None:
+                raise ValueError("a plan with a start system g needs its start points")
+            self.paths = path_count(system)
+            check(self._L.hp_plan_create(ctx.handle, ctypes.byref(self._view.c), _c64(gamma),
+                                         ctypes.byref(self.tol), int(bool(tune)), ctypes.byref(h)))
+        else:
+            st = np.ascontiguousarray(np.asarray(start, dtype=np.complex128).reshape(-1, self.n))
+            self.paths = len(st)
+            self._gview = _SysView(g) if g is not None else None
+            check(self._L.hp_plan_create_general(
+                ctx.handle, ctypes.byref(self._view.c),
+                ctypes.byref(self._gview.c) if self._gview is not None else None, _ptr(st), len(st),
+                _c64(gamma), ctypes.byref(self.tol), int(bool(tune)), ctypes.byref(h)))
         self.handle = h
         ctx._children.add(self)
         _LIVE.add(self)

@@ -28,7 +28,7 @@ EXPORTED = [
     "hp_find_duplicates_device", "hp_plan_solve_device", "hp_find_duplicates_device_static",
     "hp_membership_test", "hp_cascade", "hp_track_paths_dd", "hp_default_tolerances_dd",
     "hp_server_set_slice", "hp_server_info_get", "hp_plan_set_launch", "hp_plan_tuning",
-    "hp_tune_batch",
+    "hp_tune_batch", "hp_plan_create_general", "hp_spec_compile_form",
 ]
 
 
@@ -153,6 +153,9 @@ def load():
             "hp_server_destroy": (None, [vp]),
             "hp_server_set_slice": (ctypes.c_int, [vp, ctypes.c_double, i32]),
             "hp_plan_set_launch": (ctypes.c_int, [vp, i32, i32]),
+            "hp_spec_compile_form": (ctypes.c_int, [P(HpSystem), i32, P(i64)]),
+            "hp_plan_create_general": (ctypes.c_int, [vp, P(HpSystem), P(HpSystem), vp, i64, c64,
+                                                      P(HpTolerances), i32, P(vp)]),
             "hp_plan_tuning": (ctypes.c_int, [vp, P(HpTuneChoice)]),
             "hp_tune_batch": (ctypes.c_int, [vp, vp, i32, vp, P(HpTolerances), P(HpTuneChoice)]),
             "hp_server_info_get": (ctypes.c_int, [vp, P(HpServerInfo)]),

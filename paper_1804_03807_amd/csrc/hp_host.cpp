@@ -474,6 +474,8 @@ struct Kv {
   // dense kernel (0: 64), resident wavefronts per SIMD the launch is capped
   // at (0: as many as fit)
   int lp = 0, wps = 0;
+  // spec in the coefficient-parameter form: its (cf, cg, gamma cg - cf) table
+  const double2 *pcoef = nullptr;
 };
 
 constexpr int kDenseCode = 400;
@@ -701,6 +703,7 @@ struct hp_plan {
   hp_tune_choice tune{};  // the autotuner's record (zero: not tuned)
   bool spec_default = false;  // default variant: the specialised kernel where it applies
   DevBuf start_dev;  // explicit start points [n_start][n] (general plans)
+  DevBuf pcoef;      // (cf, cg, gamma cg - cf) per term: coefficient-parameter plans
   // plain-mode state
   DevBuf px0, pt, ph, piv, pactive;
   DevBuf ids_scratch;
@@ -921,6 +924,7 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
   a.dcoef = dev.dcoef.as<double2>();
   a.step_budget = sliced ? step_budget : 0;
   a.lane_paths = lp;
+  a.pcoef = k.pcoef;
   HIP_TRY(hipMemsetAsync(dev.qhead.p, 0, P.sys.size() * sizeof(unsigned long long), s));
   HIP_TRY(hipEventRecord(e0, s));
   if (k.spec) {
@@ -946,23 +950,58 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
   return HP_OK;
 }
 
+// A general plan whose start system g has f's support term by term (same
+// equations, same monomials in the same order) and explicit start points:
+// a coefficient-parameter continuation, which the specialised kernel's
+// coefficient-parameter form runs.
+bool plan_param(const hp_plan *plan) {
+  const Packed &P = plan->P;
+  if (!P.general || P.sys.size() != 1) return false;
+  const DevSys &d = P.sys[0];
+  if (!d.start || d.g_n_terms != d.n_terms || d.n_terms == 0) return false;
+  for (int t = 0; t < d.n_terms; ++t)
+    if (std::memcmp(P.terms[d.term_base + t].w, P.terms[d.g_term_base + t].w,
+                    sizeof(P.terms[0].w)) != 0)
+      return false;
+  return true;
+}
+
 // The plan's system can have a kernel specialised to it.
 bool plan_spec_eligible(const hp_plan *plan) {
   const Packed &P = plan->P;
-  return !P.general && P.sys.size() == 1 &&
+  return (!P.general || plan_param(plan)) && P.sys.size() == 1 &&
          hp::spec_eligible(plan->info.n, P.terms.data() + P.sys[0].term_base, P.sys[0].n_terms);
 }
 
 // Generates, compiles (hiprtc; cached per process) and loads the kernel
-// specialised to the plan's system.
+// specialised to the plan's system; for a coefficient-parameter plan the
+// coefficient-parameter form, with its coefficient table uploaded.
 int spec_prepare(hp_plan *plan, Kv &k) {
   const Packed &P = plan->P;
   const DevSys &d = P.sys[0];
-  const std::string src = hp::spec_source(plan->info.n, d.deg, P.terms.data() + d.term_base, d.n_terms);
+  const bool param = plan_param(plan);
+  const std::string src =
+      hp::spec_source(plan->info.n, d.deg, P.terms.data() + d.term_base, d.n_terms, false, param);
   std::string log;
   const int rc = hp::spec_get(plan->ctx->device, src, &k.sm, log);
   if (rc) return fail(HP_E_DEVICE, "specialised kernel: " + std::string(hipGetErrorString((hipError_t)rc)) +
                                        (log.empty() ? "" : "\n" + log));
+  if (param) {
+    // per term in packed order: f's coefficient, g's, and gamma g - f (the
+    // coefficient of -H_t)
+    std::vector<double2> tab((size_t)3 * d.n_terms);
+    for (int t = 0; t < d.n_terms; ++t) {
+      const DevTerm &F = P.terms[d.term_base + t], &G = P.terms[d.g_term_base + t];
+      tab[3 * t] = make_double2(F.cre, F.cim);
+      tab[3 * t + 1] = make_double2(G.cre, G.cim);
+      tab[3 * t + 2] = make_double2(d.gre * G.cre - d.gim * G.cim - F.cre,
+                                    d.gre * G.cim + d.gim * G.cre - F.cim);
+    }
+    int r = plan->pcoef.alloc(tab.size() * sizeof(double2));
+    if (r) return r;
+    HIP_TRY(hipMemcpy(plan->pcoef.p, tab.data(), tab.size() * sizeof(double2), hipMemcpyHostToDevice));
+    k.pcoef = plan->pcoef.as<double2>();
+  }
   return HP_OK;
 }
 
@@ -978,8 +1017,9 @@ int plan_variant(hp_plan *plan, int code) {
       ((k.lanes || k.spec || (k.dense && k.code != kDenseCode)) && k.nmax != plan->info.n))
     return fail(HP_E_INVALID_ARG, "no compiled kernel variant " + std::to_string(code) +
                                       " for n = " + std::to_string(plan->info.n));
-  if ((k.lanes || k.spec || k.dense) && plan->P.general)
-    return fail(HP_E_INVALID_ARG, "lane kernels track the total-degree start system only");
+  if ((k.lanes || k.dense || (k.spec && !plan_param(plan))) && plan->P.general)
+    return fail(HP_E_INVALID_ARG, "lane kernels track the total-degree start system only "
+                                  "(the specialised kernel also a start system on f's support)");
   if (k.dense && !dense_fits(k, plan->P))
     return fail(HP_E_INVALID_ARG, "the dense kernels take n <= " +
                                       std::to_string(hp::kDenseWideMaxN) +
@@ -1038,6 +1078,7 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
   a.ps.P = n_paths;
   a.ps.active = plan->pactive.as<unsigned int>();
   a.stage = stage;
+  a.pcoef = k.pcoef;
   HIP_TRY(hipEventRecord(ctx->ev0, s));
   HIP_TRY((hipError_t)hp_launch_plain_init(a, s));
   const int64_t per_wave = (k.lanes || k.spec) ? k.pw : hp::kLanes / n;
@@ -1267,6 +1308,13 @@ int plan_create(hp_context *ctx, const hp_system *f, const hp_system *g, const h
 
 extern "C" {
 
+int hp_plan_create_general(hp_context *ctx, const hp_system *f, const hp_system *g,
+                           const hp_c64 *start, int64_t n_start, hp_c64 gamma,
+                           const hp_tolerances *tol, int32_t tune, hp_plan **out) {
+  if (!start) return fail(HP_E_INVALID_ARG, "a general plan needs its start points");
+  return plan_create(ctx, f, g, start, n_start, gamma, tol, tune, true, out);
+}
+
 int hp_plan_create(hp_context *ctx, const hp_system *f, hp_c64 gamma, const hp_tolerances *tol,
                    int32_t tune, hp_plan **out) {
   return plan_create(ctx, f, nullptr, nullptr, 0, gamma, tol, tune, true, out);
@@ -1281,9 +1329,10 @@ void hp_plan_destroy(hp_plan *plan) {
   context_orphan(ctx);
 }
 
-int hp_spec_compile(const hp_system *f, int64_t *code_bytes) {
+int hp_spec_compile_form(const hp_system *f, int32_t form, int64_t *code_bytes) {
   if (!code_bytes) return fail(HP_E_INVALID_ARG, "NULL argument");
   *code_bytes = 0;
+  if (form < 0 || form > 2) return fail(HP_E_INVALID_ARG, "form must be 0, 1 or 2");
   SysInfo info;
   int rc = check_system(f, info);
   if (rc) return rc;
@@ -1292,14 +1341,21 @@ int hp_spec_compile(const hp_system *f, int64_t *code_bytes) {
   const DevSys &d = P.sys[0];
   if (!hp::spec_eligible(f->n, P.terms.data(), d.n_terms))
     return fail(HP_E_UNSUPPORTED_N, "system too large for a specialised kernel");
-  std::vector<char> code, serving;
+  std::vector<char> code;
   std::string log;
-  rc = hp::spec_compile(hp::spec_source(f->n, d.deg, P.terms.data(), d.n_terms), code, log);
-  if (rc) return fail(HP_E_DEVICE, "specialised kernel: " + log);
-  rc = hp::spec_compile(hp::spec_source(f->n, d.deg, P.terms.data(), d.n_terms, true), serving, log);
-  if (rc) return fail(HP_E_DEVICE, "specialised kernel (serving form): " + log);
+  rc = hp::spec_compile(hp::spec_source(f->n, d.deg, P.terms.data(), d.n_terms, form == 1, form == 2),
+                        code, log);
+  if (rc) return fail(HP_E_DEVICE, "specialised kernel (form " + std::to_string(form) + "): " + log);
   *code_bytes = (int64_t)code.size();
   return HP_OK;
+}
+
+int hp_spec_compile(const hp_system *f, int64_t *code_bytes) {
+  if (!code_bytes) return fail(HP_E_INVALID_ARG, "NULL argument");
+  int64_t serving = 0;
+  int rc = hp_spec_compile_form(f, 0, code_bytes);
+  if (rc == HP_OK) rc = hp_spec_compile_form(f, 1, &serving);
+  return rc;
 }
 
 int hp_plan_set_variant(hp_plan *plan, int32_t variant) {

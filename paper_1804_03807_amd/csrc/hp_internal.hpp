@@ -119,6 +119,8 @@ struct KArgs {
                          // suspended to their slots
   int32_t lane_paths;    // specialised and dense kernels: lanes 0 .. lane_paths - 1 of a
                          // wavefront hold paths (0: all 64), a tuning choice
+  const double2 *pcoef;  // specialised kernels in the coefficient-parameter form:
+                         // (cf, cg, gamma cg - cf) per term, in packed term order
 };
 
 // Lanes of a wavefront that take paths from the refill queue in the

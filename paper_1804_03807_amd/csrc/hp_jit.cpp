@@ -73,6 +73,104 @@ bool spec_eligible(int n, const DevTerm *terms, int n_terms) {
   return factors <= kSpecMaxFactors;
 }
 
+// Coefficient-parameter form (the start system g has f's support, term by
+// term): with s = gamma (1 - t), H = sum_k (s cg_k + t cf_k) x^a_k, so one
+// sweep over the monomials with the blended coefficient b_k = s cg_k + t cf_k
+// gives J = sum_k b_k grad x^a_k and the value H; the right-hand side
+// -H_t = sum_k (gamma cg_k - cf_k) x^a_k takes the third coefficient of the
+// term instead (and at t = 1, b_k = cf_k gives f).  Per term, prefix
+// products of the bare monomial give its value; a backward sweep of suffix
+// products that starts from b_k gives the partial derivatives.  The
+// coefficient table holds (cf_k, cg_k, gamma cg_k - cf_k) per term.
+std::string param_source(int n, const DevTerm *terms, int n_terms) {
+  std::vector<GenTerm> T;
+  T.reserve(n_terms);
+  std::vector<int> emax(n, 1);
+  for (int t = 0; t < n_terms; ++t) {
+    T.push_back(unpack(terms[t]));
+    for (const Factor &f : T.back().f) emax[f.v] = std::max(emax[f.v], f.e);
+  }
+  std::ostringstream o;
+  o << "#include \"spec_track.hpp\"\n\nnamespace hp {\nnamespace gen {\n\nstruct Sys {\n"
+    << "  static constexpr int N = " << n << ";\n"
+    << "  static constexpr bool kParam = true;\n"
+    << "  __device__ __forceinline__ static void eval(cptr<double2> cf, const cd (&x)[N], double te,\n"
+    << "                                              cd s, cd gamma, int emode, cd (&J)[N][N],\n"
+    << "                                              lds_char *spare) {\n"
+    << "    const bool rhs_t = (emode == EV_NEG_HT);\n";
+  for (int v = 0; v < n; ++v) {
+    o << "    const cd " << pw(v, 1) << " = x[" << v << "];\n";
+    for (int e = 2; e <= emax[v]; ++e)
+      o << "    const cd " << pw(v, e) << " = cmul(" << pw(v, e - 1) << ", x[" << v << "]);\n";
+  }
+  o << "    cd F[N];\n";
+  std::vector<char> jt((size_t)n * n, 0), ft(n, 0);
+  std::vector<int> last(n, -1);
+  for (int t = 0; t < n_terms; ++t) last[T[t].eq] = t;
+  auto slot = [](int i) { return "spare + " + std::to_string(i * 1024); };
+  auto add_f = [&](int eq, const std::string &val) {
+    const std::string fe = "F[" + std::to_string(eq) + "]";
+    if (ft[eq]) o << "      " << fe << " = cadd(" << fe << ", " << val << ");\n";
+    else o << "      " << fe << " = " << val << ";\n";
+    ft[eq] = 1;
+  };
+  for (int t = 0; t < n_terms; ++t) {
+    const GenTerm &g = T[t];
+    const int K = (int)g.f.size();
+    o << "    {\n      const double2 f_ = cf[" << 3 * t << "], g_ = cf[" << 3 * t + 1 << "], d_ = cf["
+      << 3 * t + 2 << "];\n"
+      << "      const cd b = cadd(cmul(s, cd{g_.x, g_.y}), cscale(cd{f_.x, f_.y}, te));\n"
+      << "      const cd r = csel(rhs_t, cd{d_.x, d_.y}, b);\n";
+    if (K == 0) {
+      add_f(g.eq, "r");
+      o << "    }\n";
+      if (last[g.eq] == t) o << "    stl(" << slot(g.eq) << ", F[" << g.eq << "]);\n";
+      continue;
+    }
+    // prefix products of the bare monomial: m0 = x^e0, m_j = m_{j-1} x^ej
+    for (int m = 1; m < K; ++m)
+      o << "      const cd m" << m << " = cmul(" << (m == 1 ? pw(g.f[0].v, g.f[0].e) : "m" + std::to_string(m - 1))
+        << ", " << pw(g.f[m].v, g.f[m].e) << ");\n";
+    const std::string mono = K == 1 ? pw(g.f[0].v, g.f[0].e) : "m" + std::to_string(K - 1);
+    add_f(g.eq, "cmul(r, " + mono + ")");
+    // backward sweep: S = b times the product of the factors after m
+    for (int m = K - 1; m >= 0; --m) {
+      const int v = g.f[m].v, e = g.f[m].e;
+      const std::string left = (m == 0) ? "" : (m == 1 ? pw(g.f[0].v, g.f[0].e) : "m" + std::to_string(m - 1));
+      const std::string suf = (m == K - 1) ? "b" : "S";
+      const std::string je = jn(g.eq, v);
+      const bool first = !jt[(size_t)g.eq * n + v];
+      jt[(size_t)g.eq * n + v] = 1;
+      std::string d = left.empty() ? suf : "cmul(" + left + ", " + suf + ")";
+      if (e > 1) d = "cmul(" + d + ", cscale(" + pw(v, e - 1) + ", " + std::to_string(e) + ".0))";
+      if (first) o << "      " << je << " = " << d << ";\n";
+      else if (e == 1 && !left.empty()) o << "      " << je << " = cfma(" << je << ", " << left << ", " << suf << ");\n";
+      else o << "      " << je << " = cadd(" << je << ", " << d << ");\n";
+      if (m > 0) {
+        if (m == K - 1) o << "      cd S = cmul(" << pw(v, e) << ", b);\n";
+        else o << "      S = cmul(S, " << pw(v, e) << ");\n";
+      }
+    }
+    o << "    }\n";
+    if (last[g.eq] == t) o << "    stl(" << slot(g.eq) << ", F[" << g.eq << "]);\n";
+  }
+  for (int i = 0; i < n; ++i) {
+    if (!ft[i]) o << "    stl(" << slot(i) << ", cd{0.0, 0.0});\n";
+    for (int j = 0; j < n; ++j)
+      if (!jt[(size_t)i * n + j]) o << "    " << jn(i, j) << " = {0.0, 0.0};\n";
+  }
+  o << "  }\n};\n\n}  // namespace gen\n}  // namespace hp\n\n"
+    << "using SpecT = hp::Spec<hp::gen::Sys>;\n"
+    << "constexpr int kRkBytes = hp::RkLds<hp::gen::Sys::N>::kBytes;\n\n"
+    << "extern \"C\" __global__ void __launch_bounds__(64) hp_spec_persistent(hp::KArgs a) {\n"
+    << "  __shared__ __attribute__((aligned(16))) char rk[kRkBytes];\n"
+    << "  SpecT tr(a, (hp::lds_char *)rk);\n  hp::lane_persistent<false>(a, tr);\n}\n\n"
+    << "extern \"C\" __global__ void __launch_bounds__(64) hp_spec_plain(hp::KArgs a) {\n"
+    << "  __shared__ __attribute__((aligned(16))) char rk[kRkBytes];\n"
+    << "  SpecT tr(a, (hp::lds_char *)rk);\n  hp::lane_plain<SpecT, 64>(a, tr);\n}\n";
+  return o.str();
+}
+
 // The evaluator follows the group and lane kernels term by term: prefix
 // products from the coefficient give the term value; a backward sweep of
 // suffix products that starts from t gives its partial derivatives already
@@ -80,7 +178,9 @@ bool spec_eligible(int n, const DevTerm *terms, int n_terms) {
 // adds s d_i x_i^{d_i-1} on the diagonal; the right-hand side is chosen by
 // emode.  A Jacobian entry or value is assigned at its first contribution
 // and accumulated with fused multiply-adds afterwards.
-std::string spec_source(int n, const int32_t *deg, const DevTerm *terms, int n_terms, bool sliced) {
+std::string spec_source(int n, const int32_t *deg, const DevTerm *terms, int n_terms, bool sliced,
+                        bool param) {
+  if (param) return param_source(n, terms, n_terms);
   std::vector<GenTerm> T;
   T.reserve(n_terms);
   std::vector<int> emax(n, 1);  // powers the terms use (computed up front)
@@ -91,6 +191,7 @@ std::string spec_source(int n, const int32_t *deg, const DevTerm *terms, int n_t
   std::ostringstream o;
   o << "#include \"spec_track.hpp\"\n\nnamespace hp {\nnamespace gen {\n\nstruct Sys {\n"
     << "  static constexpr int N = " << n << ";\n"
+    << "  static constexpr bool kParam = false;\n"
     << "  __device__ __forceinline__ static void eval(cptr<double2> cf, const cd (&x)[N], double te,\n"
     << "                                              cd s, cd gamma, int emode, cd (&J)[N][N],\n"
     << "                                              lds_char *spare) {\n";

@@ -27,8 +27,11 @@ bool spec_eligible(int n, const DevTerm *terms, int n_terms);
 // packed order (sorted by factor count; the coefficients stay run-time data).
 // sliced: the serving form, whose persistent kernel suspends and resumes
 // paths (lane_drain) and which has no plain kernel
+// param: the coefficient-parameter form (a start system on f's support,
+// coefficient table of (f, g, gamma g - f) per term, start points from
+// memory; plans only)
 std::string spec_source(int n, const int32_t *deg, const DevTerm *terms, int n_terms,
-                        bool sliced = false);
+                        bool sliced = false, bool param = false);
 
 // Code object of spec source for gfx950 (no device needed): from this
 // process's cache, else from the directory $HP_JIT_CACHE names (when set),

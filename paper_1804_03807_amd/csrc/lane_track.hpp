@@ -87,6 +87,9 @@ template <class D, int N, class Rk = RkRegs<N>>
 struct LaneTrack {
   static constexpr int NMAX = N;
   static constexpr int n = N;
+  // a tracker whose paths start at points in memory (DevSys::start) declares
+  // kStartFromMemory = true; the others decode start points from path ids
+  static constexpr bool kStartFromMemory = false;
 
   const KArgs &a;
   const int lane;
@@ -193,12 +196,18 @@ struct LaneTrack {
       if (resume(q)) return;
     }
     const long long pid = ids ? ids[q] : id_base + q;
-    cptr<double> roots = as_const((const double *)a.roots) + 2 * sp->root_base;
+    if constexpr (D::kStartFromMemory) {
+      const double2 *st = sp->start + pid * N;
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      const long long kk = (pid / sp->radix[i]) % deg[i];
-      const int ri = sp->root_off[i] + (int)kk;
-      rk.set_x0(i, {roots[2 * ri], roots[2 * ri + 1]});
+      for (int i = 0; i < N; ++i) rk.set_x0(i, {st[i].x, st[i].y});
+    } else {
+      cptr<double> roots = as_const((const double *)a.roots) + 2 * sp->root_base;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const long long kk = (pid / sp->radix[i]) % deg[i];
+        const int ri = sp->root_off[i] + (int)kk;
+        rk.set_x0(i, {roots[2 * ri], roots[2 * ri + 1]});
+      }
     }
     mode = M_TRACK;
     t = 0.0;

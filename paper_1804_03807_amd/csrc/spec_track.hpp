@@ -10,6 +10,7 @@
 //
 // S provides
 //   static constexpr int N;
+//   static constexpr bool kParam;  (the coefficient-parameter form)
 //   static void eval(cptr<double2> cf, const cd (&x)[N], double te, cd s,
 //                    cd gamma, int emode, cd (&J)[N][N], lds_char *spare);
 // which writes J = t J_f + s J_g at (x, te) with s = gamma (1 - te), and
@@ -26,6 +27,9 @@ namespace hp {
 template <class S>
 struct Spec : LaneTrack<Spec<S>, S::N, RkLds<S::N>> {
   static constexpr int N = S::N;
+  // coefficient-parameter form: start points of the launch's paths from
+  // memory, coefficient table of (f, g, gamma g - f) per term
+  static constexpr bool kStartFromMemory = S::kParam;
   using Base = LaneTrack<Spec<S>, N, RkLds<N>>;
   using Base::a;
   using Base::sp;
@@ -42,7 +46,8 @@ struct Spec : LaneTrack<Spec<S>, S::N, RkLds<S::N>> {
 
   __device__ __forceinline__ void load_system(int s) {
     this->load_common(s);
-    coef = as_const(a.tcoef) + sp->term_base;
+    if constexpr (S::kParam) coef = as_const(a.pcoef) + 3 * (long long)sp->term_base;
+    else coef = as_const(a.tcoef) + sp->term_base;
   }
 
   // [J | rhs]: J in registers, the right-hand side in the lane's spare LDS

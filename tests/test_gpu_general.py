@@ -131,3 +131,69 @@ def test_general_argument_errors(ctx):
                                     hp._c64(1j), hp.ctypes.byref(tol), hp._ptr(ends), hp._ptr(stat),
                                     None, hp.HP_BATCHED)
     assert rc == _lib.HP_E_INVALID_ARG  # g without start points
+
+
+def _continuation_case(ctx, n, seed_a, seed_b):
+    """The finite roots of one random system on the cyclic-n supports (solved
+    by total degree on the GPU) as start points for another such system."""
+    a = W.cyclic_workload(n, seed_a)
+    b = W.cyclic_workload(n, seed_b)
+    sa, sb = a.systems[0], b.systems[0]
+    ea, sta, _ = ctx.track_paths(sa, complex(a.gammas[0]))
+    return sa, sb, ea[sta == 0]
+
+
+@pytest.mark.parametrize("n,seeds", [(5, (50, 51)), (7, (52, 53))])
+def test_parameter_continuation_specialised_kernel(ctx, n, seeds):
+    """A plan for a start system on f's support (hp_plan_create_general) runs
+    the specialised kernel's coefficient-parameter form (variant 300 + n):
+    every path matches the oracle's continuation and the group kernels'
+    continuation (hp_track_paths) to the parity bar, batched and plain
+    results are bitwise equal, and the residual gate holds by the oracle's
+    evaluator."""
+    import torch
+    import paper_1804_03807_amd as hp
+    sa, sb, start = _continuation_case(ctx, n, *seeds)
+    gam = complex(np.exp(1.3j))
+    plan = ctx.plan(sb, gam, g=sa, start=start)
+    P = len(start)
+    out = {}
+    for mode in ("batched", "plain"):
+        e, st, sts = plan.outputs(P)
+        plan.track_device(e, st, sts, mode=mode)
+        torch.cuda.synchronize()
+        t = ctx.last_timing()
+        assert t["variant"] == 300 + n, (mode, t)
+        out[mode] = (hp.Plan.endpoints_to_numpy(e), st.cpu().numpy(), hp.Plan.stats_to_numpy(sts))
+    plan.close()
+    e, st, sts = out["batched"]
+    assert np.array_equal(e.view(np.float64), out["plain"][0].view(np.float64))
+    assert np.array_equal(st, out["plain"][1])
+    log(f"  cyclic-{n} continuation: converged {int((st == 0).sum())} of {P}")
+    e_o, s_o, _ = oracle.track_paths(sb, gam, start=start, g=sa, n_threads=NTHREADS)
+    assert_parity(e, st, e_o, s_o, f"cyclic{n} continuation (specialised)", sb)
+    e_g, s_g, _ = ctx.track_paths(sb, gam, start=start, g=sa)
+    assert ctx.last_timing()["variant"] < 100
+    assert_parity(e, st, e_g, s_g, f"cyclic{n} continuation (specialised vs group)", sb)
+    assert_residuals(sb, e, st)
+
+
+def test_general_plan_other_support_runs_group_kernels(ctx):
+    """A general plan whose start system has another support (linear
+    products of other degrees per equation) takes the group kernels, and
+    matches the oracle."""
+    import torch
+    import paper_1804_03807_amd as hp
+    n = 3
+    g, Lg, bg = W.linear_products(n, [2, 2, 3], np.random.default_rng(63))
+    f, Lf, bf = W.linear_products(n, [2, 3, 2], np.random.default_rng(73))
+    start = lp_roots(n, [2, 2, 3], Lg, bg)
+    gam = complex(np.exp(0.4j))
+    plan = ctx.plan(f, gam, g=g, start=start)
+    e, st, sts = plan.outputs(len(start))
+    plan.track_device(e, st, sts)
+    torch.cuda.synchronize()
+    assert ctx.last_timing()["variant"] < 100
+    plan.close()
+    e_o, s_o, _ = oracle.track_paths(f, gam, start=start, g=g, n_threads=NTHREADS)
+    assert_parity(hp.Plan.endpoints_to_numpy(e), st.cpu().numpy(), e_o, s_o, "linear products", f)

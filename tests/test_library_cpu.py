@@ -94,6 +94,18 @@ def test_specialised_kernel_compiles(hp, n):
     assert hp.spec_compile(d) > 1000
 
 
+def test_specialised_kernel_forms_compile(hp):
+    """The plans', the server's and the coefficient-parameter forms compile
+    (hiprtc, no device); another form number is an argument error."""
+    s = W.cyclic_system(5, np.random.default_rng(9))
+    sizes = [hp.spec_compile(s, form=f) for f in (0, 1, 2)]
+    assert all(b > 1000 for b in sizes)
+    assert sizes[0] == hp.spec_compile(s)
+    with pytest.raises(hp.HomotopyError) as e:
+        hp.spec_compile(s, form=3)
+    assert e.value.code == hp._lib.HP_E_INVALID_ARG
+
+
 def test_specialised_kernel_limits(hp):
     """n above 10 and systems with more than 1024 factors in all have none."""
     with pytest.raises(hp.HomotopyError) as e:
