@@ -51,16 +51,16 @@ COUNTER_PROFILE = {
     "paths_per_wave": 64,
     "waves_per_simd": 0,
     "sources_sha256": {
-        "spec_track.hpp": "bb636574221bdf00805a21bbf4a783b4222c9c83e6ae6b0d1ef22211410816f1",
-        "lane_track.hpp": "c57862aba823120a48aa71a8ff47f4c77eda4a170bfb88596b82c0c4e7babd38",
+        "spec_track.hpp": "da9ae6687eaea5a657d3d9036bdce205a27bfc5e6c87a5e07f1fd712211fb4ad",
+        "lane_track.hpp": "76581c703aa6861ac1cabf51d686efd2e89fad12778e3341dec9143c70caec5c",
         "hp_device.hpp": "f785014ca74114e45d5b32364f08af0b41660996c35cbf08085ef6fbc53b0a3e",
-        "hp_internal.hpp": "9f69f93541a55dda1e17bd1303e1af9e3dddc1f89f2df00bc5aea0cd074c1fa9",
-        "hp_jit.cpp": "539cda6476e6db04fa0235bf354936b966f41021c8148fa51ee4e63b68b82d6d",
+        "hp_internal.hpp": "647ba879129dab7e3f510dbedf642aa9fd7416998719113988cf792a93194213",
+        "hp_jit.cpp": "a8ffb22f9ceeef84ce9458481e73806991049cd21920affafe39808a8b65c16d",
         "reg_lu.hpp": "488a287cfdfca4d8c1b616ad7aa2ae6bd41dfae4f8f485f55d55bd2819711eb2",
     },
-    "fetch_kib": 74601094.875, "fetch_scale": 262144 / 131088.3125,
-    "write_kib": 1382728859.34375, "write_scale": 262144 / 262144,
-    "fma_f64": 232874150898, "mul_f64": 89306967666, "add_f64": 14735539864,
+    "fetch_kib": 74706854.875, "fetch_scale": 262144 / 131088.5,
+    "write_kib": 1382476117.09375, "write_scale": 262144 / 262144,
+    "fma_f64": 232872076788, "mul_f64": 89305942852, "add_f64": 14735393229,
 }
 COUNTER_SOURCES = ["spec_track.hpp", "lane_track.hpp", "hp_device.hpp", "hp_internal.hpp",
                    "hp_jit.cpp", "reg_lu.hpp"]
