@@ -511,6 +511,17 @@ def main():
     start10 = (hp.Plan.endpoints_to_numpy(e)[conv] if args.workload == "cyclic10" else None)
     del e, st, sts
     plan.close()
+    if not args.no_extra:
+        # the same solve with the minimum step size lowered to 1e-16 (a caller
+        # tolerance): paths that stop in the end zone next to a finite root
+        # converge, for more steps on the paths to infinity
+        p16 = ctx.plan(system, gamma, tol=hp.default_tolerances(h_min=1e-16))
+        el16, _, k16, _, _, _, (_, st16, _) = plan_solve_steps(ctx, p16, P, 1, 1, stream)
+        c16 = int((st16 == hp.CONVERGED).sum().item())
+        out["h_min_1e-16"] = {"converged": c16, "tracking_kernel_ms": float(np.mean(k16)),
+                              "paths_per_s": P / el16}
+        p16.close()
+        progress("h_min 1e-16 solve done")
     torch.cuda.empty_cache()
 
     if not args.no_extra:

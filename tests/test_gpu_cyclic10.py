@@ -29,6 +29,7 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 GOLDEN = os.path.join(HERE, "golden", "cyclic10_seed5.npz")
+NTHREADS = min(16, os.cpu_count() or 1)
 
 
 def log(*a):
@@ -172,3 +173,37 @@ def test_cyclic10_solve_post_pass(ctx):
     ce = e[st == 0]
     assert len(oracle.find_duplicates(ce, np.zeros(len(ce), np.int32))) == 0
     assert int((st == 0).sum()) >= meta["converged"]
+
+
+def test_smaller_min_step_recovers_end_zone_roots(ctx):
+    """Cyclic-9 supports (362,880 paths, mixed volume 11,016): with the
+    minimum step size lowered from 1e-13 to 1e-16 (a caller tolerance), the
+    paths that stopped on the minimum step near t = 1 and belong to finite
+    roots converge; the new roots are distinct from the others and from each
+    other, pass the residual gate by the oracle's evaluator, and each of
+    their paths matches the oracle tracked with the same tolerances."""
+    import torch
+    import oracle
+    import paper_1804_03807_amd as hp
+    wl = W.cyclic_workload(9, 42)
+    s, g = wl.systems[0], complex(wl.gammas[0])
+    P = s.bezout()
+    out = {}
+    for h_min in (1e-13, 1e-16):
+        plan = ctx.plan(s, g, tol=hp.default_tolerances(h_min=h_min))
+        e, st, sts = plan.outputs(P)
+        plan.track_device(e, st, sts)
+        torch.cuda.synchronize()
+        out[h_min] = (hp.Plan.endpoints_to_numpy(e), st.cpu().numpy())
+        plan.close()
+    (e0, s0), (e1, s1) = out[1e-13], out[1e-16]
+    new = np.nonzero((s0 == 2) & (s1 == 0))[0]
+    log(f"  cyclic-9: converged {int((s0 == 0).sum())} at h_min 1e-13, {int((s1 == 0).sum())} at 1e-16; "
+        f"{len(new)} paths newly converged")
+    assert len(new) >= 10 and int((s1 == 0).sum()) <= 11016
+    ce = e1[s1 == 0]
+    assert len(oracle.find_duplicates(ce, np.zeros(len(ce), np.int32))) == 0
+    assert_residuals(s, e1, s1)
+    tol = oracle.default_tolerances(h_min=1e-16)
+    e_o, s_o, _ = oracle.track_paths(s, g, path_ids=new, tol=tol, n_threads=NTHREADS)
+    assert_parity(e1[new], s1[new], e_o, s_o, "cyclic9 at h_min 1e-16", s, new, log)
