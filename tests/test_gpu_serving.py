@@ -245,3 +245,69 @@ def test_submit_does_not_compile(ctx):
         assert_parity(e[sample], st[sample], e_o, s_o, s.name, s, sample, log)
     finally:
         srv.close()
+
+
+def test_families_and_tolerances_mixed(ctx):
+    """One server holds a request on the group kernels (a dense system of
+    degree 4 with 1,638 factors: too many for a specialised kernel, too high
+    a degree for the dense ones), one on a specialised
+    kernel, one on the dense kernel, and one with other tolerances (served
+    in epochs of its own), under a 4-step slice that is switched to the
+    adaptive one half way; every result equals the request served alone
+    with slicing off, bit for bit."""
+    import paper_1804_03807_amd as hp
+    rng = np.random.default_rng(1203)
+    reqs = [
+        (W.dense_system(6, [4, 4, 4, 2, 2, 2], rng), complex(np.exp(0.3j)), None),
+        (W.cyclic_system(6, rng), complex(np.exp(1.1j)), None),
+        (W.dense_system(4, [2, 3, 2, 2], rng), complex(np.exp(2.2j)), None),
+        (W.cyclic_system(5, rng), complex(np.exp(0.7j)), hp.default_tolerances(tol_corr=1e-9)),
+    ]
+    ref = []
+    for s, g, tol in reqs:
+        srv = hp.Server(ctx, 1 << 30)
+        try:
+            srv.set_slice(0.0, 0)
+            ref.append(srv.wait(srv.submit(s, g, tol), stats=True))
+        finally:
+            srv.close()
+    srv = hp.Server(ctx, 1 << 30)
+    try:
+        srv.set_slice(0.0, 4)
+        ids = [srv.submit(s, g, tol) for s, g, tol in reqs]
+        time.sleep(0.02)
+        srv.set_slice(50.0, 0)
+        for k, q in enumerate(ids):
+            e, st, sts, _ = srv.wait(q, stats=True)
+            e0, st0, sts0, _ = ref[k]
+            assert np.array_equal(st, st0), f"request {k}: statuses"
+            assert np.array_equal(e.view(np.float64), e0.view(np.float64)), f"request {k}: endpoints"
+            assert np.array_equal(sts["steps"], sts0["steps"]), f"request {k}: steps"
+        log("mixed families", srv.info())
+    finally:
+        srv.close()
+
+
+def test_destroy_with_requests_in_flight(ctx):
+    """Destroying a server while requests are queued, compiling and running
+    returns (the worker and compile threads stop); a new server on the same
+    context then serves normally."""
+    import paper_1804_03807_amd as hp
+    srv = hp.Server(ctx, 1 << 30)
+    srv.set_slice(0.0, 4)
+    for r, s, g in small_requests(6, 6000):
+        srv.submit(s, g)
+    rng = np.random.default_rng(77)
+    srv.submit(W.embed(W.cyclic_system(6, rng), 1, rng, name="embedded_cyclic6"), 0.6 + 0.8j)
+    time.sleep(0.05)
+    t0 = time.perf_counter()
+    srv.close()
+    log(f"destroy took {(time.perf_counter() - t0) * 1e3:.0f} ms")
+    (r, s, g), = small_requests(1, 1000)
+    srv = hp.Server(ctx, 1 << 30)
+    try:
+        e, st, sts, _ = srv.wait(srv.submit(s, g), stats=True)
+        ref = served_alone(ctx, s, g)
+        assert_same((e, st, sts), ref, "after a destroyed server")
+    finally:
+        srv.close()
