@@ -691,6 +691,11 @@ void context_orphan(hp_context *ctx) {
 
 }  // namespace
 
+// Device list of the paths a single-system end game refines (a plan's).
+struct EgList {
+  DevBuf list, count;
+};
+
 struct hp_plan {
   hp_context *ctx = nullptr;
   SysInfo info;
@@ -704,6 +709,7 @@ struct hp_plan {
   bool spec_default = false;  // default variant: the specialised kernel where it applies
   DevBuf start_dev;  // explicit start points [n_start][n] (general plans)
   DevBuf pcoef;      // (cf, cg, gamma cg - cf) per term: coefficient-parameter plans
+  EgList eg;         // the end game's list of paths to refine
   // plain-mode state
   DevBuf px0, pt, ph, piv, pactive;
   DevBuf ids_scratch;
@@ -860,12 +866,27 @@ Kv kv_pick(const Packed &P) {
 
 // End game at t = 1 (double-double refinement and residual test) of the
 // paths a tracking launch over the systems in `dev` has just ended, on the
-// same stream.  total_paths: the queue length of a single-system launch.
+// same stream.  total_paths: the queue length of a single-system launch;
+// with eg given, the paths to refine are first compacted into its list, so
+// that the end game's wavefronts are full.
 int launch_endgame(const DevTables &dev, const Packed &P, const KArgs &a, int64_t total_paths,
-                   hipStream_t s) {
+                   hipStream_t s, EgList *eg = nullptr) {
   if (P.sys.size() == 1) {
     const int64_t blocks = (total_paths + hp::kLanes - 1) / hp::kLanes;
     if (blocks > INT32_MAX) return fail(HP_E_INVALID_ARG, "too many paths for one launch");
+    if (eg && total_paths > 0) {
+      int rc;
+      if ((rc = eg->list.alloc((size_t)total_paths * sizeof(long long)))) return rc;
+      if ((rc = eg->count.alloc(sizeof(unsigned)))) return rc;
+      HIP_TRY(hipMemsetAsync(eg->count.p, 0, sizeof(unsigned), s));
+      HIP_TRY((hipError_t)hp_launch_eg_select(a, total_paths, eg->list.as<long long>(),
+                                              eg->count.as<unsigned>(), s));
+      KArgs b = a;
+      b.eg_list = eg->list.as<long long>();
+      b.eg_count = eg->count.as<unsigned>();
+      HIP_TRY((hipError_t)hp_launch_endgame(P.sys[0].n, b, nullptr, (int)blocks, s));
+      return HP_OK;
+    }
     HIP_TRY((hipError_t)hp_launch_endgame(P.sys[0].n, a, nullptr, (int)blocks, s));
     return HP_OK;
   }
@@ -885,7 +906,7 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
                       const hp_tolerances &tol, int64_t total_paths, hp_c64 *endpoints,
                       int32_t *status, hp_path_stats *stats, hipStream_t s, int *groups_out,
                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, hipEvent_t em = nullptr,
-                      int32_t step_budget = -1) {
+                      int32_t step_budget = -1, EgList *eg = nullptr) {
   const bool sliced = step_budget >= 0;
   if (sliced && !k.spec && !k.dense) return fail(HP_E_INVALID_ARG, "no serving form of this kernel");
   if (!e0) {  // the context's events: e0 .. em the tracking kernel, em .. e1 the end game
@@ -944,7 +965,7 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
     HIP_TRY((hipError_t)hp_launch_persistent(k.nmax, P.general, a, (int)groups, lds, s));
   }
   if (em) HIP_TRY(hipEventRecord(em, s));
-  if ((rc = launch_endgame(dev, P, a, total_paths, s))) return rc;
+  if ((rc = launch_endgame(dev, P, a, total_paths, s, eg))) return rc;
   HIP_TRY(hipEventRecord(e1, s));
   if (groups_out) *groups_out = (int)groups;
   return HP_OK;
@@ -1103,7 +1124,7 @@ int track_plain(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_c64 *endp
     ++launches;
   }
   HIP_TRY(hipEventRecord(ctx->evm, s));
-  if (active == 0 && (rc = launch_endgame(plan->dev, plan->P, a, n_paths, s))) return rc;
+  if (active == 0 && (rc = launch_endgame(plan->dev, plan->P, a, n_paths, s, &plan->eg))) return rc;
   HIP_TRY(hipEventRecord(ctx->ev1, s));
   ctx->last.launches = launches;
   ctx->last.groups = wgs;
@@ -1404,7 +1425,8 @@ int hp_plan_track_device(hp_plan *plan, const int64_t *ids, int64_t n_paths, hp_
     HIP_TRY(hipMemcpyAsync(plan->dev.sys.p, &d, sizeof(d), hipMemcpyHostToDevice, s));
     int groups = 0;
     if ((rc = launch_persistent(ctx, plan->dev, plan->P, plan->kv, plan->tol, n_paths,
-                                endpoints, status, stats, s, &groups)))
+                                endpoints, status, stats, s, &groups, nullptr, nullptr, nullptr,
+                                -1, &plan->eg)))
       return rc;
     ctx->last.launches = 1;
     ctx->last.groups = groups;

@@ -121,6 +121,8 @@ struct KArgs {
                          // wavefront hold paths (0: all 64), a tuning choice
   const double2 *pcoef;  // specialised kernels in the coefficient-parameter form:
                          // (cf, cg, gamma cg - cf) per term, in packed term order
+  const long long *eg_list;  // end game of a single-system launch: the queue indices
+  const unsigned *eg_count;  // of the paths to refine (k_eg_select), and their number
 };
 
 // Lanes of a wavefront that take paths from the refill queue in the
@@ -295,6 +297,12 @@ int hp_launch_collect(const hp::CollectArgs &a, void *stream);
 int hp_launch_fill_i32(int32_t *p, long long m, int32_t v, void *stream);
 // End game of the paths of systems with n unknowns: blk[b] = (system, first
 // queue index) of block b (64 paths each), or blk == nullptr for one system
-// (system 0, block b from queue index 64 b).
+// (system 0, block b from queue index 64 b, or from entry 64 b of
+// a.eg_list when that is set).
 int hp_launch_endgame(int n, const hp::KArgs &a, const int2 *blk, int blocks, void *stream);
+// Compacts the queue indices 0 .. n-1 of system 0 whose paths the end game
+// refines (CONVERGED or FAILED_NEWTON_T1) into list, their number into
+// *count (zeroed by the caller).
+int hp_launch_eg_select(const hp::KArgs &a, long long n, long long *list, unsigned *count,
+                        void *stream);
 }
