@@ -113,29 +113,39 @@ __device__ __forceinline__ double max_mod(const cd (&v)[N]) {
   return m;
 }
 
-// The queue indices of system 0 whose paths the end game refines, appended
-// to a list with one atomic per wavefront (ballot, popcount, mbcnt), so that
-// the end game's wavefronts are full instead of one converged path in many.
-__global__ void __launch_bounds__(256) k_eg_select(KArgs a, long long n, long long *list,
-                                                   unsigned *count) {
-  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  cptr<DevSys> sp = as_const(a.sys);
+// The queue indices whose paths the end game refines, compacted per system
+// (from the system's eg_list_base) with one atomic per wavefront (ballot,
+// popcount, mbcnt), so that the end game's wavefronts are full instead of
+// one converged path among many stopped or suspended ones, and each still
+// holds paths of one system.  Block b covers 64 queue entries of one
+// system: blk[b] = (system, first index), or for one system (blk ==
+// nullptr) indices 64 b .. 64 b + 63 of system 0.
+__global__ void __launch_bounds__(64) k_eg_select(KArgs a, const int2 *blk, long long *list,
+                                                  unsigned *counts) {
+  const int lane = threadIdx.x & 63;
+  int s = 0;
+  long long q = (long long)blockIdx.x * 64 + lane;
+  if (blk) {
+    const int2 b = blk[blockIdx.x];
+    s = b.x;
+    q = (long long)b.y + lane;
+  }
+  cptr<DevSys> sp = as_const(a.sys) + s;
   bool take = false;
-  if (q < n) {
+  if (q < sp->n_paths) {
     const long long *slots = (const long long *)sp->slots;
     const int st = a.status[sp->out_path_base + (slots ? slots[q] : q)];
     take = st == HP_CONVERGED || st == HP_FAILED_NEWTON_T1;
   }
   const uint64_t m = __ballot(take);
   if (m == 0) return;
-  const int lane = threadIdx.x & 63;
   const int first = __builtin_ctzll(m);
   unsigned base = 0;
-  if (lane == first) base = atomicAdd(count, (unsigned)__popcll(m));
+  if (lane == first) base = atomicAdd(counts + s, (unsigned)__popcll(m));
   base = __shfl(base, first);
   if (!take) return;
-  list[base + __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                         __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u))] = q;
+  list[sp->eg_list_base + base +
+       __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u))] = q;
 }
 
 template <int N>
@@ -147,11 +157,12 @@ __global__ void __launch_bounds__(64) k_endgame(KArgs a, const int2 *blk) {
     const int2 b = blk[blockIdx.x];
     s = b.x;
     q = (long long)b.y + lane;
-  } else if (a.eg_list) {
-    if (q >= (long long)*a.eg_count) return;
-    q = a.eg_list[q];
   }
   cptr<DevSys> sp = as_const(a.sys) + s;
+  if (a.eg_list) {
+    if (q >= (long long)a.eg_count[s]) return;
+    q = a.eg_list[sp->eg_list_base + q];
+  }
   if (q >= sp->n_paths) return;
   // output slot of queue index q (serving keeps paths in slots of an arena)
   const long long *slots = (const long long *)sp->slots;
@@ -239,11 +250,11 @@ int launch_n(const KArgs &a, const int2 *blk, int blocks, hipStream_t s) {
 }  // namespace
 }  // namespace hp
 
-int hp_launch_eg_select(const hp::KArgs &a, long long n, long long *list, unsigned *count,
-                        void *stream) {
-  if (n <= 0) return (int)hipSuccess;
-  hipLaunchKernelGGL(hp::k_eg_select, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                     (hipStream_t)stream, a, n, list, count);
+int hp_launch_eg_select(const hp::KArgs &a, const int2 *blk, int blocks, long long *list,
+                        unsigned *count, void *stream) {
+  if (blocks <= 0) return (int)hipSuccess;
+  hipLaunchKernelGGL(hp::k_eg_select, dim3((unsigned)blocks), dim3(64), 0, (hipStream_t)stream, a,
+                     blk, list, count);
   return (int)hipGetLastError();
 }
 

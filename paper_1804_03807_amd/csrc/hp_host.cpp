@@ -403,12 +403,17 @@ struct DevTables {
     for (const DevSys &d : P.sys)
       if (d.n_paths > INT32_MAX - hp::kLanes)
         return fail(HP_E_INVALID_ARG, "too many paths for one system of a batch");
+    // the end game's list of system k starts where its first block's
+    // entries would (one system: at 0)
+    std::vector<DevSys> sysv(P.sys);
     for (int n = 1; n <= HP_MAX_N; ++n) {
       eg_first[n] = (int)blk.size();
       for (size_t k = 0; k < P.sys.size(); ++k)
-        if (P.sys[k].n == n && P.sys.size() > 1)
+        if (P.sys[k].n == n && P.sys.size() > 1) {
+          sysv[k].eg_list_base = (int64_t)blk.size() * hp::kLanes;
           for (int64_t q = 0; q < P.sys[k].n_paths; q += hp::kLanes)
             blk.push_back(make_int2((int)k, (int)q));
+        }
     }
     eg_first[HP_MAX_N + 1] = (int)blk.size();
     if ((rc = egblk.alloc(std::max<size_t>(1, blk.size()) * sizeof(int2)))) return rc;
@@ -440,7 +445,7 @@ struct DevTables {
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(roots.p, P.roots.data(), P.roots.size() * sizeof(double2),
                            hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(sys.p, P.sys.data(), P.sys.size() * sizeof(DevSys),
+    HIP_TRY(hipMemcpyAsync(sys.p, sysv.data(), sysv.size() * sizeof(DevSys),
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
     return HP_OK;
@@ -866,28 +871,44 @@ Kv kv_pick(const Packed &P) {
 
 // End game at t = 1 (double-double refinement and residual test) of the
 // paths a tracking launch over the systems in `dev` has just ended, on the
-// same stream.  total_paths: the queue length of a single-system launch;
-// with eg given, the paths to refine are first compacted into its list, so
-// that the end game's wavefronts are full.
+// same stream.  total_paths: the queue length of a single-system launch.
+// With eg given, the paths to refine are first compacted into its list (per
+// n for a multi-system launch), so that the end game's wavefronts are full.
 int launch_endgame(const DevTables &dev, const Packed &P, const KArgs &a, int64_t total_paths,
                    hipStream_t s, EgList *eg = nullptr) {
-  if (P.sys.size() == 1) {
-    const int64_t blocks = (total_paths + hp::kLanes - 1) / hp::kLanes;
-    if (blocks > INT32_MAX) return fail(HP_E_INVALID_ARG, "too many paths for one launch");
-    if (eg && total_paths > 0) {
-      int rc;
-      if ((rc = eg->list.alloc((size_t)total_paths * sizeof(long long)))) return rc;
-      if ((rc = eg->count.alloc(sizeof(unsigned)))) return rc;
-      HIP_TRY(hipMemsetAsync(eg->count.p, 0, sizeof(unsigned), s));
-      HIP_TRY((hipError_t)hp_launch_eg_select(a, total_paths, eg->list.as<long long>(),
+  const bool one = P.sys.size() == 1;
+  const int64_t single_blocks = (total_paths + hp::kLanes - 1) / hp::kLanes;
+  if (one && single_blocks > INT32_MAX) return fail(HP_E_INVALID_ARG, "too many paths for one launch");
+  if (eg) {
+    // per system a list region from its eg_list_base (64 entries per block
+    // of its queue), one counter per system
+    const int64_t entries = one ? single_blocks * hp::kLanes
+                                : (int64_t)dev.eg_first[HP_MAX_N + 1] * hp::kLanes;
+    if (entries == 0) return HP_OK;
+    int rc;
+    if ((rc = eg->list.alloc((size_t)entries * sizeof(long long)))) return rc;
+    if ((rc = eg->count.alloc(P.sys.size() * sizeof(unsigned)))) return rc;
+    HIP_TRY(hipMemsetAsync(eg->count.p, 0, P.sys.size() * sizeof(unsigned), s));
+    KArgs b = a;
+    b.eg_list = eg->list.as<long long>();
+    b.eg_count = eg->count.as<unsigned>();
+    if (one) {
+      HIP_TRY((hipError_t)hp_launch_eg_select(a, nullptr, (int)single_blocks, eg->list.as<long long>(),
                                               eg->count.as<unsigned>(), s));
-      KArgs b = a;
-      b.eg_list = eg->list.as<long long>();
-      b.eg_count = eg->count.as<unsigned>();
-      HIP_TRY((hipError_t)hp_launch_endgame(P.sys[0].n, b, nullptr, (int)blocks, s));
+      HIP_TRY((hipError_t)hp_launch_endgame(P.sys[0].n, b, nullptr, (int)single_blocks, s));
       return HP_OK;
     }
-    HIP_TRY((hipError_t)hp_launch_endgame(P.sys[0].n, a, nullptr, (int)blocks, s));
+    HIP_TRY((hipError_t)hp_launch_eg_select(a, dev.egblk.as<int2>(), dev.eg_first[HP_MAX_N + 1],
+                                            eg->list.as<long long>(), eg->count.as<unsigned>(), s));
+    for (int n = 1; n <= HP_MAX_N; ++n) {
+      const int b0 = dev.eg_first[n], b1 = dev.eg_first[n + 1];
+      if (b1 > b0)
+        HIP_TRY((hipError_t)hp_launch_endgame(n, b, dev.egblk.as<int2>() + b0, b1 - b0, s));
+    }
+    return HP_OK;
+  }
+  if (one) {
+    HIP_TRY((hipError_t)hp_launch_endgame(P.sys[0].n, a, nullptr, (int)single_blocks, s));
     return HP_OK;
   }
   for (int n = 1; n <= HP_MAX_N; ++n) {
@@ -1252,7 +1273,8 @@ int autotune(hp_plan *plan) {
   Kv best_k = def;
   rc = tune_pick(cands, def, [&](const Kv &k, float &ms) {
     int r = launch_persistent(ctx, plan->dev, plan->P, k, plan->tol, sample, e.as<hp_c64>(),
-                              st.as<int32_t>(), nullptr, ctx->stream, nullptr);
+                              st.as<int32_t>(), nullptr, ctx->stream, nullptr, nullptr, nullptr,
+                              nullptr, -1, &plan->eg);
     if (r) return r;
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
@@ -1618,9 +1640,10 @@ int hp_track_batch(hp_context *ctx, const hp_system *fs, int32_t n_systems, cons
     return rc;
   int groups = 0;
   ctx->last = hp_timing{};
+  EgList egl;
   if ((rc = launch_persistent(ctx, dev, P, kv, T, total, e.as<hp_c64>(),
                               st.as<int32_t>(), stats ? sts.as<hp_path_stats>() : nullptr,
-                              ctx->stream, &groups)))
+                              ctx->stream, &groups, nullptr, nullptr, nullptr, -1, &egl)))
     return rc;
   HIP_TRY(hipEventSynchronize(ctx->ev1));
   float ms = 0.f, eg = 0.f;
@@ -1675,12 +1698,13 @@ int hp_tune_batch(hp_context *ctx, const hp_system *fs, int32_t n_systems, const
   DevTables dev;
   if ((rc = dev.upload(P, ctx->stream))) return rc;
   DevBuf e, st;
+  EgList eg;
   if ((rc = e.alloc((size_t)std::max<int64_t>(1, xo[n_systems]) * sizeof(hp_c64)))) return rc;
   if ((rc = st.alloc((size_t)std::max<int64_t>(1, total) * sizeof(int32_t)))) return rc;
   Kv best = def;
   rc = tune_pick(cands, def, [&](const Kv &k, float &ms) {
     int r = launch_persistent(ctx, dev, P, k, T, sample, e.as<hp_c64>(), st.as<int32_t>(), nullptr,
-                              ctx->stream, nullptr);
+                              ctx->stream, nullptr, nullptr, nullptr, nullptr, -1, &eg);
     if (r) return r;
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
@@ -2056,8 +2080,9 @@ int hp_membership_test(hp_context *ctx, const hp_system *e, int32_t n_hyper, con
   kv_decode(nmax_for(n), kv);  // general start systems run on the group kernels
   int groups = 0;
   ctx->last = hp_timing{};
+  EgList egl;
   if ((rc = launch_persistent(ctx, dev, P, kv, T, total, de.as<hp_c64>(), ds.as<int32_t>(), nullptr,
-                              ctx->stream, &groups)))
+                              ctx->stream, &groups, nullptr, nullptr, nullptr, -1, &egl)))
     return rc;
   HIP_TRY(hipEventSynchronize(ctx->ev1));
   float ms = 0.f, eg = 0.f;
@@ -2332,6 +2357,7 @@ struct hp_server {
   hipStream_t fam_stream[kFamilyStreams] = {};
   std::vector<std::array<hipEvent_t, 2>> fam_ev;  // per family of an epoch
   std::vector<std::unique_ptr<DevTables>> fam_dev;
+  std::vector<std::unique_ptr<EgList>> fam_eg;  // the end game's list per family
   std::mutex mu;
   std::condition_variable cv_work, cv_done, cv_compile;
   std::deque<std::shared_ptr<Request>> pending, to_compile;
@@ -2562,6 +2588,7 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
     }
   }
   while (S->fam_dev.size() < P.size()) S->fam_dev.emplace_back(new DevTables());
+  while (S->fam_eg.size() < P.size()) S->fam_eg.emplace_back(new EgList());
   while (S->fam_ev.size() < P.size()) {
     std::array<hipEvent_t, 2> ev{};
     HIP_TRY(hipEventCreate(&ev[0]));
@@ -2578,7 +2605,8 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
     if (rc == HP_OK)
       rc = launch_persistent(ctx, *S->fam_dev[f], P[f], kv, tol, total[f], S->a_ends.as<hp_c64>(),
                              S->a_status.as<int32_t>(), S->a_stats.as<hp_path_stats>(), fs,
-                             nullptr, S->fam_ev[f][0], S->fam_ev[f][1], nullptr, fam_steps[f]);
+                             nullptr, S->fam_ev[f][0], S->fam_ev[f][1], nullptr, fam_steps[f],
+                             S->fam_eg[f].get());
   }
   // every launched family ends before the harvest reads the arena
   for (int q = 0; q < kFamilyStreams; ++q) HIP_TRY(hipStreamSynchronize(S->fam_stream[q]));

@@ -71,6 +71,10 @@ struct alignas(16) DevSys {
   int32_t eg_base;
   int32_t eg_ptr[HP_MAX_N + 1];
   int32_t eg_pad[2];
+  // the end game's compacted list of this system's paths to refine starts
+  // at this entry (64 entries per block of its queue)
+  int64_t eg_list_base;
+  int64_t eg_list_pad;
 };
 
 // Dense kernel: systems of n <= kDenseMaxN unknowns whose equations have
@@ -121,8 +125,9 @@ struct KArgs {
                          // wavefront hold paths (0: all 64), a tuning choice
   const double2 *pcoef;  // specialised kernels in the coefficient-parameter form:
                          // (cf, cg, gamma cg - cf) per term, in packed term order
-  const long long *eg_list;  // end game of a single-system launch: the queue indices
-  const unsigned *eg_count;  // of the paths to refine (k_eg_select), and their number
+  const long long *eg_list;  // end game over a list: per system, from its eg_list_base, the
+  const unsigned *eg_count;  // queue indices of the paths to refine (k_eg_select); per
+                             // system their number
 };
 
 // Lanes of a wavefront that take paths from the refill queue in the
@@ -297,12 +302,13 @@ int hp_launch_collect(const hp::CollectArgs &a, void *stream);
 int hp_launch_fill_i32(int32_t *p, long long m, int32_t v, void *stream);
 // End game of the paths of systems with n unknowns: blk[b] = (system, first
 // queue index) of block b (64 paths each), or blk == nullptr for one system
-// (system 0, block b from queue index 64 b, or from entry 64 b of
-// a.eg_list when that is set).
+// (system 0, block b from queue index 64 b); with a.eg_list set, the block
+// takes the same positions of its system's compacted list instead.
 int hp_launch_endgame(int n, const hp::KArgs &a, const int2 *blk, int blocks, void *stream);
-// Compacts the queue indices 0 .. n-1 of system 0 whose paths the end game
-// refines (CONVERGED or FAILED_NEWTON_T1) into list, their number into
-// *count (zeroed by the caller).
-int hp_launch_eg_select(const hp::KArgs &a, long long n, long long *list, unsigned *count,
-                        void *stream);
+// Compacts, per system, the queue indices of `blocks` blocks (blk as for
+// hp_launch_endgame) whose paths the end game refines (CONVERGED or
+// FAILED_NEWTON_T1) into list from the system's eg_list_base, their number
+// into counts[system] (zeroed by the caller).
+int hp_launch_eg_select(const hp::KArgs &a, const int2 *blk, int blocks, long long *list,
+                        unsigned *counts, void *stream);
 }
