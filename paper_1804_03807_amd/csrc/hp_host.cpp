@@ -397,7 +397,9 @@ struct DevTables {
   // end-game blocks of a multi-system launch, grouped by n: the blocks of
   // the systems with n unknowns are eg_first[n] .. eg_first[n+1]-1 of egblk
   int eg_first[HP_MAX_N + 2] = {};
-  int upload(const Packed &P, hipStream_t s) {
+  // The system descriptors and the end-game block table (both depend on the
+  // queue lengths); synchronous when sync.
+  int upload_sys(const Packed &P, hipStream_t s, bool sync) {
     int rc;
     std::vector<int2> blk;
     for (const DevSys &d : P.sys)
@@ -420,6 +422,16 @@ struct DevTables {
     if (!blk.empty())
       HIP_TRY(hipMemcpyAsync(egblk.p, blk.data(), blk.size() * sizeof(int2),
                              hipMemcpyHostToDevice, s));
+    if ((rc = sys.alloc(std::max<size_t>(1, P.sys.size()) * sizeof(DevSys)))) return rc;
+    if ((rc = qhead.alloc(std::max<size_t>(1, P.sys.size()) * sizeof(unsigned long long)))) return rc;
+    HIP_TRY(hipMemcpyAsync(sys.p, sysv.data(), sysv.size() * sizeof(DevSys),
+                           hipMemcpyHostToDevice, s));
+    if (sync) HIP_TRY(hipStreamSynchronize(s));
+    return HP_OK;
+  }
+  int upload(const Packed &P, hipStream_t s) {
+    int rc;
+    if ((rc = upload_sys(P, s, false))) return rc;
     const size_t nt = std::max<size_t>(1, P.terms.size());
     if ((rc = dcoef.alloc(std::max<size_t>(1, P.dense.size()) * sizeof(double2)))) return rc;
     if (!P.dense.empty())
@@ -429,8 +441,6 @@ struct DevTables {
     if ((rc = tmeta.alloc(nt * sizeof(uint4)))) return rc;
     if ((rc = kp.alloc(std::max<size_t>(1, P.kp.size()) * sizeof(int32_t)))) return rc;
     if ((rc = roots.alloc(std::max<size_t>(1, P.roots.size()) * sizeof(double2)))) return rc;
-    if ((rc = sys.alloc(std::max<size_t>(1, P.sys.size()) * sizeof(DevSys)))) return rc;
-    if ((rc = qhead.alloc(std::max<size_t>(1, P.sys.size()) * sizeof(unsigned long long)))) return rc;
     std::vector<double2> coef(P.terms.size());
     std::vector<uint4> meta(P.terms.size());
     for (size_t i = 0; i < P.terms.size(); ++i) {
@@ -444,8 +454,6 @@ struct DevTables {
     HIP_TRY(hipMemcpyAsync(kp.p, P.kp.data(), P.kp.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(roots.p, P.roots.data(), P.roots.size() * sizeof(double2),
-                           hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(sys.p, sysv.data(), sysv.size() * sizeof(DevSys),
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
     return HP_OK;
@@ -2346,6 +2354,16 @@ struct Request {
 
 }  // namespace
 
+// A kernel family's launch state in the server: the requests packed into P
+// (in order), their device tables and the end game's list.
+struct FamState {
+  std::vector<int64_t> req_ids;
+  Packed P;
+  DevTables dev;
+  EgList eg;
+  bool valid = false;
+};
+
 // Streams on which the kernel families of an epoch run side by side (with
 // the server's own stream the process holds four hardware queues).
 constexpr int kFamilyStreams = 3;
@@ -2356,8 +2374,9 @@ struct hp_server {
   hipStream_t stream = nullptr;
   hipStream_t fam_stream[kFamilyStreams] = {};
   std::vector<std::array<hipEvent_t, 2>> fam_ev;  // per family of an epoch
-  std::vector<std::unique_ptr<DevTables>> fam_dev;
-  std::vector<std::unique_ptr<EgList>> fam_eg;  // the end game's list per family
+  // per kernel family: its packed systems and device tables, kept while its
+  // set of requests stays the same
+  std::map<std::pair<int, const void *>, std::unique_ptr<FamState>> fam_state;
   std::mutex mu;
   std::condition_variable cv_work, cv_done, cv_compile;
   std::deque<std::shared_ptr<Request>> pending, to_compile;
@@ -2525,8 +2544,11 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
 
   // ---- one launch per kernel family, each request on the family it runs
   // on alone, so that its result does not depend on the other requests ----
+  // families in the order of their first request; each family's packed
+  // systems and device tables are kept from one epoch to the next and
+  // only their queue fields refreshed while its set of requests is the same
   std::map<std::pair<int, const void *>, size_t> fam_of;
-  std::vector<Packed> P;
+  std::vector<std::vector<size_t>> members;
   std::vector<int64_t> total;
   std::vector<Kv> fam_kv;
   std::vector<std::pair<int, const void *>> fam_key;
@@ -2536,8 +2558,8 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
     const auto key = R.family();
     auto it = fam_of.find(key);
     if (it == fam_of.end()) {
-      it = fam_of.emplace(key, P.size()).first;
-      P.emplace_back();
+      it = fam_of.emplace(key, members.size()).first;
+      members.emplace_back();
       total.push_back(0);
       fam_key.push_back(key);
       Kv kv;
@@ -2557,26 +2579,51 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
       }
       fam_kv.push_back(kv);  // group family: chosen from its systems below
     }
-    const size_t f = it->second;
-    // queue entries go to the request's arena region: path slots from
-    // region_off, endpoint slots of n coordinates from region_off * HP_MAX_N
-    if (R.sliceable()) {
-      pack_append(P[f], &R.sys, R.info, R.gamma, R.qlen, R.region_off, R.region_off * HP_MAX_N,
-                  d_ids + R.qoff);
-      P[f].sys.back().slots = d_slots + R.qoff;
-    } else {
-      pack_append(P[f], &R.sys, R.info, R.gamma, R.qlen, R.region_off, R.region_off * HP_MAX_N,
-                  nullptr);
-      P[f].sys.back().id_base = h_ids[R.qoff];
+    members[it->second].push_back(i);
+    total[it->second] += R.qlen;
+  }
+  std::vector<FamState *> fam(members.size());
+  std::vector<bool> fam_fresh(members.size(), false);
+  for (size_t f = 0; f < members.size(); ++f) {
+    auto &slot = S->fam_state[fam_key[f]];
+    if (!slot) slot.reset(new FamState());
+    FamState &F = *slot;
+    fam[f] = &F;
+    std::vector<int64_t> ids;
+    for (size_t i : members[f]) ids.push_back(batch[i]->id);
+    const bool same = F.valid && ids == F.req_ids;
+    if (!same) {
+      F.P = Packed();
+      F.req_ids = ids;
+      F.valid = true;
+      fam_fresh[f] = true;
     }
-    total[f] += R.qlen;
+    for (size_t m = 0; m < members[f].size(); ++m) {
+      Request &R = *batch[members[f][m]];
+      // queue entries go to the request's arena region: path slots from
+      // region_off, endpoint slots of n coordinates from region_off * HP_MAX_N
+      if (!same)
+        pack_append(F.P, &R.sys, R.info, R.gamma, R.qlen, R.region_off, R.region_off * HP_MAX_N,
+                    nullptr);
+      DevSys &d = F.P.sys[m];
+      d.n_paths = R.qlen;
+      if (R.sliceable()) {
+        d.ids = d_ids + R.qoff;
+        d.slots = d_slots + R.qoff;
+        d.id_base = 0;
+      } else {
+        d.ids = nullptr;
+        d.slots = nullptr;
+        d.id_base = h_ids[R.qoff];
+      }
+    }
   }
   // step budget per family: -1 for the group kernels (no serving form), 0
   // (no limit) when slicing is off
-  std::vector<int32_t> fam_steps(P.size(), 0);
+  std::vector<int32_t> fam_steps(members.size(), 0);
   {
     std::lock_guard<std::mutex> lk(S->mu);
-    for (size_t f = 0; f < P.size(); ++f) {
+    for (size_t f = 0; f < members.size(); ++f) {
       if (fam_key[f].first == 0) fam_steps[f] = -1;
       if (fam_key[f].first == 0 || !sliced) continue;
       if (fixed_steps > 0) {
@@ -2587,9 +2634,7 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
       }
     }
   }
-  while (S->fam_dev.size() < P.size()) S->fam_dev.emplace_back(new DevTables());
-  while (S->fam_eg.size() < P.size()) S->fam_eg.emplace_back(new EgList());
-  while (S->fam_ev.size() < P.size()) {
+  while (S->fam_ev.size() < members.size()) {
     std::array<hipEvent_t, 2> ev{};
     HIP_TRY(hipEventCreate(&ev[0]));
     HIP_TRY(hipEventCreate(&ev[1]));
@@ -2597,22 +2642,23 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
   }
   // the families run side by side (their requests' arena regions are
   // disjoint), each on one of the family streams
-  for (size_t f = 0; f < P.size() && rc == HP_OK; ++f) {
+  for (size_t f = 0; f < members.size() && rc == HP_OK; ++f) {
     const hipStream_t fs = S->fam_stream[f % kFamilyStreams];
+    FamState &F = *fam[f];
     Kv kv = fam_kv[f];
-    if (!kv.spec && !kv.dense) kv_decode(nmax_for(P[f].nl), kv);  // group kernels
-    rc = S->fam_dev[f]->upload(P[f], fs);
+    if (!kv.spec && !kv.dense) kv_decode(nmax_for(F.P.nl), kv);  // group kernels
+    rc = fam_fresh[f] ? F.dev.upload(F.P, fs) : F.dev.upload_sys(F.P, fs, true);
     if (rc == HP_OK)
-      rc = launch_persistent(ctx, *S->fam_dev[f], P[f], kv, tol, total[f], S->a_ends.as<hp_c64>(),
+      rc = launch_persistent(ctx, F.dev, F.P, kv, tol, total[f], S->a_ends.as<hp_c64>(),
                              S->a_status.as<int32_t>(), S->a_stats.as<hp_path_stats>(), fs,
                              nullptr, S->fam_ev[f][0], S->fam_ev[f][1], nullptr, fam_steps[f],
-                             S->fam_eg[f].get());
+                             &F.eg);
   }
   // every launched family ends before the harvest reads the arena
   for (int q = 0; q < kFamilyStreams; ++q) HIP_TRY(hipStreamSynchronize(S->fam_stream[q]));
   if (rc) return rc;
-  std::vector<float> fam_ms(P.size(), 0.0f);
-  for (size_t f = 0; f < P.size(); ++f)
+  std::vector<float> fam_ms(members.size(), 0.0f);
+  for (size_t f = 0; f < members.size(); ++f)
     HIP_TRY(hipEventElapsedTime(&fam_ms[f], S->fam_ev[f][0], S->fam_ev[f][1]));
 
   // ---- harvest: finished paths to the host results, slots freed ----
@@ -2669,7 +2715,7 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
   }
   // unfinished queue entries keep their slots and go first next epoch
   int64_t carried = 0;
-  std::vector<bool> fam_open(P.size(), false);
+  std::vector<bool> fam_open(members.size(), false);
   for (size_t i = 0; i < batch.size(); ++i) {
     Request &R = *batch[i];
     if (R.qlen == 0) continue;
@@ -2690,7 +2736,7 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
   S->epoch_ms_max = std::max(S->epoch_ms_max, ms);
   // adapt each sliced family's step budget toward the slice time
   if (fixed_steps <= 0 && slice_ms > 0.0) {
-    for (size_t f = 0; f < P.size(); ++f) {
+    for (size_t f = 0; f < members.size(); ++f) {
       if (fam_steps[f] <= 0) continue;
       int32_t b = fam_steps[f];
       const double km = std::max(0.01, (double)fam_ms[f]);
