@@ -54,13 +54,13 @@ COUNTER_PROFILE = {
         "spec_track.hpp": "da9ae6687eaea5a657d3d9036bdce205a27bfc5e6c87a5e07f1fd712211fb4ad",
         "lane_track.hpp": "76581c703aa6861ac1cabf51d686efd2e89fad12778e3341dec9143c70caec5c",
         "hp_device.hpp": "f785014ca74114e45d5b32364f08af0b41660996c35cbf08085ef6fbc53b0a3e",
-        "hp_internal.hpp": "647ba879129dab7e3f510dbedf642aa9fd7416998719113988cf792a93194213",
+        "hp_internal.hpp": "cc3be49581c7f77a8dfb21b9ac976e0fca621f7823e45645fc7f6ab27bb214c8",
         "hp_jit.cpp": "a8ffb22f9ceeef84ce9458481e73806991049cd21920affafe39808a8b65c16d",
         "reg_lu.hpp": "488a287cfdfca4d8c1b616ad7aa2ae6bd41dfae4f8f485f55d55bd2819711eb2",
     },
-    "fetch_kib": 74706854.875, "fetch_scale": 262144 / 131088.5,
-    "write_kib": 1382476117.09375, "write_scale": 262144 / 262144,
-    "fma_f64": 232872076788, "mul_f64": 89305942852, "add_f64": 14735393229,
+    "fetch_kib": 74402068.375, "fetch_scale": 262144 / 131088.625,
+    "write_kib": 1382883062.65625, "write_scale": 262144 / 262144,
+    "fma_f64": 232883799150, "mul_f64": 89310538483, "add_f64": 14736141312,
 }
 COUNTER_SOURCES = ["spec_track.hpp", "lane_track.hpp", "hp_device.hpp", "hp_internal.hpp",
                    "hp_jit.cpp", "reg_lu.hpp"]
