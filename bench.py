@@ -54,7 +54,7 @@ COUNTER_PROFILE = {
         "spec_track.hpp": "da9ae6687eaea5a657d3d9036bdce205a27bfc5e6c87a5e07f1fd712211fb4ad",
         "lane_track.hpp": "76581c703aa6861ac1cabf51d686efd2e89fad12778e3341dec9143c70caec5c",
         "hp_device.hpp": "f785014ca74114e45d5b32364f08af0b41660996c35cbf08085ef6fbc53b0a3e",
-        "hp_internal.hpp": "cc3be49581c7f77a8dfb21b9ac976e0fca621f7823e45645fc7f6ab27bb214c8",
+        "hp_internal.hpp": "04d72d8dc92692465d92694753b7823abd45cd078a64a32017983d7254a73f3f",
         "hp_jit.cpp": "a8ffb22f9ceeef84ce9458481e73806991049cd21920affafe39808a8b65c16d",
         "reg_lu.hpp": "488a287cfdfca4d8c1b616ad7aa2ae6bd41dfae4f8f485f55d55bd2819711eb2",
     },

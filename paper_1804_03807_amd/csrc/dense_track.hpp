@@ -4,12 +4,8 @@
 // zero where absent; layout in hp_internal.hpp).
 //
 // Evaluation.  With the loops over variables unrolled for the compile-time
-// n, an equation is evaluated in nested (Horner) form,
-//   f = c + sum_a x_a T_a,   T_a = l_a + sum_{b>=a} x_b S_ab,
-//   S_ab = q_ab + sum_{c>=b} k_abc x_c,
-// and its gradient in reverse mode over the same form: df/dx_a += T_a,
-// df/dx_b += x_a S_ab, df/dx_c += x_a x_b k_abc (repeated indices give the
-// multiplicities of squares and cubes by themselves).  Two complex
+// n, an equation is evaluated in nested (Horner) form and its gradient in
+// reverse mode over the same form (dense_eval.hpp): two complex
 // multiply-adds per cubic monomial, every index a compile-time constant, so
 // the Jacobian row is a register array and the whole Jacobian stays in
 // registers for the register LU, as in the kernels specialised at run time;
@@ -26,6 +22,7 @@
 // n.
 #pragma once
 
+#include "dense_eval.hpp"
 #include "lane_track.hpp"
 #include "reg_lu.hpp"
 
@@ -56,57 +53,11 @@ struct Dense : LaneTrack<Dense<N>, N, RkLds<N>> {
     for (int i = 0; i < N; ++i) off[i] = sp->dense_off[i];
   }
 
-  __device__ __forceinline__ static cd coef(cptr<double> c, int k) { return {c[2 * k], c[2 * k + 1]}; }
-
-  // Equation of total degree D whose table starts at c: returns its value
-  // and writes its gradient to g.
-  // Table positions (the host fills the table in the same order).
-  static constexpr int kQuad = 1 + N;                     // first x_a x_b
-  static constexpr int kCubic = kQuad + N * (N + 1) / 2;  // first x_a x_b x_c
-  __device__ static constexpr int quad_at(int va, int vb) {
-    return kQuad + va * N - va * (va - 1) / 2 + (vb - va);
-  }
-  __device__ static constexpr int cubic_at(int va, int vb, int vc) {
-    int k = kCubic;
-    for (int u = 0; u < va; ++u) k += (N - u) * (N - u + 1) / 2;
-    for (int u = va; u < vb; ++u) k += N - u;
-    return k + (vc - vb);
-  }
-
+  // Equation of total degree D whose table starts at c at the current point:
+  // returns its value and writes its gradient to g.
   template <int D>
   __device__ __forceinline__ cd equation(cptr<double> c, cd (&g)[N]) const {
-#pragma unroll
-    for (int v = 0; v < N; ++v) g[v] = {0.0, 0.0};
-    cd f = coef(c, 0);
-    sfor<0, N>([&](auto ia) {
-      constexpr int va = decltype(ia)::value;
-      // T_a, complete once its b loop is done: folded into f and df/dx_a
-      cd T = coef(c, 1 + va);
-      if constexpr (D >= 2) {
-        sfor<va, N>([&](auto ib) {
-          constexpr int vb = decltype(ib)::value;
-          cd S = coef(c, quad_at(va, vb));
-          if constexpr (D >= 3) {
-            // two partial sums shorten the dependent chain
-            const cd P = cmul(xc[va], xc[vb]);
-            cd S1 = {0.0, 0.0};
-            sfor<vb, N>([&](auto ic) {
-              constexpr int vc = decltype(ic)::value;
-              const cd k = coef(c, cubic_at(va, vb, vc));
-              if constexpr (((vc - vb) & 1) != 0) S1 = cfma(S1, k, xc[vc]);
-              else S = cfma(S, k, xc[vc]);
-              g[vc] = cfma(g[vc], P, k);
-            });
-            S = cadd(S, S1);
-          }
-          T = cfma(T, xc[vb], S);
-          g[vb] = cfma(g[vb], xc[va], S);
-        });
-      }
-      f = cfma(f, xc[va], T);
-      g[va] = cadd(g[va], T);
-    });
-    return f;
+    return dense_equation<N, D>(c, xc, g);
   }
 
   // [J_x(xc, te) | rhs]: J = t J_f + s J_g, rhs = -H_t, H or f (EvalMode).

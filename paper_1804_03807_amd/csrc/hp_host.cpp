@@ -882,8 +882,10 @@ Kv kv_pick(const Packed &P) {
 // same stream.  total_paths: the queue length of a single-system launch.
 // With eg given, the paths to refine are first compacted into its list (per
 // n for a multi-system launch), so that the end game's wavefronts are full.
+// dense: the launch ran a dense kernel, whose coefficient tables then serve
+// the end game too.
 int launch_endgame(const DevTables &dev, const Packed &P, const KArgs &a, int64_t total_paths,
-                   hipStream_t s, EgList *eg = nullptr) {
+                   hipStream_t s, EgList *eg = nullptr, bool dense = false) {
   const bool one = P.sys.size() == 1;
   const int64_t single_blocks = (total_paths + hp::kLanes - 1) / hp::kLanes;
   if (one && single_blocks > INT32_MAX) return fail(HP_E_INVALID_ARG, "too many paths for one launch");
@@ -903,7 +905,7 @@ int launch_endgame(const DevTables &dev, const Packed &P, const KArgs &a, int64_
     if (one) {
       HIP_TRY((hipError_t)hp_launch_eg_select(a, nullptr, (int)single_blocks, eg->list.as<long long>(),
                                               eg->count.as<unsigned>(), s));
-      HIP_TRY((hipError_t)hp_launch_endgame(P.sys[0].n, b, nullptr, (int)single_blocks, s));
+      HIP_TRY((hipError_t)hp_launch_endgame(P.sys[0].n, b, nullptr, (int)single_blocks, dense, s));
       return HP_OK;
     }
     HIP_TRY((hipError_t)hp_launch_eg_select(a, dev.egblk.as<int2>(), dev.eg_first[HP_MAX_N + 1],
@@ -911,18 +913,18 @@ int launch_endgame(const DevTables &dev, const Packed &P, const KArgs &a, int64_
     for (int n = 1; n <= HP_MAX_N; ++n) {
       const int b0 = dev.eg_first[n], b1 = dev.eg_first[n + 1];
       if (b1 > b0)
-        HIP_TRY((hipError_t)hp_launch_endgame(n, b, dev.egblk.as<int2>() + b0, b1 - b0, s));
+        HIP_TRY((hipError_t)hp_launch_endgame(n, b, dev.egblk.as<int2>() + b0, b1 - b0, dense, s));
     }
     return HP_OK;
   }
   if (one) {
-    HIP_TRY((hipError_t)hp_launch_endgame(P.sys[0].n, a, nullptr, (int)single_blocks, s));
+    HIP_TRY((hipError_t)hp_launch_endgame(P.sys[0].n, a, nullptr, (int)single_blocks, dense, s));
     return HP_OK;
   }
   for (int n = 1; n <= HP_MAX_N; ++n) {
     const int b0 = dev.eg_first[n], b1 = dev.eg_first[n + 1];
     if (b1 > b0)
-      HIP_TRY((hipError_t)hp_launch_endgame(n, a, dev.egblk.as<int2>() + b0, b1 - b0, s));
+      HIP_TRY((hipError_t)hp_launch_endgame(n, a, dev.egblk.as<int2>() + b0, b1 - b0, dense, s));
   }
   return HP_OK;
 }
@@ -994,7 +996,7 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
     HIP_TRY((hipError_t)hp_launch_persistent(k.nmax, P.general, a, (int)groups, lds, s));
   }
   if (em) HIP_TRY(hipEventRecord(em, s));
-  if ((rc = launch_endgame(dev, P, a, total_paths, s, eg))) return rc;
+  if ((rc = launch_endgame(dev, P, a, total_paths, s, eg, k.dense))) return rc;
   HIP_TRY(hipEventRecord(e1, s));
   if (groups_out) *groups_out = (int)groups;
   return HP_OK;

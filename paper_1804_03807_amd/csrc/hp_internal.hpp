@@ -303,8 +303,11 @@ int hp_launch_fill_i32(int32_t *p, long long m, int32_t v, void *stream);
 // End game of the paths of systems with n unknowns: blk[b] = (system, first
 // queue index) of block b (64 paths each), or blk == nullptr for one system
 // (system 0, block b from queue index 64 b); with a.eg_list set, the block
-// takes the same positions of its system's compacted list instead.
-int hp_launch_endgame(int n, const hp::KArgs &a, const int2 *blk, int blocks, void *stream);
+// takes the same positions of its system's compacted list instead.  dense:
+// the systems' dense tables (a.dcoef) evaluate f and J_f, else their
+// equation-ordered terms.
+int hp_launch_endgame(int n, const hp::KArgs &a, const int2 *blk, int blocks, bool dense,
+                      void *stream);
 // Compacts, per system, the queue indices of `blocks` blocks (blk as for
 // hp_launch_endgame) whose paths the end game refines (CONVERGED or
 // FAILED_NEWTON_T1) into list from the system's eg_list_base, their number
