@@ -707,6 +707,7 @@ void context_orphan(hp_context *ctx) {
 // Device list of the paths a single-system end game refines (a plan's).
 struct EgList {
   DevBuf list, count;
+  bool ready = false;  // sized and zeroed for the next end game (eg_prepare)
 };
 
 struct hp_plan {
@@ -884,21 +885,44 @@ Kv kv_pick(const Packed &P) {
 // n for a multi-system launch), so that the end game's wavefronts are full.
 // dense: the launch ran a dense kernel, whose coefficient tables then serve
 // the end game too.
+// Entries of the end game's lists for a launch over the systems in `dev`:
+// per system a list region from its eg_list_base (64 entries per block of
+// its queue).
+int64_t eg_entries(const DevTables &dev, const Packed &P, int64_t total_paths) {
+  if (P.sys.size() == 1) return (total_paths + hp::kLanes - 1) / hp::kLanes * hp::kLanes;
+  return (int64_t)dev.eg_first[HP_MAX_N + 1] * hp::kLanes;
+}
+
+// Sizes eg's list and zeroes its per-system counters on stream s, ahead of
+// the end game of a launch over the systems in `dev`.  launch_endgame does
+// this itself unless it has been done; the server does it for all its
+// families before any of their kernels runs, since a fill or an allocation
+// issued while another stream's persistent kernel holds every compute unit
+// waits for that kernel to end.
+int eg_prepare(EgList &eg, const DevTables &dev, const Packed &P, int64_t total_paths,
+               hipStream_t s) {
+  const int64_t entries = eg_entries(dev, P, total_paths);
+  eg.ready = false;
+  if (entries > 0) {
+    int rc;
+    if ((rc = eg.list.alloc((size_t)entries * sizeof(long long)))) return rc;
+    if ((rc = eg.count.alloc(P.sys.size() * sizeof(unsigned)))) return rc;
+    HIP_TRY(hipMemsetAsync(eg.count.p, 0, P.sys.size() * sizeof(unsigned), s));
+  }
+  eg.ready = true;
+  return HP_OK;
+}
+
 int launch_endgame(const DevTables &dev, const Packed &P, const KArgs &a, int64_t total_paths,
                    hipStream_t s, EgList *eg = nullptr, bool dense = false) {
   const bool one = P.sys.size() == 1;
   const int64_t single_blocks = (total_paths + hp::kLanes - 1) / hp::kLanes;
   if (one && single_blocks > INT32_MAX) return fail(HP_E_INVALID_ARG, "too many paths for one launch");
   if (eg) {
-    // per system a list region from its eg_list_base (64 entries per block
-    // of its queue), one counter per system
-    const int64_t entries = one ? single_blocks * hp::kLanes
-                                : (int64_t)dev.eg_first[HP_MAX_N + 1] * hp::kLanes;
-    if (entries == 0) return HP_OK;
+    if (eg_entries(dev, P, total_paths) == 0) return HP_OK;
     int rc;
-    if ((rc = eg->list.alloc((size_t)entries * sizeof(long long)))) return rc;
-    if ((rc = eg->count.alloc(P.sys.size() * sizeof(unsigned)))) return rc;
-    HIP_TRY(hipMemsetAsync(eg->count.p, 0, P.sys.size() * sizeof(unsigned), s));
+    if (!eg->ready && (rc = eg_prepare(*eg, dev, P, total_paths, s))) return rc;
+    eg->ready = false;  // the next end game zeroes the counters again
     KArgs b = a;
     b.eg_list = eg->list.as<long long>();
     b.eg_count = eg->count.as<unsigned>();
@@ -937,7 +961,7 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
                       const hp_tolerances &tol, int64_t total_paths, hp_c64 *endpoints,
                       int32_t *status, hp_path_stats *stats, hipStream_t s, int *groups_out,
                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, hipEvent_t em = nullptr,
-                      int32_t step_budget = -1, EgList *eg = nullptr) {
+                      int32_t step_budget = -1, EgList *eg = nullptr, bool qhead_zeroed = false) {
   const bool sliced = step_budget >= 0;
   if (sliced && !k.spec && !k.dense) return fail(HP_E_INVALID_ARG, "no serving form of this kernel");
   if (!e0) {  // the context's events: e0 .. em the tracking kernel, em .. e1 the end game
@@ -977,7 +1001,8 @@ int launch_persistent(hp_context *ctx, DevTables &dev, const Packed &P, const Kv
   a.step_budget = sliced ? step_budget : 0;
   a.lane_paths = lp;
   a.pcoef = k.pcoef;
-  HIP_TRY(hipMemsetAsync(dev.qhead.p, 0, P.sys.size() * sizeof(unsigned long long), s));
+  if (!qhead_zeroed)
+    HIP_TRY(hipMemsetAsync(dev.qhead.p, 0, P.sys.size() * sizeof(unsigned long long), s));
   HIP_TRY(hipEventRecord(e0, s));
   if (k.spec) {
     void *params[] = {&a};
@@ -2642,19 +2667,26 @@ int run_epoch(hp_server *S, std::vector<std::shared_ptr<Request>> &batch) {
     HIP_TRY(hipEventCreate(&ev[1]));
     S->fam_ev.push_back(ev);
   }
-  // the families run side by side (their requests' arena regions are
+  // every family's tables, queue heads and end-game lists first, while no
+  // kernel runs: a copy or fill is itself a kernel, and issued behind
+  // another family's persistent kernel it would wait for that kernel to end
+  for (size_t f = 0; f < members.size(); ++f) {
+    FamState &F = *fam[f];
+    if (!fam_kv[f].spec && !fam_kv[f].dense) kv_decode(nmax_for(F.P.nl), fam_kv[f]);  // group kernels
+    if ((rc = fam_fresh[f] ? F.dev.upload(F.P, S->stream) : F.dev.upload_sys(F.P, S->stream, true)))
+      return rc;
+    HIP_TRY(hipMemsetAsync(F.dev.qhead.p, 0, F.P.sys.size() * sizeof(unsigned long long), S->stream));
+    if ((rc = eg_prepare(F.eg, F.dev, F.P, total[f], S->stream))) return rc;
+  }
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  // then the families run side by side (their requests' arena regions are
   // disjoint), each on one of the family streams
   for (size_t f = 0; f < members.size() && rc == HP_OK; ++f) {
     const hipStream_t fs = S->fam_stream[f % kFamilyStreams];
     FamState &F = *fam[f];
-    Kv kv = fam_kv[f];
-    if (!kv.spec && !kv.dense) kv_decode(nmax_for(F.P.nl), kv);  // group kernels
-    rc = fam_fresh[f] ? F.dev.upload(F.P, fs) : F.dev.upload_sys(F.P, fs, true);
-    if (rc == HP_OK)
-      rc = launch_persistent(ctx, F.dev, F.P, kv, tol, total[f], S->a_ends.as<hp_c64>(),
-                             S->a_status.as<int32_t>(), S->a_stats.as<hp_path_stats>(), fs,
-                             nullptr, S->fam_ev[f][0], S->fam_ev[f][1], nullptr, fam_steps[f],
-                             &F.eg);
+    rc = launch_persistent(ctx, F.dev, F.P, fam_kv[f], tol, total[f], S->a_ends.as<hp_c64>(),
+                           S->a_status.as<int32_t>(), S->a_stats.as<hp_path_stats>(), fs, nullptr,
+                           S->fam_ev[f][0], S->fam_ev[f][1], nullptr, fam_steps[f], &F.eg, true);
   }
   // every launched family ends before the harvest reads the arena
   for (int q = 0; q < kFamilyStreams; ++q) HIP_TRY(hipStreamSynchronize(S->fam_stream[q]));
