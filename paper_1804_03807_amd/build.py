@@ -12,6 +12,7 @@ SO = os.path.join(HERE, "libhomotopy.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["tracker.hip", "lanes.hip", "dense.hip", "dense11.hip", "dense12.hip",
            "dense_sliced.hip", "dense_wide_sliced.hip", "endgame.hip", "endgame_dense.hip",
+           "endgame_dense_wide.hip",
            "dedup.hip", "dedup_static.hip", "ddtrack.hip", "serve.hip", "hp_host.cpp", "hp_jit.cpp"]
 # headers the run-time specialised kernels are compiled with (hiprtc)
 JIT_HEADERS = [("homotopy.h", os.path.join(ROOT, "include", "homotopy.h")),

@@ -310,8 +310,11 @@ int endgame_dispatch(int n, const KArgs &a, const int2 *blk, int blocks, hipStre
 
 }  // namespace
 
-// The dense form's instantiations (endgame_dense.hip, a translation unit of
-// their own so that both families compile side by side).
+// The dense form's instantiations, in translation units of their own so
+// that they compile side by side with the term form: n <= 10
+// (endgame_dense.hip, which hands n = 11, 12 on) and n = 11, 12
+// (endgame_dense_wide.hip).
 int launch_endgame_dense(int n, const KArgs &a, const int2 *blk, int blocks, hipStream_t s);
+int launch_endgame_dense_wide(int n, const KArgs &a, const int2 *blk, int blocks, hipStream_t s);
 
 }  // namespace hp
