@@ -14,8 +14,9 @@ Also measured (sub-keys, outside the timed region): cyclic-8 (40,320 paths)
 batched vs plain, the dense n = 5 system (32 paths) batched vs plain, 256 dense
 systems in one launch, coefficient-parameter continuation between two
 cyclic-8 systems (2,560 paths) and between two cyclic-10 systems (the
-headline's finite roots), the double-double tracker on cyclic-8, and the
-serving loop on 1,000 requests.
+headline's finite roots), the double-double tracker on cyclic-8, the cascade
+of homotopies and the membership test (each with the oracle beside it), and
+the serving loop on 1,000 requests.
 
 Prints one JSON line.
 """
@@ -235,6 +236,75 @@ def dd_run(ctx, double_ms):
             "kernel_ms": tm["kernel_ms"], "end_to_end_ms": dt * 1e3,
             "paths_per_s": s.bezout() / (tm["kernel_ms"] * 1e-3),
             "slowdown_vs_double": tm["kernel_ms"] / double_ms}
+
+
+def cascade_membership_run(ctx):
+    """The cascade of homotopies (hp_cascade, Section 3.1) on Example 3.1's
+    system embedded for its top dimension 3 (the paper's Figure 3) and on the
+    cyclic-8 workload embedded for dimension 1, and the homotopy membership
+    test (hp_membership_test, Section 4.1) of 4,096 points, half of them on
+    the three-dimensional set x1 = 1 of Example 3.1's system; each timed on
+    the device after a warm-up call, the oracle timed beside it on the same
+    inputs (its regular counts and memberships compared)."""
+    import oracle
+    import workloads as W
+    from test_oracle_membership import _three_dim_set
+    nth = min(16, os.cpu_count() or 1)
+    out = {}
+
+    def cascade(name, e, k, gammas):
+        ctx.cascade(e, k, gammas)  # warm-up
+        t0 = time.perf_counter()
+        stages, _, _ = ctx.cascade(e, k, gammas)
+        dt = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ref = oracle.cascade(e, k, gammas, n_threads=nth)
+        dto = time.perf_counter() - t0
+        paths = int(sum(st["paths"] for st in stages))
+        return {"workload": name, "paths": paths,
+                "stages": [{"dim": int(st["dim"]), "paths": int(st["paths"]),
+                            "nonzero": int(st["nonzero"]), "candidates": int(st["candidates"]),
+                            "kernel_ms": float(st["kernel_ms"])} for st in stages],
+                "end_to_end_ms": dt * 1e3, "paths_per_s": paths / dt,
+                "oracle": {"ms": dto * 1e3, "threads": nth, "paths_per_s": paths / dto,
+                           "nonzero": [int(r["nonzero"]) for r in ref],
+                           "candidates": [int(len(r["candidates"])) for r in ref]},
+                "nonzero_match": [int(st["nonzero"]) for st in stages[:-1]]
+                == [int(r["nonzero"]) for r in ref[:-1]]}
+
+    e31 = W.embed(W.multistep_system(), 3, np.random.default_rng(8))
+    out["cascade_example31"] = cascade("Example 3.1's system embedded for dimension 3, seed 8",
+                                       e31, 3, W.unit_circle(np.random.default_rng(99), 4))
+    progress("cascade example 3.1 done")
+    e8 = W.embed(W.cyclic8().systems[0], 1, np.random.default_rng(7))
+    out["cascade_cyclic8"] = cascade("cyclic8 workload embedded for dimension 1, seed 7",
+                                     e8, 1, W.unit_circle(np.random.default_rng(98), 2))
+    progress("cascade cyclic-8 done")
+
+    e3, _, witness = _three_dim_set()
+    rng = np.random.default_rng(11)
+    T = 4096
+    pts = np.zeros((T, 7), complex)
+    pts[:, :4] = W.unit_circle(rng, (T, 4)) * 1.5
+    pts[: T // 2, 0] = 1.0  # the first half on the set x1 = 1
+    ctx.membership_test(e3, 3, witness, pts[:64])  # warm-up
+    t0 = time.perf_counter()
+    _, _, mem = ctx.membership_test(e3, 3, witness, pts)
+    dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, _, mem_o = oracle.membership_test(e3, 3, witness, pts, n_threads=nth)
+    dto = time.perf_counter() - t0
+    paths = T * len(witness)
+    out["membership_three_dim_set"] = {
+        "workload": "4,096 points (half on x1 = 1) against the three-dimensional set of "
+                    "Example 3.1's system, 1 witness point",
+        "paths": paths, "members": int(mem.sum()), "end_to_end_ms": dt * 1e3,
+        "points_per_s": T / dt,
+        "oracle": {"ms": dto * 1e3, "threads": nth, "points_per_s": T / dto,
+                   "members": int(np.asarray(mem_o).sum())},
+        "membership_match": bool((np.asarray(mem_o) == mem).all())}
+    progress("membership test done")
+    return out
 
 
 def batch_run(ctx, n_systems=256):
@@ -535,6 +605,10 @@ def main():
         progress("256-system batch done")
         out["continuation_cyclic8"] = continuation_cyclic8(ctx)
         progress("continuation cyclic-8 done")
+        try:
+            out.update(cascade_membership_run(ctx))
+        except Exception as exc:  # reported in the line, the headline stands
+            out["cascade_membership_error"] = f"{type(exc).__name__}: {exc}"
         if start10 is not None:
             import workloads as W
             out["continuation_cyclic10"] = continuation_run(
