@@ -125,7 +125,10 @@ struct DdTrack {
 #pragma unroll
     for (int j = 0; j < N; ++j) xv[j] = G->x[j];
     wsync();
-    // f_r and its gradient: per term the prefix products, then suffix products
+    // f_r and its gradient: per term the prefix products, then suffix products.
+    // A factor of exponent 1 (every factor of a multilinear term) takes x_j
+    // itself for its power and its derivative factor 1, instead of products
+    // with the double-double one (exact, so the values are the same).
     cdd f = cdd_zero();
     cdd df[N];
 #pragma unroll
@@ -138,10 +141,15 @@ struct DdTrack {
       for (int j = 0; j < N; ++j) {
         const int e = (int)((w >> (4 * j)) & 15);
         pre[j] = run;
-        cdd p = {{1.0, 0.0}, {0.0, 0.0}};
-        for (int k = 0; k < e; ++k) p = cddmul(p, xv[j]);
-        pw[j] = p;
-        if (e > 0) run = cddmul(run, p);
+        if (e == 1) {
+          pw[j] = xv[j];
+          run = cddmul(run, xv[j]);
+        } else if (e > 1) {
+          cdd p = xv[j];
+          for (int k = 1; k < e; ++k) p = cddmul(p, xv[j]);
+          pw[j] = p;
+          run = cddmul(run, p);
+        }
       }
       f = cddadd(f, run);
       cdd suf = {{1.0, 0.0}, {0.0, 0.0}};
@@ -149,9 +157,12 @@ struct DdTrack {
       for (int mm = 0; mm < N; ++mm) {
         const int m = N - 1 - mm;
         const int e = (int)((w >> (4 * m)) & 15);
-        if (e > 0) {
-          cdd q = {{1.0, 0.0}, {0.0, 0.0}};
-          for (int k = 1; k < e; ++k) q = cddmul(q, xv[m]);
+        if (e == 1) {
+          df[m] = cddadd(df[m], cddmul(pre[m], suf));
+          suf = cddmul(suf, pw[m]);
+        } else if (e > 1) {
+          cdd q = xv[m];
+          for (int k = 2; k < e; ++k) q = cddmul(q, xv[m]);
           df[m] = cddadd(df[m], cddmul(cddmul(pre[m], cddscale(q, (double)e)), suf));
           suf = cddmul(suf, pw[m]);
         }
