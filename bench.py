@@ -187,6 +187,19 @@ def continuation_run(ctx, name, source, start, target):
     dt = time.perf_counter() - t0
     tm = ctx.last_timing()
     conv = int((st == 0).sum().item())
+    # the oracle beside it on a stride sample of at most 4,000 of the paths
+    import oracle
+    import workloads as W
+    nth = min(16, os.cpu_count() or 1)
+    idx = W.stride_sample(P, 4000)
+    t0 = time.perf_counter()
+    eo, so, _ = oracle.track_paths(target, gam, start=np.asarray(start)[idx], g=source, n_threads=nth)
+    dto = time.perf_counter() - t0
+    sg_dev = st.cpu().numpy()[idx]
+    eg_dev = hp.Plan.endpoints_to_numpy(e)[idx]
+    both = (sg_dev == 0) & (so == 0)
+    apart = int((np.abs(eg_dev[both] - eo[both]).max(axis=1)
+                 > 1e-8 * np.maximum(1.0, np.abs(eo[both]).max(axis=1))).sum())
     ctx.track_paths(target, gam, start=start, g=source)  # warm-up
     t0 = time.perf_counter()
     _, sg, _ = ctx.track_paths(target, gam, start=start, g=source)
@@ -200,7 +213,11 @@ def continuation_run(ctx, name, source, start, target):
             "group": {"kernel_variant": tg["variant"], "kernel_ms": tg["kernel_ms"],
                       "endgame_ms": tg["endgame_ms"], "end_to_end_ms": dtg * 1e3,
                       "paths_per_s": P / dtg, "converged": int((sg == 0).sum())},
-            "specialised_over_group_kernel": tg["kernel_ms"] / tm["kernel_ms"]}
+            "specialised_over_group_kernel": tg["kernel_ms"] / tm["kernel_ms"],
+            "oracle": {"paths_per_s": len(idx) / dto, "threads": nth,
+                       "sample": f"every {max(1, P // 4000)}-th path ({len(idx)} of {P})",
+                       "converged_flag_differences": int(((sg_dev == 0) != (so == 0)).sum()),
+                       "endpoints_apart": apart}}
 
 
 def continuation_cyclic8(ctx):
@@ -232,10 +249,20 @@ def dd_run(ctx, double_ms):
     hi, lo, st, _ = ctx.track_paths_dd(s, g, stats=False)
     dt = time.perf_counter() - t0
     tm = ctx.last_timing()
+    # the oracle's double-double tracker beside it on a stride sample
+    import oracle
+    nth = min(16, os.cpu_count() or 1)
+    idx = W.stride_sample(s.bezout(), 1000)
+    t0 = time.perf_counter()
+    _, _, so, _ = oracle.track_paths_dd(s, g, path_ids=idx, n_threads=nth)
+    dto = time.perf_counter() - t0
     return {"workload": WORKLOADS["cyclic8"], "paths": s.bezout(), "converged": int((st == 0).sum()),
             "kernel_ms": tm["kernel_ms"], "end_to_end_ms": dt * 1e3,
             "paths_per_s": s.bezout() / (tm["kernel_ms"] * 1e-3),
-            "slowdown_vs_double": tm["kernel_ms"] / double_ms}
+            "slowdown_vs_double": tm["kernel_ms"] / double_ms,
+            "oracle": {"paths_per_s": len(idx) / dto, "threads": nth,
+                       "sample": f"stride sample of {len(idx)} of {s.bezout()} path ids",
+                       "converged_flag_differences": int(((st[idx] == 0) != (so == 0)).sum())}}
 
 
 def cascade_membership_run(ctx):
