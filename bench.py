@@ -352,6 +352,18 @@ def batch_run(ctx, n_systems=256):
     conv = sum(int((st == 0).sum()) for _, st, _ in res)
     flop = sum(flops.run_flops(sy, sts) for sy, (_, _, sts) in zip(wl.systems, res))
     tfs = flop / (tm["kernel_ms"] * 1e-3) / 1e12
+    # the oracle beside it: every 16th system, a stride sample of its paths
+    import oracle
+    nth = min(16, os.cpu_count() or 1)
+    n_o, flag_diff, t_o = 0, 0, 0.0
+    for k in range(0, n_systems, 16):
+        sy = wl.systems[k]
+        ids = W.stride_sample(sy.bezout(), 128)
+        t0 = time.perf_counter()
+        _, so, _ = oracle.track_paths(sy, gam[k], path_ids=ids, n_threads=nth)
+        t_o += time.perf_counter() - t0
+        n_o += len(ids)
+        flag_diff += int(((res[k][1][ids] == 0) != (so == 0)).sum())
     return {"systems": n_systems, "paths": wl.total_paths, "converged": conv,
             "kernel_ms": tm["kernel_ms"], "endgame_ms": tm["endgame_ms"],
             "paths_per_s": wl.total_paths / ((tm["kernel_ms"] + tm["endgame_ms"]) * 1e-3),
@@ -360,7 +372,11 @@ def batch_run(ctx, n_systems=256):
                        "waves_per_simd": tm["waves_per_simd"]},
             "tuning": {**choice, "untuned_variant": t_untuned["variant"],
                        "untuned_kernel_ms": t_untuned["kernel_ms"]},
-            "achieved_tflops": tfs, "frac_of_fp64_peak": tfs / FP64_PEAK_TFLOPS}
+            "achieved_tflops": tfs, "frac_of_fp64_peak": tfs / FP64_PEAK_TFLOPS,
+            "oracle": {"paths_per_s": n_o / t_o, "threads": nth,
+                       "sample": f"every 16th system, a stride sample of about 128 of its paths "
+                                 f"({n_o} paths)",
+                       "converged_flag_differences": flag_diff}}
 
 
 def serving_run(ctx, n_requests, budget_bytes, calib=200, load=0.8):
