@@ -423,6 +423,7 @@ def serving_run(ctx, n_requests, budget_bytes, calib=200, load=0.8):
         th.start()
         th.join()
         lat, conv = [], 0
+        kept = [None] * min(8, len(sub))  # statuses of the first requests
         t_last = time.perf_counter()
         for i, q in enumerate(ids):
             while not srv.poll(q):  # poll, so that progress lines keep coming
@@ -433,6 +434,8 @@ def serving_run(ctx, n_requests, budget_bytes, calib=200, load=0.8):
             _, st, _, ms = srv.wait(q)
             lat.append(ms)
             conv += int((st == 0).sum())
+            if i < len(kept):
+                kept[i] = st
             if time.perf_counter() - t_last > 10.0:
                 t_last = time.perf_counter()
                 progress(f"serving: {i + 1}/{len(ids)} requests done")
@@ -440,15 +443,26 @@ def serving_run(ctx, n_requests, budget_bytes, calib=200, load=0.8):
         peak = srv.peak_bytes()
         info = srv.info()
         srv.close()
-        return np.asarray(lat), makespan, peak, conv, info
+        return np.asarray(lat), makespan, peak, conv, info, kept
 
     sat = reqs[:calib]
-    lat_sat, span_sat, _, _, _ = run(sat, np.zeros(len(sat)))
+    lat_sat, span_sat, _, _, _, _ = run(sat, np.zeros(len(sat)))
     rate_sat = len(sat) / span_sat
     lam = load * rate_sat
     main = reqs[:n_requests]
     paths = sum(s.bezout() for s, _ in main)
-    lat, span, peak, conv, info = run(main, W.poisson_arrivals(len(main), lam))
+    lat, span, peak, conv, info, kept = run(main, W.poisson_arrivals(len(main), lam))
+    # the oracle beside it: a stride sample of the paths of the first requests
+    import oracle
+    nth = min(16, os.cpu_count() or 1)
+    n_o, flag_diff, t_o = 0, 0, 0.0
+    for (s_k, g_k), st_k in zip(main, kept):
+        ids = W.stride_sample(s_k.bezout(), 64)
+        t0 = time.perf_counter()
+        _, so, _ = oracle.track_paths(s_k, g_k, path_ids=ids, n_threads=nth)
+        t_o += time.perf_counter() - t0
+        n_o += len(ids)
+        flag_diff += int(((st_k[ids] == 0) != (so == 0)).sum())
     return {"requests": len(main), "paths": paths, "converged": conv,
             "spec_compile_ms": compile_ms,
             "sample": f"request ids 0..{len(main) - 1} of the seeded stream (seed 4); "
@@ -463,7 +477,11 @@ def serving_run(ctx, n_requests, budget_bytes, calib=200, load=0.8):
             "slicing": {"slice_ms": info["slice_ms"], "epochs": info["epochs"],
                         "epoch_ms_mean": info["epoch_ms_mean"], "epoch_ms_max": info["epoch_ms_max"],
                         "carried_entries": info["carried"],
-                        "step_budget_range": [info["budget_min"], info["budget_max"]]}}
+                        "step_budget_range": [info["budget_min"], info["budget_max"]]},
+            "oracle": {"paths_per_s": n_o / t_o if t_o > 0 else None, "threads": nth,
+                       "sample": f"the first {len(kept)} requests, a stride sample of about 64 "
+                                 f"paths each ({n_o} paths)",
+                       "converged_flag_differences": flag_diff}}
 
 
 def cpu_baseline(system, gamma, target_paths=20000):
